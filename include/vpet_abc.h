@@ -1,0 +1,195 @@
+/*
+ * vpet_abc.h -- C ABI of the MI355X (gfx950) library for voxelwise ABC
+ * rejection in dynamic PET kinetic modelling (vPET-ABC, arXiv 2603.14859).
+ *
+ * Per voxel the library draws kinetic parameters from a uniform prior box
+ * (Alg. 1, lines 1-2), forward-simulates the frame-averaged time-activity curve
+ * of a compartment model (Eq. (1)-(2); Alg. 1, line 3), scores every draw with
+ * a noise-weighted distance to the observed curve (Alg. 1, line 4), keeps the
+ * n = floor(N p) closest draws (Alg. 1, line 5 and the remark after it; the
+ * fixed-budget variant of Sec. II-C) and reduces them to per-model posterior
+ * means and variances and model probabilities (Eq. (6); Sec. II-D3; Ki per
+ * accepted sample as in Sec. III-B2).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns a vpet_status and never throws or aborts.  On a
+ *    status other than VPET_OK, vpet_abc_last_error() returns a message for the
+ *    calling thread; nothing has been enqueued for VPET_E_ARG, VPET_E_MODEL,
+ *    VPET_E_GRID and VPET_E_LIMIT.
+ *  - "device" pointers are HIP device memory on the current device (the
+ *    caller's hipSetDevice); "host" pointers are ordinary host memory that the
+ *    library reads before the call returns.  The caller owns every buffer; the
+ *    library writes only the out_* buffers it is given.
+ *  - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the null stream)
+ *    and the call returns without waiting.  Outputs are valid once the stream
+ *    has reached that point.  Calls on different streams may overlap.
+ *  - Time is in minutes, activity in any consistent unit (kBq/mL in the tests).
+ *  - Time grid: nodes t_k = k * dt, k = 0..n_nodes-1.  The input function is
+ *    given at the nodes and taken as linear between them.  Frame bounds
+ *    frame_times[0..n_frames] must increase strictly and lie on nodes (to a
+ *    relative 1e-6).
+ *  - Parameter slots (stride VPET_PSTRIDE): 0 K1, 1 k2, 2 k3, 3 k4, 4 vB,
+ *    5 Ki (derived, outputs only), 6-7 unused.  A model uses K1,k2,vB (1TCM),
+ *    K1,k2,k3,vB (irreversible 2TCM, k4 = 0) or K1,k2,k3,k4,vB (reversible).
+ *  - Draws are stratified by model: every model in model_id gets exactly
+ *    n_draws draws per voxel; the global draw index of draw i of the model at
+ *    list position m is g = m * n_draws + i.  Models are listed in bit order.
+ *  - Draw (v, i) of list position m uses Philox4x32-10 (Salmon et al., SC'11)
+ *    with key (seed low 32 bits, seed high 32 bits) and counter
+ *    (i, v, 0, m << 16 | blk); parameter j of the model takes word j % 4 of
+ *    block blk = j / 4 and becomes
+ *        theta = fmaf((float)(hi - lo), (float)(word >> 8) * 2^-24, (float)lo).
+ *    v is the global voxel index (voxel_offset + row).
+ */
+#ifndef VPET_ABC_H
+#define VPET_ABC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VPET_OK = 0,
+    VPET_E_ARG = 1,    /* invalid argument (sizes, pointers, prior box, p)      */
+    VPET_E_MODEL = 2,  /* unknown or empty model bitmask                         */
+    VPET_E_GRID = 3,   /* frame bound off the grid, outside it, or not increasing */
+    VPET_E_HIP = 4,    /* HIP runtime or launch failure                          */
+    VPET_E_NOMEM = 5,  /* device or pinned-host allocation failed                */
+    VPET_E_LIMIT = 6   /* valid request beyond a documented capacity             */
+} vpet_status;
+
+#define VPET_M_1TCM (1u << 0)     /* one-tissue model: K1 exp(-k2 t)                 */
+#define VPET_M_2TCM_IRR (1u << 1) /* two-tissue, irreversible (k4 = 0), Eq. (1)-(2)   */
+#define VPET_M_2TCM_REV (1u << 2) /* two-tissue, reversible, Eq. (1)-(2)              */
+
+#define VPET_PSTRIDE 8
+#define VPET_SLOT_K1 0
+#define VPET_SLOT_K2 1
+#define VPET_SLOT_K3 2
+#define VPET_SLOT_K4 3
+#define VPET_SLOT_VB 4
+#define VPET_SLOT_KI 5
+
+/* Capacities.  VPET_MAX_ACCEPT bounds n = floor(N p) (the accepted set of a
+ * voxel is kept on chip); larger n returns VPET_E_LIMIT. */
+#define VPET_MAX_ACCEPT 3968
+#define VPET_MAX_NODES 16385
+#define VPET_MAX_FRAMES 1024
+
+typedef struct {
+    float dt;         /* grid step (min), > 0                         */
+    int32_t n_nodes;  /* K + 1 >= 2: input samples at t_k = k * dt     */
+    int32_t n_frames; /* F >= 1                                        */
+} vpet_grid;
+
+/* Optional settings of vpet_abc_infer.  Zero-initialised = defaults. */
+typedef struct {
+    /* Decay constant (1/min) in the default weights; 0 -> ln 2 / 109.8 (18F). */
+    double decay_lambda;
+    /* device [V][F] caller weights w_vf > 0 (inverse-variance sense); NULL ->
+     * w_vf = dt_f exp(-lambda tmid_f) / max(y_vf, floor * max_f y_vf), the
+     * inverse of the Sec. III-A1 noise variance with the unknown true curve
+     * replaced by the observation. */
+    const float* weights;
+    /* floor in the default weights as a fraction of max_f y_vf; 0 -> 0.01. */
+    float weight_floor_frac;
+    /* 0: d = sum_f w_f (y_f - x_f)^2 (default); 1: d = sum_f sqrt(w_f) |y_f - x_f|
+     * (the L1 distance recommended in Sec. IV). */
+    int32_t distance;
+    /* Debug / parity outputs (device, may be NULL): accepted global draw
+     * indices [V][n] and their fp32 distances [V][n] in ascending (d, g) order,
+     * and the n-th smallest distance [V]. */
+    int32_t* out_accept_idx;
+    float* out_accept_dist;
+    float* out_threshold;
+    /* Global index of tacs row 0 (voxel chunking); row r is voxel
+     * voxel_offset + r in the Philox counter. */
+    int64_t voxel_offset;
+    /* Waves cooperating on one voxel (1, 2 or 4); 0 = chosen from V. */
+    int32_t waves_per_voxel;
+} vpet_abc_opts;
+
+/*
+ * n = floor(n_total * accept_frac + 1e-6) (remark after Alg. 1; the 1e-6
+ * absorbs products that land just below an integer).  Host-only.
+ * Errors: VPET_E_ARG if n_total < 1, accept_frac outside (0, 1], n < 1 or
+ * out_n is NULL.
+ */
+int vpet_abc_accept_count(int64_t n_total, double accept_frac, int64_t* out_n);
+
+/*
+ * Frame-averaged model curves for n parameter rows (Eq. (1)-(2), C_wb = C_p;
+ * Alg. 1, line 3).  Each row is run in FP64 from its fp32 values; the frame
+ * value is the trapezoid rule over the frame's nodes of the exact response to
+ * the piecewise-linear input, divided by the frame length.
+ *   model_id    exactly one VPET_M_* bit
+ *   theta       device [n][VPET_PSTRIDE] fp32, slots as above (others ignored)
+ *   input_fn    host [grid.n_nodes] fp32
+ *   frame_times host [grid.n_frames + 1] fp32
+ *   out_tacs    device [n][grid.n_frames] fp32
+ * Errors: VPET_E_MODEL (not exactly one known bit), VPET_E_GRID, VPET_E_ARG
+ * (n < 0, NULL pointers with n > 0, non-finite input), VPET_E_HIP.
+ * n = 0 returns VPET_OK without enqueueing anything.
+ */
+int vpet_abc_simulate(uint32_t model_id, const float* theta, int64_t n, const float* input_fn,
+                      const float* frame_times, vpet_grid grid, float* out_tacs, void* hip_stream);
+
+/*
+ * Voxelwise fixed-budget rejection ABC (Alg. 1).
+ *   tacs          device [n_voxels][F] fp32 observed TACs
+ *   frame_times   host [F + 1] fp32;  input_fn host [grid.n_nodes] fp32
+ *   model_id      bitmask of VPET_M_*; M = popcount, listed in bit order
+ *   prior_box     host [M][VPET_PSTRIDE][2] FP64 (lo, hi) per slot; lo == hi
+ *                 fixes a parameter.  Rate constants need lo >= 0, vB needs
+ *                 0 <= lo and hi < 1; 2TCM models need k2_lo + k3_lo > 0 and the
+ *                 reversible model k3_lo > 0 (distinct eigenvalues).
+ *   n_draws       prior draws per model per voxel, M * n_draws < 2^32
+ *   accept_frac   p in (0, 1]; n = floor(M n_draws p + 1e-6) in [1, VPET_MAX_ACCEPT]
+ *   seed          Philox key
+ *   out_moments   device [n_voxels][M][VPET_PSTRIDE][2] fp32: mean and
+ *                 1/(cnt-1) variance of each slot over the accepted draws of
+ *                 that model (cnt = 1 -> variance 0; cnt = 0 -> NaN); slot 5
+ *                 is Ki = K1 k3 / (k2 + k3) for the 2TCM models; unused
+ *                 slots are NaN.  Accumulated in FP64.
+ *   out_model_prob device [n_voxels][M] fp32: cnt_m / n (Eq. (6)).
+ *   opts          optional (NULL = defaults)
+ * A voxel whose observed TAC has a non-finite value or max_f y <= 0 gets NaN
+ * moments and probabilities (debug outputs: index -1, distance NaN).
+ * The accepted set is the n smallest keys (fp32(d), g): ties in fp32 distance
+ * go to the lower global draw index.
+ * Errors: VPET_E_ARG, VPET_E_MODEL, VPET_E_GRID, VPET_E_LIMIT (see above),
+ * VPET_E_NOMEM, VPET_E_HIP.  n_voxels = 0 returns VPET_OK with no launch.
+ */
+int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times,
+                   const float* input_fn, vpet_grid grid, uint32_t model_id,
+                   const double* prior_box, int64_t n_draws, double accept_frac, uint64_t seed,
+                   float* out_moments, float* out_model_prob, const vpet_abc_opts* opts,
+                   void* hip_stream);
+
+/*
+ * The prior draws themselves (Alg. 1, lines 1-2), for checking and for
+ * re-deriving accepted samples.  For each of `count` triples (voxel[j],
+ * draw[j], model_pos[j]) (device int64, int64, int32; voxel is the global
+ * voxel index, model_pos the list position in model_id) writes the Philox
+ * words of the draw (device [count][8] u32, block-major, unused words 0) and
+ * theta (device [count][VPET_PSTRIDE] fp32, unused slots NaN).
+ * Errors: VPET_E_MODEL, VPET_E_ARG (prior box as for infer, NULL pointers with
+ * count > 0), VPET_E_HIP.  Out-of-range model_pos entries yield NaN theta.
+ */
+int vpet_abc_draws(uint32_t model_id, const double* prior_box, uint64_t seed,
+                   const int64_t* voxel, const int64_t* draw, const int32_t* model_pos,
+                   int64_t count, uint32_t* out_words, float* out_theta, void* hip_stream);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char* vpet_abc_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int vpet_abc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VPET_ABC_H */

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) library for voxelwise ABC rejection in dynamic PET (vPET-ABC).
+
+The work is done by hand-written HIP kernels in ``libvpetabc.so`` behind the C
+ABI of ``include/vpet_abc.h``; this package is the thin ctypes binding with the
+same entry points (``simulate``, ``infer``, ``draws``, ``accept_count``).
+"""
+from ._binding import (E_ARG, E_GRID, E_HIP, E_LIMIT, E_MODEL, E_NOMEM, EXPORTED, LIB_PATH, M_1TCM,  # noqa: F401
+                       M_2TCM_IRR, M_2TCM_REV, MAX_ACCEPT, OK, PSTRIDE, VpetError, accept_count, draws, infer,
+                       lib, model_mask, simulate, version)

@@ -1,0 +1,198 @@
+"""ctypes binding of libvpetabc.so (include/vpet_abc.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  Device buffers are torch tensors on the current HIP device; the
+work is enqueued on torch's current stream (or the one given).  There is no CPU
+fallback: if the shared library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvpetabc.so")
+
+OK, E_ARG, E_MODEL, E_GRID, E_HIP, E_NOMEM, E_LIMIT = range(7)
+M_1TCM, M_2TCM_IRR, M_2TCM_REV = 1, 2, 4
+PSTRIDE = 8
+MAX_ACCEPT = 3968
+
+EXPORTED = ("vpet_abc_accept_count", "vpet_abc_simulate", "vpet_abc_infer", "vpet_abc_draws",
+            "vpet_abc_last_error", "vpet_abc_version")
+
+
+class VpetError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"vpet_abc status {status}: {message}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_float), ("n_nodes", ctypes.c_int32), ("n_frames", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("decay_lambda", ctypes.c_double), ("weights", ctypes.c_void_p),
+                ("weight_floor_frac", ctypes.c_float), ("distance", ctypes.c_int32),
+                ("out_accept_idx", ctypes.c_void_p), ("out_accept_dist", ctypes.c_void_p),
+                ("out_threshold", ctypes.c_void_p), ("voxel_offset", ctypes.c_int64),
+                ("waves_per_voxel", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i64, u32, u64, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+    L.vpet_abc_accept_count.argtypes = [i64, f64, ctypes.POINTER(ctypes.c_int64)]
+    L.vpet_abc_simulate.argtypes = [u32, P, i64, P, P, Grid, P, P]
+    L.vpet_abc_infer.argtypes = [P, i64, P, P, Grid, u32, P, i64, f64, u64, P, P, ctypes.POINTER(Opts), P]
+    L.vpet_abc_draws.argtypes = [u32, P, u64, P, P, P, i64, P, P, P]
+    L.vpet_abc_last_error.restype = ctypes.c_char_p
+    L.vpet_abc_version.restype = ctypes.c_int
+    for name in EXPORTED[:4]:
+        getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != OK:
+        raise VpetError(status, lib.vpet_abc_last_error().decode())
+
+
+def model_mask(models) -> int:
+    mask = 0
+    for m in models:
+        if m not in (M_1TCM, M_2TCM_IRR, M_2TCM_REV):
+            raise ValueError(f"unknown model {m}")
+        mask |= int(m)
+    if [m for m in (M_1TCM, M_2TCM_IRR, M_2TCM_REV) if mask & m] != list(models):
+        raise ValueError("models must be distinct and listed in bit order (1TCM, IRR, REV)")
+    return mask
+
+
+def accept_count(n_total: int, accept_frac: float) -> int:
+    out = ctypes.c_int64()
+    _check(lib.vpet_abc_accept_count(int(n_total), float(accept_frac), ctypes.byref(out)))
+    return int(out.value)
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 tensor on the GPU")
+    return t
+
+
+def simulate(model: int, theta, input_fn, frame_times, dt: float, out=None, stream=None):
+    """Frame-averaged model TACs [n][F] (fp32) of parameter rows theta [n][8] (fp32, device)."""
+    import torch
+    theta = _dev_f32(theta, "theta")
+    cp = _host(input_fn, np.float32)
+    ft = _host(frame_times, np.float32)
+    F = ft.size - 1
+    n = theta.shape[0]
+    if theta.dim() != 2 or theta.shape[1] != PSTRIDE:
+        raise ValueError("theta must be [n][8]")
+    if out is None:
+        out = torch.empty((n, F), dtype=torch.float32, device=theta.device)
+    grid = Grid(float(dt), cp.size, F)
+    _check(lib.vpet_abc_simulate(int(model), _ptr(theta), n, cp.ctypes.data_as(ctypes.c_void_p),
+                                 ft.ctypes.data_as(ctypes.c_void_p), grid, _ptr(out), _stream(stream)))
+    return out
+
+
+def infer(tacs, frame_times, input_fn, dt: float, models, prior_box, n_draws: int, accept_frac: float,
+          seed: int, *, weights=None, weight_floor=0.0, decay_lambda=0.0, distance="l2", debug=False,
+          voxel_offset=0, waves_per_voxel=0, out=None, stream=None) -> dict:
+    """Voxelwise rejection ABC on observed TACs [V][F] (fp32, device).
+
+    Returns a dict of device tensors: moments [V][M][8][2], model_prob [V][M]
+    and, with debug=True, accept_idx [V][n], accept_dist [V][n], threshold [V].
+    """
+    import torch
+    tacs = _dev_f32(tacs, "tacs")
+    V, F = tacs.shape
+    mask = model_mask(models)
+    M = len(models)
+    box = _host(prior_box, np.float64).reshape(M, PSTRIDE, 2)
+    cp = _host(input_fn, np.float32)
+    ft = _host(frame_times, np.float32)
+    if ft.size != F + 1:
+        raise ValueError("frame_times must have F + 1 entries")
+    n = accept_count(M * int(n_draws), accept_frac)
+    dev = tacs.device
+    res = out if out is not None else {
+        "moments": torch.empty((V, M, PSTRIDE, 2), dtype=torch.float32, device=dev),
+        "model_prob": torch.empty((V, M), dtype=torch.float32, device=dev)}
+    if debug and "accept_idx" not in res:
+        res["accept_idx"] = torch.empty((V, n), dtype=torch.int32, device=dev)
+        res["accept_dist"] = torch.empty((V, n), dtype=torch.float32, device=dev)
+        res["threshold"] = torch.empty((V,), dtype=torch.float32, device=dev)
+    o = Opts()
+    o.decay_lambda = float(decay_lambda)
+    if weights is not None:
+        weights = _dev_f32(weights, "weights")
+        if tuple(weights.shape) != (V, F):
+            raise ValueError("weights must be [V][F]")
+        o.weights = weights.data_ptr()
+    o.weight_floor_frac = float(weight_floor)
+    o.distance = {"l2": 0, "l1": 1}[distance]
+    if debug:
+        o.out_accept_idx = res["accept_idx"].data_ptr()
+        o.out_accept_dist = res["accept_dist"].data_ptr()
+        o.out_threshold = res["threshold"].data_ptr()
+    o.voxel_offset = int(voxel_offset)
+    o.waves_per_voxel = int(waves_per_voxel)
+    grid = Grid(float(dt), cp.size, F)
+    _check(lib.vpet_abc_infer(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p), cp.ctypes.data_as(ctypes.c_void_p),
+                              grid, mask, box.ctypes.data_as(ctypes.c_void_p), int(n_draws), float(accept_frac),
+                              int(seed) & ((1 << 64) - 1), _ptr(res["moments"]), _ptr(res["model_prob"]),
+                              ctypes.byref(o), _stream(stream)))
+    res["n"] = n
+    return res
+
+
+def draws(models, prior_box, seed: int, voxel, draw, model_pos, stream=None):
+    """Philox words [count][8] (int32 view of u32) and theta [count][8] for (voxel, draw, model_pos) triples."""
+    import torch
+    mask = model_mask(models)
+    box = _host(prior_box, np.float64).reshape(len(models), PSTRIDE, 2)
+    count = voxel.shape[0]
+    for t, dt_, nm in ((voxel, torch.int64, "voxel"), (draw, torch.int64, "draw"), (model_pos, torch.int32, "model_pos")):
+        if not (t.is_cuda and t.dtype == dt_ and t.is_contiguous() and t.shape[0] == count):
+            raise TypeError(f"{nm} must be a contiguous {dt_} GPU tensor of length {count}")
+    words = torch.empty((count, 8), dtype=torch.int32, device=voxel.device)
+    theta = torch.empty((count, PSTRIDE), dtype=torch.float32, device=voxel.device)
+    _check(lib.vpet_abc_draws(mask, box.ctypes.data_as(ctypes.c_void_p), int(seed) & ((1 << 64) - 1),
+                              _ptr(voxel), _ptr(draw), _ptr(model_pos), count, _ptr(words), _ptr(theta),
+                              _stream(stream)))
+    return words, theta
+
+
+def version() -> int:
+    return int(lib.vpet_abc_version())
+
+
+DEFAULT_LAMBDA = math.log(2.0) / 109.8

@@ -1,0 +1,1118 @@
+// vpet_abc.hip -- gfx950 (CDNA4) kernels and C ABI for voxelwise ABC rejection
+// (vPET-ABC, arXiv 2603.14859).  The ABI is declared in include/vpet_abc.h.
+//
+// Design (one voxel per wavefront group, draws streamed through registers):
+//  * Prior draws: Philox4x32-10 (Salmon et al., SC'11) per (voxel, draw), in
+//    VGPRs; nothing about a draw is ever stored in memory (Alg. 1, lines 1-2).
+//  * Forward model (Eq. (1)-(2), Alg. 1 line 3): each compartment-model
+//    response is a sum of at most two decaying exponentials plus, for the
+//    irreversible 2TCM, a rate-0 term.  For the piecewise-linear input, one
+//    grid step of exp(-beta t) convolved with the input is exactly
+//        I_{k+1} = z I_k + a C_k + b C_{k+1},  z = exp(-beta h).
+//    With I_k = g H_k + b C_k and g = z b + a this becomes ONE fused
+//    multiply-add per step,  H_{k+1} = z H_k + C_k,  whose C_k is the same for
+//    every lane and is read through the scalar cache.  The recursion runs in
+//    FP64: gfx950 issues v_fma_f64 at the rate of non-packed v_fma_f32, so the
+//    accuracy costs nothing in throughput.
+//  * Frame averages: the trapezoid sum of H over a frame follows from the
+//    recursion itself, sum_{k=a}^{b-1} H_k = (H_a - H_b + sum C_k) / (1 - z),
+//    so no per-step accumulation is needed; when 1 - z is tiny for some lane of
+//    a wavefront (a nearly-zero rate) that wavefront accumulates per step
+//    instead (a wave-uniform choice).
+//  * Distance (Alg. 1 line 4): weighted L2 (or L1) against the observed TAC,
+//    whose scaled values and weights sit in LDS and are read once per frame.
+//  * Selection (Alg. 1 line 5): each wavefront keeps its voxel's running n
+//    smallest 64-bit keys (fp32 distance bits << 32 | global draw index) in
+//    LDS; a draw is appended only if it beats the running n-th key, and the
+//    buffer is merged by a wavefront bitonic sort when full.
+//  * Survivors (Eq. (6), Sec. II-D3, Sec. III-B2): the accepted draws are
+//    regenerated from Philox and reduced in FP64 to per-model counts, means
+//    and variances (two passes) and Ki = K1 k3 / (k2 + k3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "vpet_abc.h"
+
+#define VPET_VERSION_NUMBER 10000
+
+namespace {
+
+// Scalar-cache pointers: uniform loads through these become s_load.
+typedef const __attribute__((address_space(4))) double* cdp;
+typedef const __attribute__((address_space(4))) int* cip;
+
+constexpr int kWave = 64;
+constexpr int kU = 2;                 // draws per lane per tile (ILP)
+constexpr int kTile = kWave * kU;     // draws per wavefront tile
+constexpr double kCmin = 1e-5;        // 1 - z below which frame sums are accumulated
+constexpr int kMaxModels = 3;
+constexpr int kMaxWpv = 4;
+constexpr uint64_t kNoKey = ~0ull;
+constexpr int kLdsLimit = 65536;
+
+enum ModelKind { KIND_1TCM = 1, KIND_IRR = 2, KIND_REV = 4 };
+
+struct ModelDev {
+    int kind;
+    int np;
+    int slot[5];
+    float lo[5];
+    float wid[5];
+};
+
+struct Tab {
+    const double* C;   // C_k, k = 0 .. kend-1 (input at the start of each step)
+    const double* fr;  // per frame: SS (trapezoid sum of the running integral Q),
+                       // PP (trapezoid sum of C), R (sum of C over the frame's steps), omega
+    const int* nf;     // steps per frame
+};
+
+struct InferArgs {
+    const float* tacs;
+    const float* weights;
+    Tab tab;
+    double C0, h, floor_frac;
+    int F, k0, M, cap, wpv, l1;
+    long long V;
+    unsigned long long vbase;
+    unsigned n_draws, n_acc, key0, key1;
+    ModelDev md[kMaxModels];
+    float* out_mom;
+    float* out_prob;
+    int* out_idx;
+    float* out_dist;
+    float* out_thr;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+__device__ __forceinline__ float unit24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+
+// Parameters of draw i of list position m for voxel v, in the model's order.
+__device__ __forceinline__ void draw_params(const ModelDev& md, uint32_t key0, uint32_t key1,
+                                            uint32_t v, uint32_t i, uint32_t m, float th[5],
+                                            uint32_t* words = nullptr) {
+    uint32_t w[8];
+    philox10(i, v, 0u, m << 16, key0, key1, w);
+    if (md.np > 4) {
+        philox10(i, v, 0u, (m << 16) | 1u, key0, key1, w + 4);
+    } else {
+        w[4] = w[5] = w[6] = w[7] = 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) th[j] = (j < md.np) ? __builtin_fmaf(md.wid[j], unit24(w[j]), md.lo[j]) : 0.0f;
+    if (words) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) words[j] = (j < 4 * ((md.np + 3) / 4)) ? w[j] : 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-draw coefficients.
+// ---------------------------------------------------------------------------
+struct Exp1 {
+    double z, H0, c, rc, eT;  // eT = (1 - vB) A g (coefficient of the trapezoid sum of H)
+};
+
+// One decaying exponential exp(-beta t), amplitude A (already times 1 - vB).
+// Returns the b coefficient (times A) through *bA for the PP term.
+__device__ __forceinline__ Exp1 exp_setup(double beta, double amp, double h, double C0, double* bA) {
+    const double x = beta * h;
+    const double c = -expm1(-x);
+    const double rx = 1.0 / x;
+    const double rc = 1.0 / c;
+    // b/h: (x - c)/x^2, or its Taylor series for x < 0.01 (cancellation)
+    const double bs = 0.5 + x * (-1.0 / 6.0 + x * (1.0 / 24.0 + x * (-1.0 / 120.0 + x * (1.0 / 720.0))));
+    const double bd = (x - c) * rx * rx;
+    const double bh = (x < 0.01) ? bs : bd;
+    const double cx = (x > 0.0) ? c * rx : 1.0;  // c / x
+    const double xc = (x > 0.0) ? x * rc : 1.0;  // x / c
+    Exp1 e;
+    e.z = 1.0 - c;
+    e.c = c;
+    e.rc = rc;
+    e.H0 = -bh * xc * xc * C0;  // H_0 = -(b / g) C_0, g = h (c/x)^2
+    e.eT = amp * h * cx * cx;
+    *bA = amp * h * bh;
+    return e;
+}
+
+template <int KIND>
+struct ModelTraits;
+template <>
+struct ModelTraits<KIND_1TCM> {
+    static constexpr int NE = 1;
+    static constexpr bool Q = false;
+};
+template <>
+struct ModelTraits<KIND_IRR> {
+    static constexpr int NE = 1;
+    static constexpr bool Q = true;
+};
+template <>
+struct ModelTraits<KIND_REV> {
+    static constexpr int NE = 2;
+    static constexpr bool Q = false;
+};
+
+template <int NE, int U>
+struct DrawState {
+    double z[NE][U], H[NE][U], c[NE][U], rc[NE][U], eT[NE][U];
+    double e0[U], eP[U];
+};
+
+// th: parameters in model order.  Fills the per-draw state for column u.
+template <int KIND, int NE, int U>
+__device__ __forceinline__ void setup(const float th[5], double h, double C0, DrawState<NE, U>& s,
+                                      int u) {
+    const double K1 = th[0], k2 = th[1];
+    if constexpr (KIND == KIND_1TCM) {
+        const double vB = th[2];
+        const double w = 1.0 - vB;
+        double bA;
+        Exp1 e = exp_setup(k2, w * K1, h, C0, &bA);
+        s.z[0][u] = e.z; s.H[0][u] = e.H0; s.c[0][u] = e.c; s.rc[0][u] = e.rc; s.eT[0][u] = e.eT;
+        s.e0[u] = 0.0;
+        s.eP[u] = vB + bA;
+    } else if constexpr (KIND == KIND_IRR) {
+        const double k3 = th[2], vB = th[3];
+        const double w = 1.0 - vB;
+        const double beta = k2 + k3;
+        const double rb = 1.0 / beta;
+        double bA;
+        Exp1 e = exp_setup(beta, w * K1 * k2 * rb, h, C0, &bA);
+        s.z[0][u] = e.z; s.H[0][u] = e.H0; s.c[0][u] = e.c; s.rc[0][u] = e.rc; s.eT[0][u] = e.eT;
+        s.e0[u] = w * K1 * k3 * rb;  // (1 - vB) Ki on the running integral of the input
+        s.eP[u] = vB + bA;
+    } else {
+        const double k3 = th[2], k4 = th[3], vB = th[4];
+        const double w = 1.0 - vB;
+        const double sum = k2 + k3 + k4;
+        const double r = sqrt(sum * sum - 4.0 * k2 * k4);
+        const double sr = sum + r;
+        const double a2 = 0.5 * sr;
+        const double a1 = 2.0 * k2 * k4 / sr;
+        const double rr = 1.0 / r;  // 1 / (a2 - a1)
+        double b1, b2;
+        Exp1 e1 = exp_setup(a1, w * K1 * (k3 + k4 - a1) * rr, h, C0, &b1);
+        Exp1 e2 = exp_setup(a2, w * K1 * (a2 - k3 - k4) * rr, h, C0, &b2);
+        s.z[0][u] = e1.z; s.H[0][u] = e1.H0; s.c[0][u] = e1.c; s.rc[0][u] = e1.rc; s.eT[0][u] = e1.eT;
+        s.z[1][u] = e2.z; s.H[1][u] = e2.H0; s.c[1][u] = e2.c; s.rc[1][u] = e2.rc; s.eT[1][u] = e2.eT;
+        s.e0[u] = 0.0;
+        s.eP[u] = vB + b1 + b2;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The step/frame loop.  ACCj: exponential j accumulates its frame sums per
+// step (else they come from the recursion identity).  The sink receives the
+// frame value times the frame's step count, X_f = n_f x_f.
+// ---------------------------------------------------------------------------
+template <int NE, int U, bool Q, bool ACC0, bool ACC1, class Sink>
+__device__ __forceinline__ void run_frames(const Tab& T, int F, int k0, DrawState<NE, U>& s, Sink& sink) {
+    const cdp C = (cdp)T.C;
+    const cdp FR = (cdp)T.fr;
+    const cip NF = (cip)T.nf;
+    double H[NE][U], Ha[NE][U], acc[NE][U], eD[NE][U], eA[NE][U], eR[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        eR[u] = 0.0;
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            const bool accj = (j == 0) ? ACC0 : ACC1;
+            H[j][u] = s.H[j][u];
+            acc[j][u] = 0.0;
+            if (accj) {  // T = acc - D/2
+                eA[j][u] = s.eT[j][u];
+                eD[j][u] = -0.5 * s.eT[j][u];
+            } else {     // T = (1/c - 1/2) D + R / c
+                eA[j][u] = 0.0;
+                eD[j][u] = s.eT[j][u] * (s.rc[j][u] - 0.5);
+                eR[u] = fma(s.eT[j][u], s.rc[j][u], eR[u]);
+            }
+        }
+    }
+#define VPET_STEP(cval)                                                  \
+    do {                                                                 \
+        const double cc_ = (cval);                                       \
+        _Pragma("unroll") for (int u = 0; u < U; ++u) {                  \
+            _Pragma("unroll") for (int j = 0; j < NE; ++j) {             \
+                const bool accj = (j == 0) ? ACC0 : ACC1;                \
+                if (accj) acc[j][u] += H[j][u];                          \
+                H[j][u] = fma(s.z[j][u], H[j][u], cc_);                  \
+            }                                                            \
+        }                                                                \
+    } while (0)
+
+    int k = 0;
+    for (; k < k0; ++k) VPET_STEP(C[k]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            Ha[j][u] = H[j][u];
+            acc[j][u] = 0.0;  // the steps before the first frame are not part of any frame sum
+        }
+
+    for (int f = 0; f < F; ++f) {
+        const int n = NF[f];
+        const cdp Cp = C + k;
+        int q = 0;
+        for (; q + 4 <= n; q += 4) {
+            const double c0 = Cp[q], c1 = Cp[q + 1], c2 = Cp[q + 2], c3 = Cp[q + 3];
+            VPET_STEP(c0);
+            VPET_STEP(c1);
+            VPET_STEP(c2);
+            VPET_STEP(c3);
+        }
+        for (; q < n; ++q) VPET_STEP(Cp[q]);
+        k += n;
+        const double SS = FR[4 * f], PP = FR[4 * f + 1], R = FR[4 * f + 2];
+        double X[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double x = s.eP[u] * PP;
+            if (Q) x = fma(s.e0[u], SS, x);
+            x = fma(eR[u], R, x);
+#pragma unroll
+            for (int j = 0; j < NE; ++j) {
+                const bool accj = (j == 0) ? ACC0 : ACC1;
+                x = fma(eD[j][u], Ha[j][u] - H[j][u], x);
+                if (accj) {
+                    x = fma(eA[j][u], acc[j][u], x);
+                    acc[j][u] = 0.0;
+                }
+                Ha[j][u] = H[j][u];
+            }
+            X[u] = x;
+        }
+        sink(f, n, X);
+    }
+#undef VPET_STEP
+}
+
+__device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0ull; }
+
+// Choose the frame-sum path per exponential from a wave vote, then run.
+template <int KIND, int U, class Sink>
+__device__ __forceinline__ void simulate_draws(const Tab& T, int F, int k0, DrawState<ModelTraits<KIND>::NE, U>& s,
+                                               Sink& sink) {
+    constexpr int NE = ModelTraits<KIND>::NE;
+    constexpr bool Q = ModelTraits<KIND>::Q;
+    bool ok0 = true, ok1 = true;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        ok0 = ok0 && (s.c[0][u] >= kCmin);
+        if (NE > 1) ok1 = ok1 && (s.c[NE - 1][u] >= kCmin);
+    }
+    const bool id0 = wave_all(ok0);
+    if constexpr (NE == 1) {
+        if (id0)
+            run_frames<NE, U, Q, false, false>(T, F, k0, s, sink);
+        else
+            run_frames<NE, U, Q, true, false>(T, F, k0, s, sink);
+    } else {
+        const bool id1 = wave_all(ok1);
+        if (id0 && id1)
+            run_frames<NE, U, Q, false, false>(T, F, k0, s, sink);
+        else if (id1)
+            run_frames<NE, U, Q, true, false>(T, F, k0, s, sink);
+        else
+            run_frames<NE, U, Q, true, true>(T, F, k0, s, sink);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront / block helpers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Bitonic sort of a[0..len) (len a power of two >= 2) by one wavefront.
+__device__ void wave_bitonic_sort(uint64_t* a, int len) {
+    const int lane = lane_id();
+    for (int kk = 2; kk <= len; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int p = lane; p < (len >> 1); p += kWave) {
+                const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                const int l = i | j;
+                const uint64_t x = a[i], y = a[l];
+                const bool up = (i & kk) == 0;
+                if ((x > y) == up) {
+                    a[i] = y;
+                    a[l] = x;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+// Same over the whole block (all waves), with barriers.
+__device__ void block_bitonic_sort(uint64_t* a, int len) {
+    for (int kk = 2; kk <= len; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int p = threadIdx.x; p < (len >> 1); p += blockDim.x) {
+                const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                const int l = i | j;
+                const uint64_t x = a[i], y = a[l];
+                const bool up = (i & kk) == 0;
+                if ((x > y) == up) {
+                    a[i] = y;
+                    a[l] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Running top-n of one wavefront: keys[0, n) is the sorted set (padded with
+// kNoKey), keys[n, n + nbuf) the unsorted candidates, keys[.., cap) free.
+struct TopN {
+    uint64_t* keys;
+    int n, cap, nbuf;
+    uint64_t tau;
+
+    __device__ void merge() {
+        for (int j = n + nbuf + lane_id(); j < cap; j += kWave) keys[j] = kNoKey;
+        wave_lds_sync();
+        wave_bitonic_sort(keys, cap);
+        tau = keys[n - 1];
+        nbuf = 0;
+    }
+
+    template <int U>
+    __device__ void insert(const uint64_t (&key)[U]) {
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) cnt += __popcll(__ballot(key[u] < tau));
+        if (cnt == 0) return;
+        if (nbuf + cnt > cap - n) merge();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool p = key[u] < tau;
+            const uint64_t b = __ballot(p);
+            if (p) keys[n + nbuf + (int)mbcnt(b)] = key[u];
+            nbuf += __popcll(b);
+        }
+        wave_lds_sync();
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Sum of NV values over the block; every thread gets the totals.
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double* red, int wpv) {
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    if (lane_id() == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[wave * 8 + q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < wpv; ++w) t += red[w * 8 + q];
+        v[q] = t;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Sinks.
+// ---------------------------------------------------------------------------
+template <int U, bool L1>
+struct DistSink {
+    const double2* yw;  // per frame: (n_f y_f, scaled weight)
+    double d[U];
+    __device__ __forceinline__ void operator()(int f, int, const double (&X)[U]) {
+        const double2 q = yw[f];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double r = q.x - X[u];
+            d[u] = L1 ? fma(q.y, fabs(r), d[u]) : fma(q.y * r, r, d[u]);
+        }
+    }
+};
+
+struct TacSink {
+    float* out;  // row base, or nullptr for a padding lane
+    __device__ __forceinline__ void operator()(int f, int n, const double (&X)[1]) {
+        if (out) out[f] = (float)(X[0] / (double)n);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+template <int KIND, int U, bool L1>
+__device__ __forceinline__ void tile_keys(const InferArgs& P, int m, uint32_t v, uint32_t i0,
+                                          const double2* yw, uint64_t (&key)[U]) {
+    const ModelDev& md = P.md[m];
+    constexpr int NE = ModelTraits<KIND>::NE;
+    DrawState<NE, U> s;
+    uint32_t idx[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t i = i0 + (uint32_t)(u * kWave + lane_id());
+        ok[u] = i < P.n_draws;
+        idx[u] = ok[u] ? i : P.n_draws - 1;
+        float th[5];
+        draw_params(md, P.key0, P.key1, v, idx[u], (uint32_t)m, th);
+        setup<KIND, NE, U>(th, P.h, P.C0, s, u);
+    }
+    DistSink<U, L1> sink;
+    sink.yw = yw;
+#pragma unroll
+    for (int u = 0; u < U; ++u) sink.d[u] = 0.0;
+    simulate_draws<KIND, U>(P.tab, P.F, P.k0, s, sink);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        float fd = (float)sink.d[u];
+        if (!(fd == fd)) fd = __builtin_inff();
+        const uint32_t g = (uint32_t)m * P.n_draws + idx[u];
+        key[u] = ok[u] ? (((uint64_t)__float_as_uint(fd) << 32) | g) : kNoKey;
+    }
+}
+
+// Slot values (K1, k2, k3, k4, vB, Ki) of an accepted draw.
+__device__ __forceinline__ void slot_values(int kind, const float th[5], double val[6]) {
+    val[0] = th[0];
+    val[1] = th[1];
+    if (kind == KIND_1TCM) {
+        val[2] = 0.0; val[3] = 0.0; val[4] = th[2]; val[5] = 0.0;
+    } else if (kind == KIND_IRR) {
+        val[2] = th[2]; val[3] = 0.0; val[4] = th[3];
+        val[5] = val[0] * val[2] / (val[1] + val[2]);
+    } else {
+        val[2] = th[2]; val[3] = th[3]; val[4] = th[4];
+        val[5] = val[0] * val[2] / (val[1] + val[2]);
+    }
+}
+
+__device__ __forceinline__ bool slot_used(int kind, int q) {
+    if (q == 5) return kind != KIND_1TCM;
+    if (kind == KIND_1TCM) return q == 0 || q == 1 || q == 4;
+    if (kind == KIND_IRR) return q != 3;
+    return true;
+}
+
+template <bool L1>
+__global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long row = blockIdx.x;
+    if (row >= P.V) return;
+    const int F = P.F;
+    const uint32_t vg = (uint32_t)(P.vbase + (unsigned long long)row);
+    double2* yw = reinterpret_cast<double2*>(lds);
+    const int yw_bytes = (16 * F + 15) & ~15;
+    uint64_t* keys_all = reinterpret_cast<uint64_t*>(lds + yw_bytes);
+    double* red = reinterpret_cast<double*>(keys_all + (size_t)P.wpv * P.cap);
+    int* flag = reinterpret_cast<int*>(red + 8 * kMaxWpv);
+    const int n = (int)P.n_acc;
+
+    // Observed curve, validity and scaled weights (wave 0).
+    if (wave == 0) {
+        const float* y = P.tacs + (size_t)row * F;
+        const cdp FR = (cdp)P.tab.fr;
+        const cip NF = (cip)P.tab.nf;
+        float ymax = -__builtin_inff();
+        int bad = 0;
+        for (int f = lane; f < F; f += kWave) {
+            const float yy = y[f];
+            bad |= !isfinite(yy);
+            ymax = fmaxf(ymax, yy);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            ymax = fmaxf(ymax, __shfl_xor(ymax, off, kWave));
+            bad |= __shfl_xor(bad, off, kWave);
+        }
+        const bool valid = !bad && ymax > 0.0f;
+        const double den_floor = P.floor_frac * (double)ymax;
+        for (int f = lane; f < F; f += kWave) {
+            const double nfd = (double)NF[f];
+            const double yy = (double)y[f];
+            double w;
+            if (P.weights) {
+                w = (double)P.weights[(size_t)row * F + f];
+            } else {
+                const double den = yy > den_floor ? yy : den_floor;
+                w = FR[4 * f + 3] / den;
+            }
+            const double W = P.l1 ? sqrt(w) / nfd : w / (nfd * nfd);
+            yw[f] = make_double2(nfd * yy, W);
+        }
+        if (lane == 0) *flag = valid ? 1 : 0;
+    }
+    __syncthreads();
+    if (*flag == 0) {
+        if (wave == 0) {
+            const float qnan = __builtin_nanf("");
+            for (int j = lane; j < P.M * 16; j += kWave) P.out_mom[(size_t)row * P.M * 16 + j] = qnan;
+            for (int j = lane; j < P.M; j += kWave) P.out_prob[(size_t)row * P.M + j] = qnan;
+            if (P.out_idx)
+                for (int j = lane; j < n; j += kWave) P.out_idx[(size_t)row * n + j] = -1;
+            if (P.out_dist)
+                for (int j = lane; j < n; j += kWave) P.out_dist[(size_t)row * n + j] = qnan;
+            if (P.out_thr && lane == 0) P.out_thr[row] = qnan;
+        }
+        return;
+    }
+
+    // Stream every draw of every model through the wave's running top-n.
+    TopN top;
+    top.keys = keys_all + (size_t)wave * P.cap;
+    top.n = n;
+    top.cap = P.cap;
+    top.nbuf = 0;
+    top.tau = kNoKey;
+    for (int j = lane; j < P.cap; j += kWave) top.keys[j] = kNoKey;
+    wave_lds_sync();
+    const uint32_t ntiles = (P.n_draws + kTile - 1) / kTile;
+    for (int m = 0; m < P.M; ++m) {
+        const int kind = P.md[m].kind;
+        for (uint32_t t = (uint32_t)wave; t < ntiles; t += (uint32_t)P.wpv) {
+            uint64_t key[kU];
+            if (kind == KIND_IRR)
+                tile_keys<KIND_IRR, kU, L1>(P, m, vg, t * kTile, yw, key);
+            else if (kind == KIND_REV)
+                tile_keys<KIND_REV, kU, L1>(P, m, vg, t * kTile, yw, key);
+            else
+                tile_keys<KIND_1TCM, kU, L1>(P, m, vg, t * kTile, yw, key);
+            top.insert(key);
+        }
+    }
+    top.merge();
+    __syncthreads();
+    if (P.wpv > 1) block_bitonic_sort(keys_all, P.wpv * P.cap);
+    const uint64_t* acc = keys_all;  // the n accepted keys, ascending
+
+    if (P.out_idx)
+        for (int j = tid; j < n; j += blockDim.x) P.out_idx[(size_t)row * n + j] = (int)(uint32_t)acc[j];
+    if (P.out_dist)
+        for (int j = tid; j < n; j += blockDim.x) P.out_dist[(size_t)row * n + j] = __uint_as_float((uint32_t)(acc[j] >> 32));
+    if (P.out_thr && tid == 0) P.out_thr[row] = __uint_as_float((uint32_t)(acc[n - 1] >> 32));
+
+    // Survivor reduction per model: count, mean, variance (two passes, FP64).
+    for (int m = 0; m < P.M; ++m) {
+        const ModelDev& md = P.md[m];
+        double s1[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) s1[q] = 0.0;
+        for (int j = tid; j < n; j += blockDim.x) {
+            const uint32_t g = (uint32_t)acc[j];
+            if (g / P.n_draws != (uint32_t)m) continue;
+            float th[5];
+            draw_params(md, P.key0, P.key1, vg, g - (uint32_t)m * P.n_draws, (uint32_t)m, th);
+            double val[6];
+            slot_values(md.kind, th, val);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s1[q] += val[q];
+            s1[6] += 1.0;
+        }
+        block_sum<7>(s1, red, P.wpv);
+        const double cnt = s1[6];
+        double mean[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) mean[q] = s1[q] / cnt;
+        double s2[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s2[q] = 0.0;
+        for (int j = tid; j < n; j += blockDim.x) {
+            const uint32_t g = (uint32_t)acc[j];
+            if (g / P.n_draws != (uint32_t)m) continue;
+            float th[5];
+            draw_params(md, P.key0, P.key1, vg, g - (uint32_t)m * P.n_draws, (uint32_t)m, th);
+            double val[6];
+            slot_values(md.kind, th, val);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const double dv = val[q] - mean[q];
+                s2[q] = fma(dv, dv, s2[q]);
+            }
+        }
+        block_sum<6>(s2, red, P.wpv);
+        if (tid < 16) {
+            const int q = tid >> 1;
+            float outv = __builtin_nanf("");
+            if (q < 6 && slot_used(md.kind, q) && cnt > 0.0) {
+                if ((tid & 1) == 0)
+                    outv = (float)mean[q];
+                else
+                    outv = (cnt > 1.0) ? (float)(s2[q] / (cnt - 1.0)) : 0.0f;
+            }
+            P.out_mom[((size_t)row * P.M + m) * 16 + tid] = outv;
+        }
+        if (tid == 0) P.out_prob[(size_t)row * P.M + m] = (float)(cnt / (double)n);
+    }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void vpet_simulate_kernel(const float* __restrict__ theta, long long n, Tab T,
+                                                            double C0, double h, int F, int k0, float* out) {
+    const long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = row < n;
+    const long long r = ok ? row : n - 1;
+    float th[5];
+    const float* t = theta + (size_t)r * VPET_PSTRIDE;
+    if (KIND == KIND_1TCM) {
+        th[0] = t[0]; th[1] = t[1]; th[2] = t[4]; th[3] = 0.f; th[4] = 0.f;
+    } else if (KIND == KIND_IRR) {
+        th[0] = t[0]; th[1] = t[1]; th[2] = t[2]; th[3] = t[4]; th[4] = 0.f;
+    } else {
+        th[0] = t[0]; th[1] = t[1]; th[2] = t[2]; th[3] = t[3]; th[4] = t[4];
+    }
+    constexpr int NE = ModelTraits<KIND>::NE;
+    DrawState<NE, 1> s;
+    setup<KIND, NE, 1>(th, h, C0, s, 0);
+    TacSink sink{ok ? out + (size_t)row * F : nullptr};
+    simulate_draws<KIND, 1>(T, F, k0, s, sink);
+}
+
+__global__ __launch_bounds__(256) void vpet_draws_kernel(ModelDev md0, ModelDev md1, ModelDev md2, int M,
+                                                         uint32_t key0, uint32_t key1, const int64_t* voxel,
+                                                         const int64_t* draw, const int32_t* mpos, long long count,
+                                                         uint32_t* out_words, float* out_theta) {
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const int m = mpos[j];
+    float* th_out = out_theta + (size_t)j * VPET_PSTRIDE;
+    uint32_t* w_out = out_words + (size_t)j * 8;
+    for (int q = 0; q < VPET_PSTRIDE; ++q) th_out[q] = __builtin_nanf("");
+    for (int q = 0; q < 8; ++q) w_out[q] = 0u;
+    if (m < 0 || m >= M) return;
+    const ModelDev& md = (m == 0) ? md0 : (m == 1 ? md1 : md2);
+    float th[5];
+    uint32_t words[8];
+    draw_params(md, key0, key1, (uint32_t)voxel[j], (uint32_t)draw[j], (uint32_t)m, th, words);
+    for (int q = 0; q < 8; ++q) w_out[q] = words[q];
+    for (int q = 0; q < md.np; ++q) th_out[md.slot[q]] = th[q];
+}
+
+// ===========================================================================
+// Host side.
+// ===========================================================================
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(VPET_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Draw-independent tables, FP64 on the host.
+struct HostTab {
+    int K = 0, F = 0, k0 = 0, kend = 0;
+    double h = 0.0, C0 = 0.0;
+    std::vector<double> C, fr;
+    std::vector<int> nf;
+};
+
+int make_tables(const float* input_fn, const float* frame_times, vpet_grid g, double lambda, HostTab& T) {
+    if (!input_fn || !frame_times) return fail(VPET_E_ARG, "input_fn and frame_times must not be NULL");
+    if (!(std::isfinite(g.dt) && g.dt > 0.0f)) return fail(VPET_E_GRID, "grid.dt must be finite and > 0");
+    if (g.n_nodes < 2 || g.n_nodes > VPET_MAX_NODES)
+        return fail(g.n_nodes > VPET_MAX_NODES ? VPET_E_LIMIT : VPET_E_GRID, "grid.n_nodes %d outside [2, %d]",
+                    g.n_nodes, VPET_MAX_NODES);
+    if (g.n_frames < 1 || g.n_frames > VPET_MAX_FRAMES)
+        return fail(g.n_frames > VPET_MAX_FRAMES ? VPET_E_LIMIT : VPET_E_GRID, "grid.n_frames %d outside [1, %d]",
+                    g.n_frames, VPET_MAX_FRAMES);
+    T.K = g.n_nodes - 1;
+    T.F = g.n_frames;
+    T.h = (double)g.dt;
+    for (int k = 0; k <= T.K; ++k)
+        if (!std::isfinite(input_fn[k])) return fail(VPET_E_ARG, "input_fn[%d] is not finite", k);
+    std::vector<int> kf(T.F + 1);
+    for (int f = 0; f <= T.F; ++f) {
+        const double tau = (double)frame_times[f];
+        if (!std::isfinite(tau)) return fail(VPET_E_GRID, "frame_times[%d] is not finite", f);
+        const double kd = std::nearbyint(tau / T.h);
+        if (std::fabs(kd * T.h - tau) > 1e-6 * std::fmax(1.0, std::fabs(tau)))
+            return fail(VPET_E_GRID, "frame bound %g is not on the %g-min grid", tau, T.h);
+        if (kd < 0.0 || kd > (double)T.K)
+            return fail(VPET_E_GRID, "frame bound %g lies outside the grid [0, %g]", tau, T.K * T.h);
+        kf[f] = (int)kd;
+        if (f > 0 && kf[f] <= kf[f - 1]) return fail(VPET_E_GRID, "frame bounds must increase strictly");
+    }
+    T.k0 = kf[0];
+    T.kend = kf[T.F];
+    T.C0 = (double)input_fn[0];
+    std::vector<double> Cn(T.kend + 1), Q(T.kend + 1);
+    for (int k = 0; k <= T.kend; ++k) Cn[k] = (double)input_fn[k];
+    Q[0] = 0.0;
+    for (int k = 0; k < T.kend; ++k) Q[k + 1] = Q[k] + 0.5 * T.h * (Cn[k] + Cn[k + 1]);
+    T.C.assign(Cn.begin(), Cn.begin() + T.kend);
+    T.fr.assign(4 * (size_t)T.F, 0.0);
+    T.nf.assign(T.F, 0);
+    for (int f = 0; f < T.F; ++f) {
+        const int a = kf[f], b = kf[f + 1];
+        double ss = 0.5 * (Q[a] + Q[b]), pp = 0.5 * (Cn[a] + Cn[b]), rr = 0.0;
+        for (int k = a + 1; k < b; ++k) {
+            ss += Q[k];
+            pp += Cn[k];
+        }
+        for (int k = a; k < b; ++k) rr += Cn[k];
+        const double dt = (double)(b - a) * T.h;
+        const double tmid = 0.5 * (double)(a + b) * T.h;
+        T.fr[4 * f + 0] = ss;
+        T.fr[4 * f + 1] = pp;
+        T.fr[4 * f + 2] = rr;
+        T.fr[4 * f + 3] = dt * std::exp(-lambda * tmid);
+        T.nf[f] = b - a;
+    }
+    return VPET_OK;
+}
+
+int model_list(uint32_t model_id, int kinds[kMaxModels]) {
+    if (model_id == 0u || (model_id & ~(VPET_M_1TCM | VPET_M_2TCM_IRR | VPET_M_2TCM_REV)) != 0u) return -1;
+    int M = 0;
+    for (uint32_t b = 1u; b <= VPET_M_2TCM_REV; b <<= 1)
+        if (model_id & b) kinds[M++] = (int)b;
+    return M;
+}
+
+int fill_model(int kind, const double* box, ModelDev& md) {
+    static const int s1[3] = {VPET_SLOT_K1, VPET_SLOT_K2, VPET_SLOT_VB};
+    static const int s2[4] = {VPET_SLOT_K1, VPET_SLOT_K2, VPET_SLOT_K3, VPET_SLOT_VB};
+    static const int s3[5] = {VPET_SLOT_K1, VPET_SLOT_K2, VPET_SLOT_K3, VPET_SLOT_K4, VPET_SLOT_VB};
+    const int* sl = kind == KIND_1TCM ? s1 : (kind == KIND_IRR ? s2 : s3);
+    md = ModelDev{};
+    md.kind = kind;
+    md.np = kind == KIND_1TCM ? 3 : (kind == KIND_IRR ? 4 : 5);
+    for (int j = 0; j < md.np; ++j) {
+        const int s = sl[j];
+        const double lo = box[2 * s], hi = box[2 * s + 1];
+        if (!(std::isfinite(lo) && std::isfinite(hi))) return fail(VPET_E_ARG, "prior box slot %d is not finite", s);
+        if (lo > hi) return fail(VPET_E_ARG, "prior box slot %d has lo > hi", s);
+        if (lo < 0.0) return fail(VPET_E_ARG, "prior box slot %d must be >= 0", s);
+        if (s == VPET_SLOT_VB && !(hi < 1.0)) return fail(VPET_E_ARG, "vB must stay below 1");
+        md.slot[j] = s;
+        md.lo[j] = (float)lo;
+        md.wid[j] = (float)(hi - lo);
+    }
+    if (kind != KIND_1TCM && !(box[2 * VPET_SLOT_K2] + box[2 * VPET_SLOT_K3] > 0.0))
+        return fail(VPET_E_ARG, "2TCM prior needs k2_lo + k3_lo > 0");
+    if (kind == KIND_REV && !(box[2 * VPET_SLOT_K3] > 0.0))
+        return fail(VPET_E_ARG, "reversible 2TCM prior needs k3_lo > 0");
+    return VPET_OK;
+}
+
+// Per-device ring of (pinned host, device) table slots.
+constexpr int kSlots = 8;
+constexpr size_t kSlotBytes = 256 * 1024;
+
+struct DevCtx {
+    std::mutex mu;
+    bool ready = false;
+    char* dbuf = nullptr;
+    char* hbuf = nullptr;
+    hipEvent_t ev[kSlots];
+    int next = 0;
+};
+DevCtx g_ctx[64];
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Uploads T into a slot and returns device pointers; the caller holds ctx.mu
+// until it has recorded ctx.ev[slot] after its launch.
+int upload_tables(DevCtx& ctx, const HostTab& T, hipStream_t st, Tab& tab, int& slot) {
+    if (!ctx.ready) {
+        hipError_t e = hipMalloc((void**)&ctx.dbuf, kSlots * kSlotBytes);
+        if (e != hipSuccess) return fail(VPET_E_NOMEM, "table buffer: %s", hipGetErrorString(e));
+        e = hipHostMalloc((void**)&ctx.hbuf, kSlots * kSlotBytes, hipHostMallocDefault);
+        if (e != hipSuccess) return fail(VPET_E_NOMEM, "pinned table buffer: %s", hipGetErrorString(e));
+        for (int s = 0; s < kSlots; ++s) {
+            e = hipEventCreateWithFlags(&ctx.ev[s], hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        }
+        ctx.ready = true;
+    }
+    const size_t offC = 0;
+    const size_t offF = align256(offC + sizeof(double) * T.C.size());
+    const size_t offN = align256(offF + sizeof(double) * T.fr.size());
+    const size_t bytes = align256(offN + sizeof(int) * T.nf.size());
+    if (bytes > kSlotBytes) return fail(VPET_E_LIMIT, "tables need %zu bytes (> %zu)", bytes, kSlotBytes);
+    slot = ctx.next;
+    ctx.next = (ctx.next + 1) % kSlots;
+    hipError_t e = hipEventSynchronize(ctx.ev[slot]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    char* hs = ctx.hbuf + slot * kSlotBytes;
+    char* ds = ctx.dbuf + slot * kSlotBytes;
+    if (!T.C.empty()) std::memcpy(hs + offC, T.C.data(), sizeof(double) * T.C.size());
+    std::memcpy(hs + offF, T.fr.data(), sizeof(double) * T.fr.size());
+    std::memcpy(hs + offN, T.nf.data(), sizeof(int) * T.nf.size());
+    e = hipMemcpyAsync(ds, hs, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tables)");
+    tab.C = reinterpret_cast<const double*>(ds + offC);
+    tab.fr = reinterpret_cast<const double*>(ds + offF);
+    tab.nf = reinterpret_cast<const int*>(ds + offN);
+    return VPET_OK;
+}
+
+int current_ctx(DevCtx** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(VPET_E_HIP, "device ordinal %d out of range", dev);
+    *out = &g_ctx[dev];
+    return VPET_OK;
+}
+
+int pow2_at_least(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI.
+// ===========================================================================
+extern "C" {
+
+const char* vpet_abc_last_error(void) { return g_err.c_str(); }
+
+int vpet_abc_version(void) { return VPET_VERSION_NUMBER; }
+
+int vpet_abc_accept_count(int64_t n_total, double accept_frac, int64_t* out_n) {
+    if (!out_n) return fail(VPET_E_ARG, "out_n must not be NULL");
+    if (n_total < 1) return fail(VPET_E_ARG, "n_total must be >= 1");
+    if (!(accept_frac > 0.0 && accept_frac <= 1.0)) return fail(VPET_E_ARG, "accept_frac must lie in (0, 1]");
+    const double v = std::floor((double)n_total * accept_frac + 1e-6);
+    if (v < 1.0) return fail(VPET_E_ARG, "n = floor(N p) = 0: accept at least one draw");
+    *out_n = v > (double)n_total ? n_total : (int64_t)v;
+    return VPET_OK;
+}
+
+int vpet_abc_simulate(uint32_t model_id, const float* theta, int64_t n, const float* input_fn,
+                      const float* frame_times, vpet_grid grid, float* out_tacs, void* hip_stream) {
+    int kinds[kMaxModels];
+    const int M = model_list(model_id, kinds);
+    if (M != 1) return fail(VPET_E_MODEL, "simulate needs exactly one known model bit (got 0x%x)", model_id);
+    if (n < 0) return fail(VPET_E_ARG, "n must be >= 0");
+    HostTab T;
+    int rc = make_tables(input_fn, frame_times, grid, 0.0, T);
+    if (rc != VPET_OK) return rc;
+    if (n == 0) return VPET_OK;
+    if (!theta || !out_tacs) return fail(VPET_E_ARG, "theta and out_tacs must not be NULL");
+    DevCtx* ctx;
+    if ((rc = current_ctx(&ctx)) != VPET_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    Tab tab;
+    int slot;
+    if ((rc = upload_tables(*ctx, T, st, tab, slot)) != VPET_OK) return rc;
+    const int threads = 256;
+    for (long long base = 0; base < n; base += (1LL << 30)) {
+        const long long cnt = std::min<long long>(n - base, 1LL << 30);
+        const unsigned blocks = (unsigned)((cnt + threads - 1) / threads);
+        const float* th = theta + (size_t)base * VPET_PSTRIDE;
+        float* out = out_tacs + (size_t)base * T.F;
+        if (kinds[0] == KIND_1TCM)
+            hipLaunchKernelGGL(vpet_simulate_kernel<KIND_1TCM>, dim3(blocks), dim3(threads), 0, st, th, cnt, tab, T.C0,
+                               T.h, T.F, T.k0, out);
+        else if (kinds[0] == KIND_IRR)
+            hipLaunchKernelGGL(vpet_simulate_kernel<KIND_IRR>, dim3(blocks), dim3(threads), 0, st, th, cnt, tab, T.C0,
+                               T.h, T.F, T.k0, out);
+        else
+            hipLaunchKernelGGL(vpet_simulate_kernel<KIND_REV>, dim3(blocks), dim3(threads), 0, st, th, cnt, tab, T.C0,
+                               T.h, T.F, T.k0, out);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "simulate launch");
+    }
+    hipError_t e = hipEventRecord(ctx->ev[slot], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return VPET_OK;
+}
+
+int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times, const float* input_fn,
+                   vpet_grid grid, uint32_t model_id, const double* prior_box, int64_t n_draws, double accept_frac,
+                   uint64_t seed, float* out_moments, float* out_model_prob, const vpet_abc_opts* opts,
+                   void* hip_stream) {
+    int kinds[kMaxModels];
+    const int M = model_list(model_id, kinds);
+    if (M < 1) return fail(VPET_E_MODEL, "unknown or empty model bitmask 0x%x", model_id);
+    if (n_voxels < 0) return fail(VPET_E_ARG, "n_voxels must be >= 0");
+    if (!prior_box) return fail(VPET_E_ARG, "prior_box must not be NULL");
+    if (n_draws < 1) return fail(VPET_E_ARG, "n_draws must be >= 1");
+    if ((double)M * (double)n_draws > 4294967295.0)
+        return fail(VPET_E_LIMIT, "M * n_draws must stay below 2^32");
+    vpet_abc_opts o{};
+    if (opts) o = *opts;
+    if (o.voxel_offset < 0 || (double)o.voxel_offset + (double)n_voxels > 4294967296.0)
+        return fail(VPET_E_ARG, "voxel indices must lie in [0, 2^32)");
+    if (o.distance != 0 && o.distance != 1) return fail(VPET_E_ARG, "opts.distance must be 0 (L2) or 1 (L1)");
+    if (!(std::isfinite(o.decay_lambda) && o.decay_lambda >= 0.0))
+        return fail(VPET_E_ARG, "opts.decay_lambda must be finite and >= 0");
+    if (!(std::isfinite(o.weight_floor_frac) && o.weight_floor_frac >= 0.0f))
+        return fail(VPET_E_ARG, "opts.weight_floor_frac must be finite and >= 0");
+    if (o.waves_per_voxel != 0 && o.waves_per_voxel != 1 && o.waves_per_voxel != 2 && o.waves_per_voxel != 4)
+        return fail(VPET_E_ARG, "opts.waves_per_voxel must be 0, 1, 2 or 4");
+    int64_t n_acc = 0;
+    int rc = vpet_abc_accept_count((int64_t)M * n_draws, accept_frac, &n_acc);
+    if (rc != VPET_OK) return rc;
+    if (n_acc > VPET_MAX_ACCEPT)
+        return fail(VPET_E_LIMIT, "n = %lld accepted draws exceeds VPET_MAX_ACCEPT = %d", (long long)n_acc,
+                    VPET_MAX_ACCEPT);
+    InferArgs P{};
+    for (int m = 0; m < M; ++m)
+        if ((rc = fill_model(kinds[m], prior_box + (size_t)m * VPET_PSTRIDE * 2, P.md[m])) != VPET_OK) return rc;
+    const double lambda = o.decay_lambda > 0.0 ? o.decay_lambda : std::log(2.0) / 109.8;
+    HostTab T;
+    if ((rc = make_tables(input_fn, frame_times, grid, lambda, T)) != VPET_OK) return rc;
+    if (n_voxels == 0) return VPET_OK;
+    if (!tacs || !out_moments || !out_model_prob)
+        return fail(VPET_E_ARG, "tacs, out_moments and out_model_prob must not be NULL");
+
+    const int cap = pow2_at_least((int)n_acc + kTile);
+    int wpv = o.waves_per_voxel;
+    if (wpv == 0) {
+        wpv = 1;
+        while (wpv < kMaxWpv && (double)n_voxels * wpv < 8192.0) wpv <<= 1;
+    }
+    auto lds_for = [&](int w) {
+        return (size_t)((16 * T.F + 15) & ~15) + sizeof(uint64_t) * (size_t)w * cap + sizeof(double) * 8 * kMaxWpv + 16;
+    };
+    while (wpv > 1 && lds_for(wpv) > (size_t)kLdsLimit) wpv >>= 1;
+    if (lds_for(wpv) > (size_t)kLdsLimit) return fail(VPET_E_LIMIT, "selection buffer exceeds LDS");
+
+    P.weights = o.weights;
+    P.C0 = T.C0;
+    P.h = T.h;
+    P.floor_frac = o.weight_floor_frac > 0.0f ? (double)o.weight_floor_frac : 0.01;
+    P.F = T.F;
+    P.k0 = T.k0;
+    P.M = M;
+    P.cap = cap;
+    P.wpv = wpv;
+    P.l1 = o.distance;
+    P.n_draws = (unsigned)n_draws;
+    P.n_acc = (unsigned)n_acc;
+    P.key0 = (unsigned)(seed & 0xffffffffu);
+    P.key1 = (unsigned)(seed >> 32);
+    P.out_mom = out_moments;
+    P.out_prob = out_model_prob;
+    P.out_idx = o.out_accept_idx;
+    P.out_dist = o.out_accept_dist;
+    P.out_thr = o.out_threshold;
+
+    DevCtx* ctx;
+    if ((rc = current_ctx(&ctx)) != VPET_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int slot;
+    if ((rc = upload_tables(*ctx, T, st, P.tab, slot)) != VPET_OK) return rc;
+    const size_t lds = lds_for(wpv);
+    const long long chunk = 1LL << 30;
+    for (long long base = 0; base < n_voxels; base += chunk) {
+        InferArgs Q = P;
+        Q.V = std::min<long long>(n_voxels - base, chunk);
+        Q.vbase = (unsigned long long)(o.voxel_offset + base);
+        Q.tacs = tacs + (size_t)base * T.F;
+        Q.weights = o.weights ? o.weights + (size_t)base * T.F : nullptr;
+        Q.out_mom = out_moments + (size_t)base * M * 16;
+        Q.out_prob = out_model_prob + (size_t)base * M;
+        Q.out_idx = o.out_accept_idx ? o.out_accept_idx + (size_t)base * n_acc : nullptr;
+        Q.out_dist = o.out_accept_dist ? o.out_accept_dist + (size_t)base * n_acc : nullptr;
+        Q.out_thr = o.out_threshold ? o.out_threshold + base : nullptr;
+        if (o.distance == 1)
+            hipLaunchKernelGGL(vpet_infer_kernel<true>, dim3((unsigned)Q.V), dim3(kWave * wpv), lds, st, Q);
+        else
+            hipLaunchKernelGGL(vpet_infer_kernel<false>, dim3((unsigned)Q.V), dim3(kWave * wpv), lds, st, Q);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "infer launch");
+    }
+    hipError_t e = hipEventRecord(ctx->ev[slot], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return VPET_OK;
+}
+
+int vpet_abc_draws(uint32_t model_id, const double* prior_box, uint64_t seed, const int64_t* voxel,
+                   const int64_t* draw, const int32_t* model_pos, int64_t count, uint32_t* out_words,
+                   float* out_theta, void* hip_stream) {
+    int kinds[kMaxModels];
+    const int M = model_list(model_id, kinds);
+    if (M < 1) return fail(VPET_E_MODEL, "unknown or empty model bitmask 0x%x", model_id);
+    if (!prior_box) return fail(VPET_E_ARG, "prior_box must not be NULL");
+    if (count < 0) return fail(VPET_E_ARG, "count must be >= 0");
+    ModelDev md[kMaxModels] = {};
+    int rc;
+    for (int m = 0; m < M; ++m)
+        if ((rc = fill_model(kinds[m], prior_box + (size_t)m * VPET_PSTRIDE * 2, md[m])) != VPET_OK) return rc;
+    if (count == 0) return VPET_OK;
+    if (!voxel || !draw || !model_pos || !out_words || !out_theta)
+        return fail(VPET_E_ARG, "device pointers must not be NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int threads = 256;
+    for (long long base = 0; base < count; base += (1LL << 30)) {
+        const long long cnt = std::min<long long>(count - base, 1LL << 30);
+        hipLaunchKernelGGL(vpet_draws_kernel, dim3((unsigned)((cnt + threads - 1) / threads)), dim3(threads), 0, st,
+                           md[0], md[1], md[2], M, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32),
+                           voxel + base, draw + base, model_pos + base, cnt, out_words + (size_t)base * 8,
+                           out_theta + (size_t)base * VPET_PSTRIDE);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "draws launch");
+    }
+    return VPET_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and rejects invalid requests with the documented status before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def V():
+    import paper_2603_14859_amd as mod
+    return mod
+
+
+def test_exports_every_declared_symbol(V):
+    hdr = open(os.path.join(ROOT, "include", "vpet_abc.h")).read()
+    declared = set(re.findall(r"\b(vpet_abc_\w+)\s*\(", hdr))
+    assert declared == set(V.EXPORTED)
+    for name in declared:
+        assert hasattr(V.lib, name)
+    assert V.version() == 10000
+
+
+def test_accept_count(V):
+    import oracle
+    for n_tot, p in [(2000, 0.01), (100000, 0.001), (10, 0.3), (3, 0.999), (7, 1.0), (10**9, 1e-7)]:
+        assert V.accept_count(n_tot, p) == oracle.accept_count(n_tot, p)
+    for n_tot, p in [(10, 0.05), (10, 0.0), (10, 1.5), (0, 0.5), (10, float("nan"))]:
+        with pytest.raises(V.VpetError) as e:
+            V.accept_count(n_tot, p)
+        assert e.value.status == V.E_ARG
+
+
+def _call_infer(V, *, model=2, ft=None, cp=None, dt=0.2, box=None, n_draws=100, p=0.1, V_=0, F=None, opts=None):
+    ft = W.frame_times(W.SCHED_22x60) if ft is None else np.asarray(ft, dtype=np.float32)
+    cp = W.grid(0.2, 60.0)[1] if cp is None else np.asarray(cp, dtype=np.float32)
+    M = bin(model).count("1") if model else 1
+    box = W.box_array([2] * M) if box is None else np.asarray(box, dtype=np.float64)
+    F = ft.size - 1 if F is None else F
+    grid = V._binding.Grid(dt, cp.size, F)
+    st = V.lib.vpet_abc_infer(None, V_, ft.ctypes.data_as(ctypes.c_void_p), cp.ctypes.data_as(ctypes.c_void_p), grid,
+                              model, box.ctypes.data_as(ctypes.c_void_p), n_draws, p, 1, None, None,
+                              ctypes.byref(opts) if opts is not None else None, None)
+    return st, V.lib.vpet_abc_last_error().decode()
+
+
+def test_infer_validation_without_gpu(V):
+    assert _call_infer(V)[0] == V.OK                      # V = 0: nothing to do
+    assert _call_infer(V, model=0)[0] == V.E_MODEL
+    assert _call_infer(V, model=8)[0] == V.E_MODEL
+    assert _call_infer(V, p=0.0)[0] == V.E_ARG
+    assert _call_infer(V, p=0.001)[0] == V.E_ARG          # n = 0
+    assert _call_infer(V, n_draws=0)[0] == V.E_ARG
+    assert _call_infer(V, n_draws=200000, p=0.5)[0] == V.E_LIMIT
+    bad = W.frame_times(W.SCHED_22x60).copy()
+    bad[3] += np.float32(0.05)
+    assert _call_infer(V, ft=bad)[0] == V.E_GRID
+    assert _call_infer(V, ft=np.array([0, 1, 1], np.float32), F=2)[0] == V.E_GRID
+    assert _call_infer(V, ft=np.array([0, 1, 70], np.float32), F=2)[0] == V.E_GRID
+    box = W.box_array([2])
+    box[0, 0] = (0.5, 0.1)
+    st, msg = _call_infer(V, box=box)
+    assert st == V.E_ARG and "lo > hi" in msg
+    box = W.box_array([2])
+    box[0, 4] = (0.0, 1.0)
+    assert _call_infer(V, box=box)[0] == V.E_ARG          # vB must stay below 1
+    box = W.box_array([4])
+    box[0, 2] = (0.0, 0.3)
+    assert _call_infer(V, model=4, box=box)[0] == V.E_ARG  # reversible needs k3_lo > 0
+    box = W.box_array([2])
+    box[0, 1] = (0.0, 1.0)
+    box[0, 2] = (0.0, 0.3)
+    assert _call_infer(V, box=box)[0] == V.E_ARG          # 2TCM needs k2_lo + k3_lo > 0
+    box = W.box_array([2])
+    box[0, 1] = (-0.1, 1.0)
+    assert _call_infer(V, box=box)[0] == V.E_ARG
+    box = W.box_array([2])
+    box[0, 0] = (0.0, np.inf)
+    assert _call_infer(V, box=box)[0] == V.E_ARG
+    o = V._binding.Opts()
+    o.distance = 3
+    assert _call_infer(V, opts=o)[0] == V.E_ARG
+    o = V._binding.Opts()
+    o.waves_per_voxel = 3
+    assert _call_infer(V, opts=o)[0] == V.E_ARG
+    o = V._binding.Opts()
+    o.voxel_offset = 2**32 + 5
+    assert _call_infer(V, opts=o)[0] == V.E_ARG
+    assert _call_infer(V, dt=0.0)[0] == V.E_GRID
+    cp = W.grid(0.2, 60.0)[1].copy()
+    cp[4] = np.nan
+    assert _call_infer(V, cp=cp)[0] == V.E_ARG
+
+
+def test_simulate_and_draws_validation_without_gpu(V):
+    ft = W.frame_times(W.SCHED_22x60)
+    cp = W.grid(0.2, 60.0)[1]
+    g = V._binding.Grid(0.2, cp.size, ft.size - 1)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert V.lib.vpet_abc_simulate(6, None, 10, P(cp), P(ft), g, None, None) == V.E_MODEL
+    assert V.lib.vpet_abc_simulate(2, None, -1, P(cp), P(ft), g, None, None) == V.E_ARG
+    assert V.lib.vpet_abc_simulate(2, None, 0, P(cp), P(ft), g, None, None) == V.OK
+    g2 = V._binding.Grid(0.2, cp.size, 5)
+    assert V.lib.vpet_abc_simulate(2, None, 0, P(cp), P(np.array([0, .2, .3, .4, .6, .8], np.float32)), g2, None,
+                                   None) == V.E_GRID
+    box = W.box_array([2])
+    assert V.lib.vpet_abc_draws(0, P(box), 1, None, None, None, 5, None, None, None) == V.E_MODEL
+    assert V.lib.vpet_abc_draws(2, P(box), 1, None, None, None, 0, None, None, None) == V.OK
+    assert V.lib.vpet_abc_draws(2, P(box), 1, None, None, None, 5, None, None, None) == V.E_ARG
+    assert V.lib.vpet_abc_last_error().decode() != ""

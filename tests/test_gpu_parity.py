@@ -1,0 +1,250 @@
+"""GPU parity: the HIP library against the FP64 oracle on identical seeded inputs.
+
+All calls go through the C ABI (ctypes binding).  Inputs come from the
+`workloads` generators; observed TACs are made noise-free by the oracle's
+forward model and then noised, so no input or expected value comes from the
+GPU path.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import MEAN_RTOL, TAC_RTOL, compare_sets, oracle_moments_of, tac_rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU-only hosts
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2603_14859_amd as V  # noqa: E402  (fails loudly if the library is missing)
+
+DEV = torch.device("cuda:0")
+H = 0.2
+
+
+def _inputs(sched=W.SCHED_22x60, n_vox=64, model=W.M_2TCM_IRR, seed=2603014859, level=0.05):
+    import oracle as ora
+    ft = W.frame_times(sched)
+    _, cp = W.grid(H, float(np.sum(sched)))
+    rng = np.random.default_rng(seed)
+    box = W.box_array([model])[0]
+    th = W.true_params(rng, n_vox, model, box)
+    clean = ora.simulate(model, th, cp, H, ft)
+    y = W.add_noise(clean, ft, rng.standard_normal(clean.shape), level=level)
+    return ft, cp, y
+
+
+def _gpu_infer(y, ft, cp, models, boxes, n_draws, p, seed, **kw):
+    res = V.infer(torch.from_numpy(y).to(DEV), ft, cp, H, models, boxes, n_draws, p, seed, debug=True, **kw)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()}
+
+
+def _check_infer(ora, y, ft, cp, models, boxes, n_draws, p, seed, voxel_offset=0, l1=False, weights=None,
+                 wpv=0, strict_means=True):
+    g = _gpu_infer(y, ft, cp, models, boxes, n_draws, p, seed, voxel_offset=voxel_offset,
+                   distance="l1" if l1 else "l2", waves_per_voxel=wpv,
+                   weights=None if weights is None else torch.from_numpy(weights).to(DEV))
+    o = ora.infer(y, ft, cp, H, models, boxes, n_draws, p, seed, voxel_offset=voxel_offset, l1=l1,
+                  weights=weights, nthreads=0)
+    assert g["n"] == o["n"]
+    nvox, swaps = compare_sets(ora, g["accept_idx"], o, y, ft, cp, H, models, boxes, n_draws, seed,
+                               voxel_offset=voxel_offset, l1=l1, weights=weights)
+    print(f"[parity] V={y.shape[0]} n={o['n']} voxels with boundary swaps: {nvox} ({len(swaps)} draws)")
+    for v in range(y.shape[0]):
+        same = set(g["accept_idx"][v].tolist()) == set(o["accept_idx"][v].tolist())
+        if same:
+            ref_mom, ref_prob = o["moments"][v], o["model_prob"][v]
+        else:
+            ref_mom, ref_prob = oracle_moments_of(ora, list(models), boxes, seed, v + voxel_offset,
+                                                  g["accept_idx"][v], n_draws)
+        gm = g["moments"][v].astype(np.float64)
+        assert np.array_equal(np.isnan(gm), np.isnan(ref_mom)), f"voxel {v}: NaN pattern differs"
+        ok = ~np.isnan(ref_mom)
+        rt = 1e-5 if strict_means else MEAN_RTOL
+        assert np.allclose(gm[..., 0][ok[..., 0]], ref_mom[..., 0][ok[..., 0]], rtol=rt, atol=1e-7), f"voxel {v} means"
+        assert np.allclose(gm[..., 1][ok[..., 1]], ref_mom[..., 1][ok[..., 1]], rtol=1e-4, atol=1e-9), f"voxel {v} vars"
+        assert np.allclose(g["model_prob"][v], ref_prob, rtol=0, atol=1e-7, equal_nan=True)
+        # the accepted distances agree with the oracle's to fp32 rounding
+        if same:
+            assert np.allclose(np.sort(g["accept_dist"][v]), np.sort(o["accept_dist"][v]), rtol=1e-6, equal_nan=True)
+    return g, o
+
+
+# ---------------------------------------------------------------------------
+# A1: draws bit-exact
+# ---------------------------------------------------------------------------
+def test_draws_bitexact():
+    import oracle as ora
+    models = [W.M_1TCM, W.M_2TCM_IRR, W.M_2TCM_REV]
+    boxes = W.box_array(models)
+    boxes[2, 1] = (0.013, 1.7)
+    rng = np.random.default_rng(5)
+    n = 8192
+    v = rng.integers(0, 2**32, n)
+    i = rng.integers(0, 2**32, n)
+    m = rng.integers(0, 3, n).astype(np.int32)
+    v[:3], i[:3] = [0, 2**32 - 1, 5], [0, 2**32 - 1, 7]
+    for seed in (0, 14859, 2**64 - 1):
+        w_g, th_g = V.draws(models, boxes, seed, torch.from_numpy(v.astype(np.int64)).to(DEV),
+                            torch.from_numpy(i.astype(np.int64)).to(DEV), torch.from_numpy(m).to(DEV))
+        w_o, _, th_o = ora.draws(models, boxes, seed, v, i, m)
+        assert np.array_equal(w_g.cpu().numpy().view(np.uint32), w_o)
+        assert np.array_equal(th_g.cpu().numpy().view(np.uint32), th_o.view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# A2-A4: simulated TACs within 1e-5
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("model", [W.M_1TCM, W.M_2TCM_IRR, W.M_2TCM_REV])
+@pytest.mark.parametrize("sched", ["22x60", "30x50", "offset"])
+def test_simulate_parity(model, sched):
+    import oracle as ora
+    durations = {"22x60": W.SCHED_22x60, "30x50": W.SCHED_30x50, "offset": [0.2, 0.4, 1.0, 3.0, 5.4]}[sched]
+    ft = W.frame_times(durations)
+    t_end = float(np.sum(durations))
+    if sched == "offset":   # first frame starts after t = 0, grid longer than the last frame
+        ft = (ft + np.float32(1.4)).astype(np.float32)
+        t_end += 3.0
+    _, cp = W.grid(H, t_end)
+    box = W.box_array([model])[0]
+    if model == W.M_1TCM:
+        box[1] = (0.0, 1.0)         # includes a zero rate
+    rng = np.random.default_rng(model * 7 + len(durations))
+    n = 60_000
+    th = W.true_params(rng, n, model, box)
+    # corners of the prior box (slowest / fastest rates, extreme blood fraction)
+    slots = W.SLOTS[model]
+    corners = np.array(np.meshgrid(*[[0, 1]] * len(slots))).reshape(len(slots), -1).T
+    for r, c in enumerate(corners):
+        for s, b in zip(slots, c):
+            th[r, s] = np.float32(box[s][b])
+    if model == W.M_2TCM_REV:
+        th[-1000:, 3] = np.float32(0.0)                     # k4 = 0: a zero eigenvalue
+        th[-2000:-1000, 3] = rng.uniform(0, 1e-7, 1000).astype(np.float32)
+    got = V.simulate(model, torch.from_numpy(th).to(DEV), cp, ft, H).cpu().numpy()
+    want = ora.simulate(model, th, cp, H, ft)
+    err = tac_rel_err(got, want)
+    print(f"[simulate] model={model} sched={sched} max rel err {err.max():.3e}")
+    assert err.max() <= TAC_RTOL
+
+
+# ---------------------------------------------------------------------------
+# A0-A6 end to end: the small configuration at full size
+# ---------------------------------------------------------------------------
+def test_infer_parity_1024_voxels_22_frames():
+    import oracle as ora
+    cfg = W.CFG_SMALL
+    ft, cp, y = _inputs(cfg.durations, cfg.n_voxels)
+    models = [W.M_2TCM_IRR]
+    boxes = W.box_array(models)
+    _check_infer(ora, y, ft, cp, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed)
+
+
+@pytest.mark.parametrize("models", [(W.M_2TCM_IRR, W.M_2TCM_REV), (W.M_1TCM, W.M_2TCM_IRR),
+                                    (W.M_1TCM, W.M_2TCM_IRR, W.M_2TCM_REV)])
+def test_infer_parity_model_selection(models):
+    import oracle as ora
+    ft, cp, y = _inputs(W.SCHED_30x50, 48, model=W.M_2TCM_REV, seed=11)
+    boxes = W.box_array(list(models))
+    _check_infer(ora, y, ft, cp, list(models), boxes, 1500, 0.01, 77)
+
+
+def test_infer_parity_l1_and_caller_weights():
+    import oracle as ora
+    ft, cp, y = _inputs(W.SCHED_22x60, 40, seed=3)
+    models = [W.M_2TCM_IRR]
+    boxes = W.box_array(models)
+    _check_infer(ora, y, ft, cp, models, boxes, 1000, 0.02, 5, l1=True)
+    w = np.random.default_rng(2).uniform(0.2, 3.0, y.shape).astype(np.float32)
+    _check_infer(ora, y, ft, cp, models, boxes, 1000, 0.02, 5, weights=w)
+
+
+@pytest.mark.parametrize("n_draws,p", [(1, 1.0), (77, 0.05), (1000, 1.0), (1984, 1.0), (333, 0.003)])
+def test_infer_edge_sizes(n_draws, p):
+    import oracle as ora
+    ft, cp, y = _inputs(W.SCHED_22x60, 9, seed=n_draws)
+    models = [W.M_2TCM_IRR, W.M_2TCM_REV]
+    boxes = W.box_array(models)
+    _check_infer(ora, y, ft, cp, models, boxes, n_draws, p, 123, voxel_offset=1000)
+
+
+def test_infer_ties_nan_voxels_and_offsets():
+    import oracle as ora
+    ft, cp, y = _inputs(W.SCHED_22x60, 12, seed=4)
+    y[3, 5] = np.nan
+    y[7] = 0.0
+    models = [W.M_2TCM_IRR]
+    boxes = W.box_array(models)
+    g, o = _check_infer(ora, y, ft, cp, models, boxes, 500, 0.04, 9, voxel_offset=77)
+    for v in (3, 7):
+        assert np.isnan(g["moments"][v]).all() and np.isnan(g["model_prob"][v]).all()
+        assert (g["accept_idx"][v] == -1).all()
+    # a degenerate prior: every distance ties, so the lowest indices win
+    th = (0.4, 0.2, 0.05, 0.0, 0.04)
+    dbox = np.zeros((1, 8, 2))
+    for s in range(5):
+        dbox[0, s] = (th[s], th[s])
+    g = _gpu_infer(y[:2], ft, cp, models, dbox, 700, 0.1, 3)
+    assert np.array_equal(g["accept_idx"], np.tile(np.arange(70), (2, 1)))
+
+
+def test_infer_deterministic_across_launch_shapes():
+    ft, cp, y = _inputs(W.SCHED_22x60, 33, seed=8)
+    models = [W.M_2TCM_IRR, W.M_2TCM_REV]
+    boxes = W.box_array(models)
+    outs = [_gpu_infer(y, ft, cp, models, boxes, 900, 0.02, 4, waves_per_voxel=w) for w in (1, 2, 4, 4)]
+    for o in outs[1:]:
+        for k in ("accept_idx", "accept_dist", "threshold", "moments", "model_prob"):
+            assert np.array_equal(o[k], outs[0][k], equal_nan=True), k
+
+
+def test_infer_zero_voxels_and_errors():
+    t = torch.empty((0, 22), dtype=torch.float32, device=DEV)
+    ft = W.frame_times(W.SCHED_22x60)
+    _, cp = W.grid(H, 60.0)
+    res = V.infer(t, ft, cp, H, [W.M_2TCM_IRR], W.box_array([W.M_2TCM_IRR]), 100, 0.1, 1)
+    assert res["moments"].shape == (0, 1, 8, 2)
+    y = torch.ones((2, 22), dtype=torch.float32, device=DEV)
+    with pytest.raises(V.VpetError) as e:
+        V.infer(y, ft, cp, H, [W.M_2TCM_IRR], W.box_array([W.M_2TCM_IRR]), 100_000, 0.05, 1)
+    assert e.value.status == V.E_LIMIT
+
+
+# ---------------------------------------------------------------------------
+# Full size of the large configuration, in the launch shape the benchmark times:
+# sampled voxels against the oracle.
+# ---------------------------------------------------------------------------
+def test_infer_full_size_large_config_sampled():
+    import oracle as ora
+    cfg = W.CFG_LARGE
+    ft = cfg.frame_times
+    cp = cfg.input_fn()
+    th, eps = cfg.truth()
+    rng = np.random.default_rng(1)
+    sample = np.sort(rng.choice(cfg.n_voxels, 6, replace=False))
+    # noise-free curves from the oracle for the sampled voxels; the rest of the
+    # volume only needs plausible curves, so it reuses the sampled ones.
+    clean_s = ora.simulate(W.M_2TCM_IRR, th[sample], cp, H, ft)
+    y_s = W.add_noise(clean_s, ft, eps[sample])
+    y = np.tile(y_s, (cfg.n_voxels // len(sample) + 1, 1))[:cfg.n_voxels]
+    y[sample] = y_s
+    models = list(cfg.models)
+    boxes = cfg.box_array()
+    yt = torch.from_numpy(y).to(DEV)
+    res = V.infer(yt, ft, cp, H, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed, debug=True)
+    torch.cuda.synchronize()
+    g_idx = res["accept_idx"][torch.from_numpy(sample).to(DEV)].cpu().numpy()
+    g_mom = res["moments"][torch.from_numpy(sample).to(DEV)].cpu().numpy()
+    for j, v in enumerate(sample):
+        o = ora.infer(y_s[j:j + 1], ft, cp, H, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed,
+                      voxel_offset=int(v))
+        nvox, _ = compare_sets(ora, g_idx[j:j + 1], o, y_s[j:j + 1], ft, cp, H, models, boxes, cfg.n_draws,
+                               cfg.infer_seed, voxel_offset=int(v))
+        if nvox == 0:
+            ok = ~np.isnan(o["moments"][0])
+            assert np.allclose(g_mom[j][ok], o["moments"][0][ok], rtol=1e-4, atol=1e-7)
+    # every voxel of the volume produced finite outputs
+    assert torch.isfinite(res["model_prob"]).all()
+    assert torch.isfinite(res["moments"][:, 0, [0, 1, 2, 4, 5], 0]).all()
