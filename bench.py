@@ -1,0 +1,211 @@
+"""Benchmark: posterior voxels/s of voxelwise ABC rejection on one MI355X.
+
+One step = one vpet_abc_infer call over the whole synthetic volume (all voxels,
+all draws: prior sampling, forward simulation, discrepancy, selection and the
+posterior/model-probability reduction).  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+
+Default workload: 1,048,576 voxels (128 x 128 x 64), 30 frames over 50 min on a
+0.2-min grid, irreversible 2TCM prior box, 100,000 prior draws per voxel drawn
+independently for every voxel, 0.1 % accepted (n = 100).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "posterior voxels/s at fixed draws & error vs FP64 oracle; % of roofline"
+# MI355X: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s FP64 vector.
+PEAK_F64_VECTOR_TFLOPS = 78.6
+KERNEL_NAME = "vpet_infer_kernel"
+SRC = os.path.join(ROOT, "paper_2603_14859_amd", "csrc", "vpet_abc.hip")
+
+
+def flops_per_draw(n_steps: int, n_frames: int) -> int:
+    """Floating-point work of one irreversible-2TCM draw in the kernel's formulation:
+    one FMA per grid step (2 flops), 12 flops per frame (frame value from the
+    recursion identity: 8; weighted squared residual: 4), 40 flops of per-draw
+    set-up (theta map and coefficients, transcendental internals not counted)."""
+    return 2 * n_steps + 12 * n_frames + 40
+
+
+def source_sha() -> str:
+    with open(SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(workload_name: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{KERNEL_NAME}_{workload_name}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_src_sha") != source_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def make_inputs(cfg, dev):
+    import torch
+
+    import paper_2603_14859_amd as V
+    import workloads as W
+    ft, cp = cfg.frame_times, cfg.input_fn()
+    th, eps = cfg.truth()
+    # Noise-free curves of the true parameters from the library's forward model
+    # (this is input preparation, outside the timed region), then noise.
+    clean = V.simulate(cfg.models[0], torch.from_numpy(th).to(dev), cp, ft, cfg.dt).cpu().numpy()
+    y = W.add_noise(clean, ft, eps)
+    return ft, cp, y
+
+
+def cpu_baseline(cfg, ft, cp, y, y_dev, budget_s: float):
+    """The FP64 oracle on the host cores over a bounded sample of the same volume,
+    and the error of the GPU outputs on that sample."""
+    import torch
+
+    import oracle
+    import paper_2603_14859_amd as V
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    threads = max(1, min(threads, 64))
+    models, boxes = list(cfg.models), cfg.box_array()
+    n_cal = max(1, threads // 4)
+    t0 = time.perf_counter()
+    oracle.infer(y[:n_cal], ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed,
+                 nthreads=threads)
+    per_vox = (time.perf_counter() - t0) / n_cal
+    nv = int(max(threads, min(cfg.n_voxels, budget_s / max(per_vox, 1e-9))))
+    nv = max(threads, (nv // threads) * threads)
+    t0 = time.perf_counter()
+    ref = oracle.infer(y[:nv], ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed,
+                       nthreads=threads)
+    dt = time.perf_counter() - t0
+    # error of the GPU outputs against the oracle on these voxels (the same
+    # voxels re-run with the debug outputs on; results do not depend on how
+    # the volume is split into calls)
+    gpu_res = V.infer(y_dev[:nv].contiguous(), ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac,
+                      cfg.infer_seed, debug=True)
+    torch.cuda.synchronize()
+    g_idx = gpu_res["accept_idx"][:nv].cpu().numpy()
+    g_mom = gpu_res["moments"][:nv].cpu().numpy().astype(np.float64)
+    g_prob = gpu_res["model_prob"][:nv].cpu().numpy().astype(np.float64)
+    same = np.array([set(a.tolist()) == set(b.tolist()) for a, b in zip(g_idx, ref["accept_idx"])])
+    ok = ~np.isnan(ref["moments"])
+    rel = np.abs(g_mom - ref["moments"])[ok] / np.maximum(np.abs(ref["moments"][ok]), 1e-300)
+    mean_mask = ok.copy()
+    mean_mask[..., 1] = False
+    rel_mean = (np.abs(g_mom - ref["moments"])[mean_mask] / np.abs(ref["moments"][mean_mask]))
+    same_mean = np.abs(g_mom[same] - ref["moments"][same])[mean_mask[same]] / np.abs(ref["moments"][same][mean_mask[same]])
+    err = {
+        "voxels": int(nv),
+        "identical_accepted_sets": int(same.sum()),
+        "max_rel_err_posterior_mean_identical_sets": float(same_mean.max()) if same_mean.size else None,
+        "max_rel_err_posterior_mean_all": float(rel_mean.max()) if rel_mean.size else None,
+        "max_rel_err_moments_all": float(rel.max()) if rel.size else None,
+        "max_abs_err_model_prob": float(np.abs(g_prob - ref["model_prob"]).max()),
+    }
+    base = {"value": nv / dt, "unit": "voxels/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {nv} voxels of the same volume, all {cfg.n_draws} draws each, FP64, "
+                      f"OpenMP over voxels ({dt:.1f} s)"}
+    return base, err
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); voxels are independent, so "
+              "a multi-GPU run is one process per GPU on disjoint voxel ranges with no exchange.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2603_14859_amd as V
+    import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    cfg = W.CFG_LARGE if args.workload == "large" else W.CFG_SMALL
+    ft, cp, y_host = make_inputs(cfg, dev)
+    y = torch.from_numpy(y_host).to(dev)
+    models, boxes = list(cfg.models), cfg.box_array()
+    n_steps = int(round(float(ft[-1] - ft[0]) / np.float32(cfg.dt)))
+    F = ft.size - 1
+
+    def step(out):
+        return V.infer(y, ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed,
+                       out=out)
+
+    M = len(models)
+    res = {"moments": torch.empty((cfg.n_voxels, M, 8, 2), dtype=torch.float32, device=dev),
+           "model_prob": torch.empty((cfg.n_voxels, M), dtype=torch.float32, device=dev)}
+    for _ in range(args.warmup):
+        step(res)
+    torch.cuda.synchronize()
+    if args.copy_calibration:
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        step(res)
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = wall * 1e3 / args.steps
+    kernel_ms = float(np.mean(launch_ms))
+
+    fl = flops_per_draw(n_steps, F) * cfg.n_voxels * cfg.n_draws * len(models)
+    achieved = fl / (kernel_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_F64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_VECTOR_TFLOPS, 4),
+                "traffic": traffic_from_profiles(cfg.name),
+                "kernel": KERNEL_NAME, "kernel_ms": round(kernel_ms, 3),
+                "flops_per_draw": flops_per_draw(n_steps, F)}
+
+    out = {"metric": METRIC, "value": cfg.n_voxels / (ms_per_step * 1e-3), "unit": "voxels/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded Feng input, uniform prior truths, Gaussian frame noise)",
+           "config": {"workload": cfg.name, "voxels": cfg.n_voxels, "frames": F, "minutes": float(ft[-1]),
+                      "grid_dt_min": cfg.dt, "draws_per_voxel": cfg.n_draws, "accept_frac": cfg.accept_frac,
+                      "n_accept": V.accept_count(M * cfg.n_draws, cfg.accept_frac), "models": ["2TCM-irreversible"], "draws": "per-voxel Philox4x32-10",
+                      "parallelism": "single GPU"},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        base, err = cpu_baseline(cfg, ft, cp, y_host, y, args.cpu_budget)
+        out["cpu_baseline"] = base
+        out["error_vs_oracle"] = err
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -545,7 +545,9 @@ __device__ __forceinline__ bool slot_used(int kind, int q) {
     return true;
 }
 
-template <bool L1>
+// KINDS: the one model kind of a single-model call (a smaller kernel with
+// fewer live registers), or 0 for any mix of models.
+template <int KINDS, bool L1>
 __global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -620,10 +622,12 @@ __global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
     wave_lds_sync();
     const uint32_t ntiles = (P.n_draws + kTile - 1) / kTile;
     for (int m = 0; m < P.M; ++m) {
-        const int kind = P.md[m].kind;
+        const int kind = KINDS != 0 ? KINDS : P.md[m].kind;
         for (uint32_t t = (uint32_t)wave; t < ntiles; t += (uint32_t)P.wpv) {
             uint64_t key[kU];
-            if (kind == KIND_IRR)
+            if constexpr (KINDS != 0)
+                tile_keys<KINDS, kU, L1>(P, m, vg, t * kTile, yw, key);
+            else if (kind == KIND_IRR)
                 tile_keys<KIND_IRR, kU, L1>(P, m, vg, t * kTile, yw, key);
             else if (kind == KIND_REV)
                 tile_keys<KIND_REV, kU, L1>(P, m, vg, t * kTile, yw, key);
@@ -1074,10 +1078,18 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
         Q.out_idx = o.out_accept_idx ? o.out_accept_idx + (size_t)base * n_acc : nullptr;
         Q.out_dist = o.out_accept_dist ? o.out_accept_dist + (size_t)base * n_acc : nullptr;
         Q.out_thr = o.out_threshold ? o.out_threshold + base : nullptr;
-        if (o.distance == 1)
-            hipLaunchKernelGGL(vpet_infer_kernel<true>, dim3((unsigned)Q.V), dim3(kWave * wpv), lds, st, Q);
-        else
-            hipLaunchKernelGGL(vpet_infer_kernel<false>, dim3((unsigned)Q.V), dim3(kWave * wpv), lds, st, Q);
+        const dim3 grid((unsigned)Q.V), block(kWave * wpv);
+        const int sel = (M == 1 ? kinds[0] : 0) * 2 + (o.distance == 1 ? 1 : 0);
+        switch (sel) {
+            case 2 * KIND_IRR: hipLaunchKernelGGL((vpet_infer_kernel<KIND_IRR, false>), grid, block, lds, st, Q); break;
+            case 2 * KIND_IRR + 1: hipLaunchKernelGGL((vpet_infer_kernel<KIND_IRR, true>), grid, block, lds, st, Q); break;
+            case 2 * KIND_REV: hipLaunchKernelGGL((vpet_infer_kernel<KIND_REV, false>), grid, block, lds, st, Q); break;
+            case 2 * KIND_REV + 1: hipLaunchKernelGGL((vpet_infer_kernel<KIND_REV, true>), grid, block, lds, st, Q); break;
+            case 2 * KIND_1TCM: hipLaunchKernelGGL((vpet_infer_kernel<KIND_1TCM, false>), grid, block, lds, st, Q); break;
+            case 2 * KIND_1TCM + 1: hipLaunchKernelGGL((vpet_infer_kernel<KIND_1TCM, true>), grid, block, lds, st, Q); break;
+            case 1: hipLaunchKernelGGL((vpet_infer_kernel<0, true>), grid, block, lds, st, Q); break;
+            default: hipLaunchKernelGGL((vpet_infer_kernel<0, false>), grid, block, lds, st, Q); break;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "infer launch");
     }
