@@ -77,6 +77,8 @@ typedef enum {
 #define VPET_MAX_ACCEPT 3968
 #define VPET_MAX_NODES 16385
 #define VPET_MAX_FRAMES 1024
+#define VPET_BANK_MAX_FRAMES 32
+#define VPET_BANK_MAX_ACCEPT 512
 
 typedef struct {
     float dt;         /* grid step (min), > 0                         */
@@ -109,6 +111,9 @@ typedef struct {
     int64_t voxel_offset;
     /* Waves cooperating on one voxel (1, 2 or 4); 0 = chosen from V. */
     int32_t waves_per_voxel;
+    /* Shared-bank form only: bank rows in the pilot that sets each voxel's
+     * candidate threshold; 0 = ceil(4 N / n), so that about 4 n rows pass. */
+    int64_t bank_pilot;
 } vpet_abc_opts;
 
 /*
@@ -181,6 +186,46 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
 int vpet_abc_draws(uint32_t model_id, const double* prior_box, uint64_t seed,
                    const int64_t* voxel, const int64_t* draw, const int32_t* model_pos,
                    int64_t count, uint32_t* out_words, float* out_theta, void* hip_stream);
+
+/*
+ * Shared-bank form (Alg. 1 as printed: lines 1-3 are done once and the bank
+ * of draws and curves serves every voxel).  Bank draw i of list position m is
+ * the Philox draw of counter (i, 0, 1, m << 16 | blk) -- stream 1, no voxel
+ * index -- so a bank is a function of (model_id, prior_box, n_draws, seed,
+ * grid) only and may be reused across calls and voxel chunks.
+ *
+ * vpet_abc_bank_ld(F): row stride (frames rounded up to a multiple of 8) of the
+ * bank curves.  Host-only; 0 for F <= 0.
+ *
+ * vpet_abc_bank_build writes
+ *   out_theta  device [M * n_draws][VPET_PSTRIDE] fp32 (unused slots NaN)
+ *   out_x      device [M * n_draws][vpet_abc_bank_ld(F)] FP64 frame averages
+ *              (the same forward model as vpet_abc_simulate; padding 0)
+ * Errors: as vpet_abc_infer; VPET_E_LIMIT if F > VPET_BANK_MAX_FRAMES.
+ */
+int vpet_abc_bank_ld(int32_t n_frames);
+int vpet_abc_bank_build(uint32_t model_id, const double* prior_box, int64_t n_draws, uint64_t seed,
+                        const float* input_fn, const float* frame_times, vpet_grid grid, float* out_theta,
+                        double* out_x, void* hip_stream);
+
+/*
+ * Fixed-budget rejection ABC of every voxel against one bank (Alg. 1, lines
+ * 4-5, and the summaries of vpet_abc_infer).  model_id and n_draws describe
+ * the bank (bank_theta, bank_x as written by vpet_abc_bank_build on the same
+ * grid); frame_times and grid give the frames (the input function is not
+ * needed).  Distances are FP64; the accepted set is the n smallest keys
+ * (fp32(d), g), n = floor(M n_draws p + 1e-6) <= VPET_BANK_MAX_ACCEPT.
+ * opts: weights, weight_floor_frac, decay_lambda, distance, the debug outputs
+ * and bank_pilot are honoured; voxel_offset and waves_per_voxel do not apply.
+ * Device scratch (about 8 n keys per voxel, in chunks of at most 2 GiB) is
+ * allocated and freed in stream order.
+ * Errors: VPET_E_ARG, VPET_E_MODEL, VPET_E_GRID, VPET_E_LIMIT, VPET_E_NOMEM,
+ * VPET_E_HIP.
+ */
+int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_times, vpet_grid grid,
+                        uint32_t model_id, int64_t n_draws, double accept_frac, const float* bank_theta,
+                        const double* bank_x, float* out_moments, float* out_model_prob,
+                        const vpet_abc_opts* opts, void* hip_stream);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* vpet_abc_last_error(void);

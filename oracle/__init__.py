@@ -70,6 +70,10 @@ def lib():
         L.ora_infer.restype = i64
         L.ora_voxel_distances.argtypes = [P, i32, P, i32, f64, P, P, i32, P, i64, u64, i64, f64, f64,
                                           i32, P, P]
+        L.ora_bank.argtypes = [P, i32, P, i64, u64, P, i32, f64, P, i32, P, P]
+        L.ora_infer_bank.argtypes = [P, i64, i32, P, i32, f64, P, P, i32, P, i64, f64, u64, f64, f64, i32, P, i32,
+                                     P, P, P, P, P]
+        L.ora_infer_bank.restype = i64
         _lib = L
     return _lib
 
@@ -232,3 +236,54 @@ def voxel_distances(y_v, frame_times, input_fn, dt, models, boxes, n_draws, seed
                               _p(mo), M, _p(bx), int(n_draws), int(seed), int(v_global), float(lam),
                               float(floor), int(bool(l1)), None if w is None else _p(w), _p(out))
     return out
+
+
+# --------------------------------------------------------------------------
+# Shared-bank form (Alg. 1 as printed): one bank of prior draws and curves
+# for all voxels; bank draw i of list position m uses the Philox counter
+# (i, 0, 1, m << 16 | blk).
+# --------------------------------------------------------------------------
+def bank(models, boxes, n_draws, seed, input_fn, dt, frame_times):
+    """Bank parameters [M*n_draws][8] (fp32) and frame-averaged curves [M*n_draws][F] (FP64)."""
+    mo = _c(models, np.uint32)
+    M = mo.shape[0]
+    bx = _c(boxes, np.float64).reshape(M, NSLOT, 2)
+    cp = _c(input_fn, np.float32)
+    kf = frame_nodes(frame_times, dt, cp.shape[0])
+    F = kf.shape[0] - 1
+    n_tot = M * int(n_draws)
+    th = np.empty((n_tot, NSLOT), dtype=np.float32)
+    x = np.empty((n_tot, F), dtype=np.float64)
+    L = lib()
+    L.ora_bank(_p(mo), M, _p(bx), int(n_draws), int(seed), _p(cp), cp.shape[0] - 1, float(np.float32(dt)), _p(kf), F,
+               _p(th), _p(x))
+    return th, x
+
+
+def infer_bank(tacs, frame_times, input_fn, dt, models, boxes, n_draws, accept_frac, seed, lam=DEFAULT_LAMBDA,
+               floor=DEFAULT_FLOOR, l1=False, weights=None, nthreads=0) -> dict:
+    y = _c(tacs, np.float32)
+    V, F = y.shape
+    cp = _c(input_fn, np.float32)
+    kf = frame_nodes(frame_times, dt, cp.shape[0])
+    if kf.shape[0] - 1 != F:
+        raise ValueError("tacs and frame_times disagree on the frame count")
+    mo = _c(models, np.uint32)
+    M = mo.shape[0]
+    bx = _c(boxes, np.float64).reshape(M, NSLOT, 2)
+    n = accept_count(M * int(n_draws), accept_frac)
+    if n == 0:
+        raise ValueError("accept count n = floor(N p) must be >= 1")
+    acc_g = np.empty((V, n), dtype=np.int32)
+    acc_d = np.empty((V, n), dtype=np.float64)
+    thr = np.empty((V, 2), dtype=np.float64)
+    mom = np.empty((V, M, NSLOT, 2), dtype=np.float64)
+    pr = np.empty((V, M), dtype=np.float64)
+    w = None if weights is None else _c(weights, np.float32)
+    got = lib().ora_infer_bank(_p(y), V, F, _p(cp), cp.shape[0] - 1, float(np.float32(dt)), _p(kf), _p(mo), M, _p(bx),
+                               int(n_draws), float(accept_frac), int(seed), float(lam), float(floor), int(bool(l1)),
+                               None if w is None else _p(w), int(nthreads), _p(acc_g), _p(acc_d), _p(thr), _p(mom),
+                               _p(pr))
+    assert got == n
+    return {"n": n, "accept_idx": acc_g, "accept_dist": acc_d, "threshold": thr[:, 0], "next_dist": thr[:, 1],
+            "moments": mom, "model_prob": pr}

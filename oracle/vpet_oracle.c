@@ -350,6 +350,68 @@ static int cand_cmp(const void* pa, const void* pb) {
     return (a->g < b->g) ? -1 : (a->g > b->g);
 }
 
+/* Posterior summaries of the accepted draws cand[0..n) (Eq. (6): model
+ * probability = share of accepted draws; Sec. II-D3: posterior mean; Ki per
+ * accepted sample, Sec. III-B2).  theta_tab, if not NULL, holds the fp32
+ * parameters of every global draw index ([n_tot][8], the shared-bank form);
+ * otherwise each accepted draw is regenerated from its Philox counter
+ * (voxel vg, stream). */
+static void summarize(const ora_cand* cand, int64_t n, int M, const uint32_t* models, const double* boxes,
+                      int64_t n_draws, uint64_t seed, uint64_t vg, uint32_t stream, const float* theta_tab,
+                      double* mom, double* pr) {
+    float thf[8];
+    for (int m = 0; m < M; ++m) {
+        int slots[8];
+        int np = model_params(models[m], slots);
+        int use[8] = {0};
+        for (int j = 0; j < np; ++j) use[slots[j]] = 1;
+        if (models[m] != ORA_M_1TCM) use[SLOT_KI] = 1;
+        double sum[8] = {0}, sq[8] = {0};
+        int64_t cnt = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int64_t j = 0; j < n; ++j) {
+                int64_t g = cand[j].g;
+                if (g / n_draws != m) continue;
+                int64_t i = g % n_draws;
+                if (theta_tab)
+                    memcpy(thf, theta_tab + 8 * g, sizeof thf);
+                else
+                    ora_draw(models[m], boxes + (size_t)m * 16, seed, vg, (uint64_t)i, (uint32_t)m, stream, thf,
+                             NULL, NULL);
+                double val[8];
+                for (int s = 0; s < 8; ++s) val[s] = (double)thf[s];
+                if (use[SLOT_KI]) {
+                    double K1 = val[SLOT_K1], k2 = val[SLOT_K2], k3 = val[SLOT_K3];
+                    val[SLOT_KI] = K1 * k3 / (k2 + k3);
+                }
+                if (pass == 0) {
+                    ++cnt;
+                    for (int s = 0; s < 8; ++s)
+                        if (use[s]) sum[s] += val[s];
+                } else {
+                    for (int s = 0; s < 8; ++s)
+                        if (use[s]) {
+                            double dv = val[s] - sum[s];
+                            sq[s] += dv * dv;
+                        }
+                }
+            }
+            if (pass == 0 && cnt > 0)
+                for (int s = 0; s < 8; ++s) sum[s] /= (double)cnt;
+        }
+        pr[m] = (double)cnt / (double)n;
+        for (int s = 0; s < 8; ++s) {
+            double mean = NAN, var = NAN;
+            if (use[s] && cnt > 0) {
+                mean = sum[s];
+                var = (cnt > 1) ? sq[s] / (double)(cnt - 1) : 0.0;
+            }
+            mom[(size_t)m * 16 + 2 * s] = mean;
+            mom[(size_t)m * 16 + 2 * s + 1] = var;
+        }
+    }
+}
+
 /* n = floor(N_tot * p) (remark after Alg. 1) with a 1e-6 guard against the
  * product landing just below an integer. Returns 0 if invalid. */
 int64_t ora_accept_count(int64_t n_tot, double p) {
@@ -438,55 +500,7 @@ int64_t ora_infer(const float* y, int64_t V, int F, const float* cp_f32, int K, 
         thr[2 * v] = cand[n - 1].d;
         thr[2 * v + 1] = (n < n_tot) ? cand[n].d : INFINITY;
 
-        /* Posterior summaries per model (Eq. (6): model probability = share of
-         * accepted draws; Sec. II-D3: posterior mean; Ki per accepted sample). */
-        for (int m = 0; m < M; ++m) {
-            int slots[8];
-            int np = model_params(models[m], slots);
-            int use[8] = {0};
-            for (int j = 0; j < np; ++j) use[slots[j]] = 1;
-            if (models[m] != ORA_M_1TCM) use[SLOT_KI] = 1;
-            double sum[8] = {0}, sq[8] = {0};
-            int64_t cnt = 0;
-            for (int pass = 0; pass < 2; ++pass) {
-                for (int64_t j = 0; j < n; ++j) {
-                    int64_t g = cand[j].g;
-                    if (g / n_draws != m) continue;
-                    int64_t i = g % n_draws;
-                    ora_draw(models[m], boxes + (size_t)m * 16, seed, vg, (uint64_t)i, (uint32_t)m,
-                             0u, thf, NULL, NULL);
-                    double val[8];
-                    for (int s = 0; s < 8; ++s) val[s] = (double)thf[s];
-                    if (use[SLOT_KI]) {
-                        double K1 = val[SLOT_K1], k2 = val[SLOT_K2], k3 = val[SLOT_K3];
-                        val[SLOT_KI] = K1 * k3 / (k2 + k3);
-                    }
-                    if (pass == 0) {
-                        ++cnt;
-                        for (int s = 0; s < 8; ++s)
-                            if (use[s]) sum[s] += val[s];
-                    } else {
-                        for (int s = 0; s < 8; ++s)
-                            if (use[s]) {
-                                double dv = val[s] - sum[s];
-                                sq[s] += dv * dv;
-                            }
-                    }
-                }
-                if (pass == 0 && cnt > 0)
-                    for (int s = 0; s < 8; ++s) sum[s] /= (double)cnt;
-            }
-            pr[m] = (double)cnt / (double)n;
-            for (int s = 0; s < 8; ++s) {
-                double mean = NAN, var = NAN;
-                if (use[s] && cnt > 0) {
-                    mean = sum[s];
-                    var = (cnt > 1) ? sq[s] / (double)(cnt - 1) : 0.0;
-                }
-                mom[(size_t)m * 16 + 2 * s] = mean;
-                mom[(size_t)m * 16 + 2 * s + 1] = var;
-            }
-        }
+        summarize(cand, n, M, models, boxes, n_draws, seed, vg, 0u, NULL, mom, pr);
         free(cand);
         free(nodes);
         free(x);
@@ -528,4 +542,89 @@ void ora_voxel_distances(const float* yv, int F, const float* cp_f32, int K, dou
     free(x);
     free(w);
     free(cp);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Shared-bank form (Alg. 1 as printed): one set of N_tot prior draws and     */
+/* their simulated curves serves every voxel (Alg. 1, lines 1-3 are done      */
+/* once; line 4 is a voxels x draws matrix; line 5 selects per voxel).        */
+/* Bank draw i of list position m uses the Philox counter (i, 0, 1, m<<16|blk)*/
+/* (stream 1; no voxel index).                                               */
+/* ------------------------------------------------------------------------- */
+void ora_bank(const uint32_t* models, int M, const double* boxes, int64_t n_draws, uint64_t seed,
+              const float* cp_f32, int K, double h, const int32_t* kf, int F, float* theta_out, double* x_out) {
+    double* cp = (double*)malloc(sizeof(double) * (size_t)(K + 1));
+    double* nodes = (double*)malloc(sizeof(double) * (size_t)(K + 1));
+    for (int k = 0; k <= K; ++k) cp[k] = (double)cp_f32[k];
+    for (int m = 0; m < M; ++m)
+        for (int64_t i = 0; i < n_draws; ++i) {
+            int64_t g = (int64_t)m * n_draws + i;
+            float* thf = theta_out + 8 * g;
+            double th[8];
+            ora_draw(models[m], boxes + (size_t)m * 16, seed, 0u, (uint64_t)i, (uint32_t)m, 1u, thf, NULL, NULL);
+            for (int s = 0; s < 8; ++s) th[s] = (double)thf[s];
+            ora_simulate_nodes(models[m], th, cp, K, h, nodes);
+            ora_frame_average(nodes, kf, F, x_out + (size_t)F * g);
+        }
+    free(nodes);
+    free(cp);
+}
+
+int64_t ora_infer_bank(const float* y, int64_t V, int F, const float* cp_f32, int K, double h,
+                       const int32_t* kf, const uint32_t* models, int M, const double* boxes, int64_t n_draws,
+                       double p, uint64_t seed, double lambda, double floor_frac, int l1,
+                       const float* weights_in, int nthreads, int32_t* acc_g, double* acc_d, double* thr,
+                       double* moments, double* probs) {
+    int64_t n_tot = (int64_t)M * n_draws;
+    int64_t n = ora_accept_count(n_tot, p);
+    if (n == 0) return 0;
+    float* theta = (float*)malloc(sizeof(float) * 8 * (size_t)n_tot);
+    double* xb = (double*)malloc(sizeof(double) * (size_t)F * (size_t)n_tot);
+    ora_bank(models, M, boxes, n_draws, seed, cp_f32, K, h, kf, F, theta, xb);
+    (void)nthreads;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t v = 0; v < V; ++v) {
+        const float* yv = y + (size_t)F * v;
+        double* mom = moments + (size_t)v * M * 16;
+        double* pr = probs + (size_t)v * M;
+        if (!voxel_valid(yv, F)) {
+            for (int j = 0; j < M * 16; ++j) mom[j] = NAN;
+            for (int m = 0; m < M; ++m) pr[m] = NAN;
+            for (int64_t j = 0; j < n; ++j) {
+                acc_g[(size_t)v * n + j] = -1;
+                acc_d[(size_t)v * n + j] = NAN;
+            }
+            thr[2 * v] = NAN;
+            thr[2 * v + 1] = NAN;
+            continue;
+        }
+        double* w = (double*)malloc(sizeof(double) * (size_t)F);
+        ora_cand* cand = (ora_cand*)malloc(sizeof(ora_cand) * (size_t)n_tot);
+        if (weights_in) {
+            for (int f = 0; f < F; ++f) w[f] = (double)weights_in[(size_t)F * v + f];
+        } else {
+            ora_weights(yv, kf, F, h, lambda, floor_frac, w);
+        }
+        for (int64_t g = 0; g < n_tot; ++g) {
+            double d = distance(yv, xb + (size_t)F * g, w, F, l1);
+            cand[g].d = isnan(d) ? INFINITY : d;
+            cand[g].g = (uint32_t)g;
+        }
+        qsort(cand, (size_t)n_tot, sizeof(ora_cand), cand_cmp);
+        for (int64_t j = 0; j < n; ++j) {
+            acc_g[(size_t)v * n + j] = (int32_t)cand[j].g;
+            acc_d[(size_t)v * n + j] = cand[j].d;
+        }
+        thr[2 * v] = cand[n - 1].d;
+        thr[2 * v + 1] = (n < n_tot) ? cand[n].d : INFINITY;
+        summarize(cand, n, M, models, boxes, n_draws, seed, 0u, 1u, theta, mom, pr);
+        free(cand);
+        free(w);
+    }
+    free(xb);
+    free(theta);
+    return n;
 }

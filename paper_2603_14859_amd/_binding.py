@@ -22,7 +22,10 @@ PSTRIDE = 8
 MAX_ACCEPT = 3968
 
 EXPORTED = ("vpet_abc_accept_count", "vpet_abc_simulate", "vpet_abc_infer", "vpet_abc_draws",
+            "vpet_abc_bank_ld", "vpet_abc_bank_build", "vpet_abc_infer_bank",
             "vpet_abc_last_error", "vpet_abc_version")
+BANK_MAX_ACCEPT = 512
+BANK_MAX_FRAMES = 32
 
 
 class VpetError(RuntimeError):
@@ -40,7 +43,7 @@ class Opts(ctypes.Structure):
                 ("weight_floor_frac", ctypes.c_float), ("distance", ctypes.c_int32),
                 ("out_accept_idx", ctypes.c_void_p), ("out_accept_dist", ctypes.c_void_p),
                 ("out_threshold", ctypes.c_void_p), ("voxel_offset", ctypes.c_int64),
-                ("waves_per_voxel", ctypes.c_int32)]
+                ("waves_per_voxel", ctypes.c_int32), ("bank_pilot", ctypes.c_int64)]
 
 
 def _load():
@@ -52,9 +55,13 @@ def _load():
     L.vpet_abc_simulate.argtypes = [u32, P, i64, P, P, Grid, P, P]
     L.vpet_abc_infer.argtypes = [P, i64, P, P, Grid, u32, P, i64, f64, u64, P, P, ctypes.POINTER(Opts), P]
     L.vpet_abc_draws.argtypes = [u32, P, u64, P, P, P, i64, P, P, P]
+    L.vpet_abc_bank_ld.argtypes = [ctypes.c_int32]
+    L.vpet_abc_bank_ld.restype = ctypes.c_int
+    L.vpet_abc_bank_build.argtypes = [u32, P, i64, u64, P, P, Grid, P, P, P]
+    L.vpet_abc_infer_bank.argtypes = [P, i64, P, Grid, u32, i64, f64, P, P, P, P, ctypes.POINTER(Opts), P]
     L.vpet_abc_last_error.restype = ctypes.c_char_p
     L.vpet_abc_version.restype = ctypes.c_int
-    for name in EXPORTED[:4]:
+    for name in EXPORTED[:4] + EXPORTED[5:7]:
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -189,6 +196,68 @@ def draws(models, prior_box, seed: int, voxel, draw, model_pos, stream=None):
                               _ptr(voxel), _ptr(draw), _ptr(model_pos), count, _ptr(words), _ptr(theta),
                               _stream(stream)))
     return words, theta
+
+
+def bank_build(models, prior_box, n_draws: int, seed: int, input_fn, frame_times, dt: float, device="cuda",
+               stream=None):
+    """Shared bank: parameters [M*n_draws][8] (fp32) and FP64 frame averages [M*n_draws][ld] (device)."""
+    import torch
+    mask = model_mask(models)
+    M = len(models)
+    box = _host(prior_box, np.float64).reshape(M, PSTRIDE, 2)
+    cp = _host(input_fn, np.float32)
+    ft = _host(frame_times, np.float32)
+    F = ft.size - 1
+    ld = int(lib.vpet_abc_bank_ld(F))
+    n_tot = M * int(n_draws)
+    theta = torch.empty((n_tot, PSTRIDE), dtype=torch.float32, device=device)
+    x = torch.empty((n_tot, max(ld, 1)), dtype=torch.float64, device=device)
+    _check(lib.vpet_abc_bank_build(mask, box.ctypes.data_as(ctypes.c_void_p), int(n_draws), int(seed) & ((1 << 64) - 1),
+                                   cp.ctypes.data_as(ctypes.c_void_p), ft.ctypes.data_as(ctypes.c_void_p),
+                                   Grid(float(dt), cp.size, F), _ptr(theta), _ptr(x), _stream(stream)))
+    return theta, x
+
+
+def infer_bank(tacs, frame_times, dt: float, n_nodes: int, models, n_draws: int, accept_frac: float, bank_theta,
+               bank_x, *, weights=None, weight_floor=0.0, decay_lambda=0.0, distance="l2", debug=False,
+               bank_pilot=0, out=None, stream=None) -> dict:
+    """Rejection ABC of every voxel against one shared bank (see bank_build)."""
+    import torch
+    tacs = _dev_f32(tacs, "tacs")
+    V, F = tacs.shape
+    mask = model_mask(models)
+    M = len(models)
+    ft = _host(frame_times, np.float32)
+    if ft.size != F + 1:
+        raise ValueError("frame_times must have F + 1 entries")
+    if not (bank_x.dtype == torch.float64 and bank_theta.dtype == torch.float32):
+        raise TypeError("bank_x must be float64 and bank_theta float32 (from bank_build)")
+    n = accept_count(M * int(n_draws), accept_frac)
+    dev = tacs.device
+    res = out if out is not None else {
+        "moments": torch.empty((V, M, PSTRIDE, 2), dtype=torch.float32, device=dev),
+        "model_prob": torch.empty((V, M), dtype=torch.float32, device=dev)}
+    if debug and "accept_idx" not in res:
+        res["accept_idx"] = torch.empty((V, n), dtype=torch.int32, device=dev)
+        res["accept_dist"] = torch.empty((V, n), dtype=torch.float32, device=dev)
+        res["threshold"] = torch.empty((V,), dtype=torch.float32, device=dev)
+    o = Opts()
+    o.decay_lambda = float(decay_lambda)
+    if weights is not None:
+        weights = _dev_f32(weights, "weights")
+        o.weights = weights.data_ptr()
+    o.weight_floor_frac = float(weight_floor)
+    o.distance = {"l2": 0, "l1": 1}[distance]
+    if debug:
+        o.out_accept_idx = res["accept_idx"].data_ptr()
+        o.out_accept_dist = res["accept_dist"].data_ptr()
+        o.out_threshold = res["threshold"].data_ptr()
+    o.bank_pilot = int(bank_pilot)
+    _check(lib.vpet_abc_infer_bank(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p), Grid(float(dt), int(n_nodes), F),
+                                   mask, int(n_draws), float(accept_frac), _ptr(bank_theta), _ptr(bank_x),
+                                   _ptr(res["moments"]), _ptr(res["model_prob"]), ctypes.byref(o), _stream(stream)))
+    res["n"] = n
+    return res
 
 
 def version() -> int:

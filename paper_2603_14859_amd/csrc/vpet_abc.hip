@@ -51,8 +51,17 @@ typedef const __attribute__((address_space(4))) double* cdp;
 typedef const __attribute__((address_space(4))) int* cip;
 
 constexpr int kWave = 64;
-constexpr int kU = 2;                 // draws per lane per tile (ILP)
-constexpr int kTile = kWave * kU;     // draws per wavefront tile
+// Draws per lane per tile (independent FMA chains): 4 for the one-exponential
+// models, 2 where two exponentials double the per-draw state.
+#ifndef VPET_DRAWS_PER_LANE
+#define VPET_DRAWS_PER_LANE 4
+#endif
+#ifndef VPET_STEP_UNROLL
+#define VPET_STEP_UNROLL 4
+#endif
+constexpr int kUmax = VPET_DRAWS_PER_LANE;
+template <int KINDS>
+constexpr int draws_per_lane() { return (KINDS == 1 || KINDS == 2) ? kUmax : 2; }
 constexpr double kCmin = 1e-5;        // 1 - z below which frame sums are accumulated
 constexpr int kMaxModels = 3;
 constexpr int kMaxWpv = 4;
@@ -122,11 +131,11 @@ __device__ __forceinline__ float unit24(uint32_t w) { return (float)(w >> 8) * 0
 // Parameters of draw i of list position m for voxel v, in the model's order.
 __device__ __forceinline__ void draw_params(const ModelDev& md, uint32_t key0, uint32_t key1,
                                             uint32_t v, uint32_t i, uint32_t m, float th[5],
-                                            uint32_t* words = nullptr) {
+                                            uint32_t* words = nullptr, uint32_t stream = 0u) {
     uint32_t w[8];
-    philox10(i, v, 0u, m << 16, key0, key1, w);
+    philox10(i, v, stream, m << 16, key0, key1, w);
     if (md.np > 4) {
-        philox10(i, v, 0u, (m << 16) | 1u, key0, key1, w + 4);
+        philox10(i, v, stream, (m << 16) | 1u, key0, key1, w + 4);
     } else {
         w[4] = w[5] = w[6] = w[7] = 0u;
     }
@@ -289,6 +298,7 @@ __device__ __forceinline__ void run_frames(const Tab& T, int F, int k0, DrawStat
         const int n = NF[f];
         const cdp Cp = C + k;
         int q = 0;
+#if VPET_STEP_UNROLL == 4
         for (; q + 4 <= n; q += 4) {
             const double c0 = Cp[q], c1 = Cp[q + 1], c2 = Cp[q + 2], c3 = Cp[q + 3];
             VPET_STEP(c0);
@@ -296,6 +306,8 @@ __device__ __forceinline__ void run_frames(const Tab& T, int F, int k0, DrawStat
             VPET_STEP(c2);
             VPET_STEP(c3);
         }
+#endif
+#pragma nounroll
         for (; q < n; ++q) VPET_STEP(Cp[q]);
         k += n;
         const double SS = FR[4 * f], PP = FR[4 * f + 1], R = FR[4 * f + 2];
@@ -421,21 +433,22 @@ struct TopN {
         nbuf = 0;
     }
 
+    // One column of 64 keys at a time, so the buffer (cap - n >= 128 keys)
+    // always has room for a column after a merge.
     template <int U>
     __device__ void insert(const uint64_t (&key)[U]) {
-        int cnt = 0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) cnt += __popcll(__ballot(key[u] < tau));
-        if (cnt == 0) return;
-        if (nbuf + cnt > cap - n) merge();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool p = key[u] < tau;
-            const uint64_t b = __ballot(p);
-            if (p) keys[n + nbuf + (int)mbcnt(b)] = key[u];
+            uint64_t b = __ballot(key[u] < tau);
+            if (b == 0ull) continue;
+            if (nbuf + __popcll(b) > cap - n) {
+                merge();
+                b = __ballot(key[u] < tau);
+            }
+            if (key[u] < tau) keys[n + nbuf + (int)mbcnt(b)] = key[u];
             nbuf += __popcll(b);
+            wave_lds_sync();
         }
-        wave_lds_sync();
     }
 };
 
@@ -620,6 +633,8 @@ __global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
     top.tau = kNoKey;
     for (int j = lane; j < P.cap; j += kWave) top.keys[j] = kNoKey;
     wave_lds_sync();
+    constexpr int kU = draws_per_lane<KINDS>();
+    constexpr int kTile = kWave * kU;
     const uint32_t ntiles = (P.n_draws + kTile - 1) / kTile;
     for (int m = 0; m < P.M; ++m) {
         const int kind = KINDS != 0 ? KINDS : P.md[m].kind;
@@ -741,6 +756,303 @@ __global__ __launch_bounds__(256) void vpet_draws_kernel(ModelDev md0, ModelDev 
     draw_params(md, key0, key1, (uint32_t)voxel[j], (uint32_t)draw[j], (uint32_t)m, th, words);
     for (int q = 0; q < 8; ++q) w_out[q] = words[q];
     for (int q = 0; q < md.np; ++q) th_out[md.slot[q]] = th[q];
+}
+
+// ===========================================================================
+// Shared-bank form (Alg. 1 as printed): one bank of draws and curves for all
+// voxels.  Bank draw i of list position m uses the Philox counter
+// (i, 0, 1, m << 16 | blk): stream 1, no voxel index.
+// ===========================================================================
+constexpr int kBankTopK = 16;  // pilot: each voxel's 16th smallest distance over a bank prefix
+
+struct BankSink {
+    double* row;  // bank row of this draw, or nullptr for a padding lane
+    __device__ __forceinline__ void operator()(int f, int n, const double (&X)[1]) {
+        if (row) row[f] = X[0] / (double)n;
+    }
+};
+
+// One thread per bank draw of one model: parameters and frame averages.
+template <int KIND>
+__global__ __launch_bounds__(256) void vpet_bank_kernel(ModelDev md, int m, unsigned n_draws, unsigned key0,
+                                                        unsigned key1, Tab T, double C0, double h, int F, int k0,
+                                                        int ld, float* theta_out, double* x_out) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = i < n_draws;
+    const unsigned ii = ok ? i : n_draws - 1;
+    const size_t g = (size_t)m * n_draws + ii;
+    float th[5];
+    draw_params(md, key0, key1, 0u, ii, (uint32_t)m, th, nullptr, 1u);
+    if (ok) {
+        float* to = theta_out + g * VPET_PSTRIDE;
+        for (int q = 0; q < VPET_PSTRIDE; ++q) to[q] = __builtin_nanf("");
+        for (int q = 0; q < md.np; ++q) to[md.slot[q]] = th[q];
+        double* row = x_out + g * (size_t)ld;
+        for (int f = F; f < ld; ++f) row[f] = 0.0;  // padding frames contribute nothing
+    }
+    constexpr int NE = ModelTraits<KIND>::NE;
+    DrawState<NE, 1> s;
+    setup<KIND, NE, 1>(th, h, C0, s, 0);
+    BankSink sink{ok ? x_out + g * (size_t)ld : nullptr};
+    simulate_draws<KIND, 1>(T, F, k0, s, sink);
+}
+
+struct BankArgs {
+    const float* tacs;
+    const float* weights;
+    const double* omega;    // per frame: dt_f exp(-lambda tmid_f)
+    const double* bank_x;   // [N][ld] frame averages (zero padding)
+    const float* bank_theta;
+    double floor_frac;
+    int F, ld, l1, M, cap;
+    long long V;            // voxels in this launch
+    unsigned n_tot, n_draws, n_acc, n_pilot;
+    int kinds[kMaxModels];
+    float* tau;             // [V] pilot threshold (fp32 distance), NaN for an invalid voxel
+    int* cnt;               // [V] candidates found (may exceed cap)
+    uint64_t* cand;         // [V][cap] candidate keys
+    int* fallback;          // [V] 1 if the candidate set cannot certify the top n
+    float* out_mom;
+    float* out_prob;
+    int* out_idx;
+    float* out_dist;
+    float* out_thr;
+};
+
+// Per-lane observed curve and weights of voxel `row` (a lane per voxel).
+template <int LD, bool L1>
+__device__ __forceinline__ bool lane_curve(const BankArgs& P, long long row, double (&Y)[LD], double (&Wt)[LD]) {
+    const float* y = P.tacs + (size_t)row * P.F;
+    float ymax = -__builtin_inff();
+    bool bad = false;
+#pragma unroll
+    for (int f = 0; f < LD; ++f) {
+        const float yy = (f < P.F) ? y[f] : 0.0f;
+        bad = bad || !isfinite(yy);
+        ymax = fmaxf(ymax, (f < P.F) ? yy : -__builtin_inff());
+        Y[f] = (double)yy;
+    }
+    const double den_floor = P.floor_frac * (double)ymax;
+    const cdp OM = (cdp)P.omega;
+#pragma unroll
+    for (int f = 0; f < LD; ++f) {
+        double w = 0.0;
+        if (f < P.F) {
+            if (P.weights)
+                w = (double)P.weights[(size_t)row * P.F + f];
+            else
+                w = OM[f] / (Y[f] > den_floor ? Y[f] : den_floor);
+            if (L1) w = sqrt(w);
+        }
+        Wt[f] = w;
+    }
+    return !bad && ymax > 0.0f;
+}
+
+// Distance of one bank row to the lane's voxel; the row is wave-uniform, so
+// its values are scalar operands.
+template <int LD, bool L1>
+__device__ __forceinline__ double bank_distance(cdp xr, const double (&Y)[LD], const double (&Wt)[LD]) {
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int f = 0; f < LD; f += 2) {
+        const double r0 = Y[f] - xr[f];
+        const double r1 = Y[f + 1] - xr[f + 1];
+        if (L1) {
+            d0 = fma(Wt[f], fabs(r0), d0);
+            d1 = fma(Wt[f + 1], fabs(r1), d1);
+        } else {
+            d0 = fma(Wt[f] * r0, r0, d0);
+            d1 = fma(Wt[f + 1] * r1, r1, d1);
+        }
+    }
+    return d0 + d1;
+}
+
+__device__ __forceinline__ float key_dist(double d) {
+    float fd = (float)d;
+    return (fd == fd) ? fd : __builtin_inff();
+}
+
+// PILOT: each lane's 16 smallest distances over the first n_pilot bank rows ->
+// tau.  SCAN: every bank row; rows with fp32 distance <= tau are appended to
+// the voxel's candidate list.
+template <int LD, bool L1, bool PILOT>
+__global__ __launch_bounds__(256) void vpet_bank_scan_kernel(BankArgs P) {
+    const long long row0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = row0 < P.V;
+    const long long row = live ? row0 : P.V - 1;
+    double Y[LD], Wt[LD];
+    const bool valid = lane_curve<LD, L1>(P, row, Y, Wt);
+    const cdp X = (cdp)P.bank_x;
+    if (PILOT) {
+        float top[kBankTopK];
+#pragma unroll
+        for (int q = 0; q < kBankTopK; ++q) top[q] = __builtin_inff();
+        for (unsigned g = 0; g < P.n_pilot; ++g) {
+            const float fd = key_dist(bank_distance<LD, L1>(X + (size_t)g * LD, Y, Wt));
+            if (fd < top[kBankTopK - 1]) {  // insert into the sorted list
+#pragma unroll
+                for (int q = kBankTopK - 1; q > 0; --q)
+                    top[q] = (fd < top[q - 1]) ? top[q - 1] : ((fd < top[q]) ? fd : top[q]);
+                top[0] = fminf(top[0], fd);
+            }
+        }
+        if (live) P.tau[row] = valid ? top[kBankTopK - 1] : __builtin_nanf("");
+    } else {
+        const float tau = P.tau[row];
+        uint64_t* out = P.cand + (size_t)row * P.cap;
+        int c = 0;
+        for (unsigned g = 0; g < P.n_tot; ++g) {
+            const float fd = key_dist(bank_distance<LD, L1>(X + (size_t)g * LD, Y, Wt));
+            if (fd <= tau) {
+                if (c < P.cap) out[c] = ((uint64_t)__float_as_uint(fd) << 32) | g;
+                ++c;
+            }
+        }
+        if (live) P.cnt[row] = valid ? c : -1;
+    }
+}
+
+// Outputs of one voxel from its n accepted keys (sorted, in LDS).
+__device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* acc, double* red) {
+    const int n = (int)P.n_acc;
+    const int tid = threadIdx.x;
+    if (P.out_idx)
+        for (int j = tid; j < n; j += blockDim.x) P.out_idx[(size_t)row * n + j] = (int)(uint32_t)acc[j];
+    if (P.out_dist)
+        for (int j = tid; j < n; j += blockDim.x)
+            P.out_dist[(size_t)row * n + j] = __uint_as_float((uint32_t)(acc[j] >> 32));
+    if (P.out_thr && tid == 0) P.out_thr[row] = __uint_as_float((uint32_t)(acc[n - 1] >> 32));
+    for (int m = 0; m < P.M; ++m) {
+        const int kind = P.kinds[m];
+        double s1[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) s1[q] = 0.0;
+        double val[6];
+        for (int j = tid; j < n; j += blockDim.x) {
+            const uint32_t g = (uint32_t)acc[j];
+            if (g / P.n_draws != (uint32_t)m) continue;
+            const float* t = P.bank_theta + (size_t)g * VPET_PSTRIDE;
+            const float th[5] = {t[0], t[1], kind == KIND_1TCM ? t[4] : t[2], kind == KIND_REV ? t[3] : t[4], t[4]};
+            slot_values(kind, th, val);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) s1[q] += val[q];
+            s1[6] += 1.0;
+        }
+        block_sum<7>(s1, red, blockDim.x >> 6);
+        const double cnt = s1[6];
+        double mean[6], s2[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            mean[q] = s1[q] / cnt;
+            s2[q] = 0.0;
+        }
+        for (int j = tid; j < n; j += blockDim.x) {
+            const uint32_t g = (uint32_t)acc[j];
+            if (g / P.n_draws != (uint32_t)m) continue;
+            const float* t = P.bank_theta + (size_t)g * VPET_PSTRIDE;
+            const float th[5] = {t[0], t[1], kind == KIND_1TCM ? t[4] : t[2], kind == KIND_REV ? t[3] : t[4], t[4]};
+            slot_values(kind, th, val);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const double dv = val[q] - mean[q];
+                s2[q] = fma(dv, dv, s2[q]);
+            }
+        }
+        block_sum<6>(s2, red, blockDim.x >> 6);
+        if (tid < 16) {
+            const int q = tid >> 1;
+            float outv = __builtin_nanf("");
+            if (q < 6 && slot_used(kind, q) && cnt > 0.0) {
+                if ((tid & 1) == 0)
+                    outv = (float)mean[q];
+                else
+                    outv = (cnt > 1.0) ? (float)(s2[q] / (cnt - 1.0)) : 0.0f;
+            }
+            P.out_mom[((size_t)row * P.M + m) * 16 + tid] = outv;
+        }
+        if (tid == 0) P.out_prob[(size_t)row * P.M + m] = (float)(cnt / (double)n);
+    }
+}
+
+__device__ void bank_invalid(const BankArgs& P, long long row) {
+    const int n = (int)P.n_acc;
+    const float qnan = __builtin_nanf("");
+    for (int j = threadIdx.x; j < P.M * 16; j += blockDim.x) P.out_mom[(size_t)row * P.M * 16 + j] = qnan;
+    for (int j = threadIdx.x; j < P.M; j += blockDim.x) P.out_prob[(size_t)row * P.M + j] = qnan;
+    if (P.out_idx)
+        for (int j = threadIdx.x; j < n; j += blockDim.x) P.out_idx[(size_t)row * n + j] = -1;
+    if (P.out_dist)
+        for (int j = threadIdx.x; j < n; j += blockDim.x) P.out_dist[(size_t)row * n + j] = qnan;
+    if (P.out_thr && threadIdx.x == 0) P.out_thr[row] = qnan;
+}
+
+// One wavefront per voxel: sort the candidates, keep the n smallest.  When
+// the candidate count is below n or above the buffer, the voxel is marked
+// for the exact fallback instead.
+__global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
+    double* red = reinterpret_cast<double*>(keys + P.cap);
+    const long long row = blockIdx.x;
+    if (row >= P.V) return;
+    const int c = P.cnt[row];
+    if (c < 0) {
+        if (threadIdx.x == 0) P.fallback[row] = 0;
+        bank_invalid(P, row);
+        return;
+    }
+    if (c < (int)P.n_acc || c > P.cap) {
+        if (threadIdx.x == 0) P.fallback[row] = 1;
+        return;
+    }
+    if (threadIdx.x == 0) P.fallback[row] = 0;
+    const int len = c <= 1 ? 2 : (1 << (32 - __clz(c - 1)));
+    const uint64_t* src = P.cand + (size_t)row * P.cap;
+    for (int j = threadIdx.x; j < len; j += kWave) keys[j] = j < c ? src[j] : kNoKey;
+    wave_lds_sync();
+    wave_bitonic_sort(keys, len);
+    bank_outputs(P, row, keys, red);
+}
+
+// Exact fallback: one wavefront per marked voxel streams every bank row
+// through a running top-n (the per-voxel selection of the infer kernel).
+template <int LD, bool L1>
+__global__ __launch_bounds__(64) void vpet_bank_fallback_kernel(BankArgs P) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const long long row = blockIdx.x;
+    if (row >= P.V || P.fallback[row] == 0) return;
+    uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
+    double* red = reinterpret_cast<double*>(keys + P.cap);
+    double Y[LD], Wt[LD];
+    lane_curve<LD, L1>(P, row, Y, Wt);  // every lane holds the same voxel
+    TopN top;
+    top.keys = keys;
+    top.n = (int)P.n_acc;
+    top.cap = P.cap;
+    top.nbuf = 0;
+    top.tau = kNoKey;
+    for (int j = lane_id(); j < P.cap; j += kWave) keys[j] = kNoKey;
+    wave_lds_sync();
+    const double* X = P.bank_x;
+    for (unsigned g0 = 0; g0 < P.n_tot; g0 += kWave) {
+        const unsigned g = g0 + (unsigned)lane_id();
+        uint64_t key[1] = {kNoKey};
+        if (g < P.n_tot) {
+            const double* xr = X + (size_t)g * LD;
+            double d0 = 0.0;
+#pragma unroll
+            for (int f = 0; f < LD; ++f) {
+                const double r = Y[f] - xr[f];
+                d0 = L1 ? fma(Wt[f], fabs(r), d0) : fma(Wt[f] * r, r, d0);
+            }
+            key[0] = ((uint64_t)__float_as_uint(key_dist(d0)) << 32) | g;
+        }
+        top.insert(key);
+    }
+    top.merge();
+    bank_outputs(P, row, keys, red);
 }
 
 // ===========================================================================
@@ -911,6 +1223,33 @@ int upload_tables(DevCtx& ctx, const HostTab& T, hipStream_t st, Tab& tab, int& 
     return VPET_OK;
 }
 
+// Uploads `bytes` of host data into a slot (same ring and locking rules as
+// upload_tables).
+int upload_blob(DevCtx& ctx, const void* data, size_t bytes, hipStream_t st, const void** dptr, int& slot) {
+    if (!ctx.ready) {
+        Tab t;
+        HostTab T;
+        T.fr.assign(4, 0.0);
+        T.nf.assign(1, 0);
+        int rc = upload_tables(ctx, T, st, t, slot);  // allocates the ring
+        if (rc != VPET_OK) return rc;
+        hipError_t e = hipEventRecord(ctx.ev[slot], st);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    if (bytes > kSlotBytes) return fail(VPET_E_LIMIT, "table of %zu bytes exceeds %zu", bytes, kSlotBytes);
+    slot = ctx.next;
+    ctx.next = (ctx.next + 1) % kSlots;
+    hipError_t e = hipEventSynchronize(ctx.ev[slot]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    char* hs = ctx.hbuf + slot * kSlotBytes;
+    char* ds = ctx.dbuf + slot * kSlotBytes;
+    std::memcpy(hs, data, bytes);
+    e = hipMemcpyAsync(ds, hs, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(table)");
+    *dptr = ds;
+    return VPET_OK;
+}
+
 int current_ctx(DevCtx** out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1027,7 +1366,7 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
     if (!tacs || !out_moments || !out_model_prob)
         return fail(VPET_E_ARG, "tacs, out_moments and out_model_prob must not be NULL");
 
-    const int cap = pow2_at_least((int)n_acc + kTile);
+    const int cap = pow2_at_least((int)n_acc + 2 * kWave);
     int wpv = o.waves_per_voxel;
     if (wpv == 0) {
         wpv = 1;
@@ -1125,6 +1464,190 @@ int vpet_abc_draws(uint32_t model_id, const double* prior_box, uint64_t seed, co
         if (e != hipSuccess) return hip_fail(e, "draws launch");
     }
     return VPET_OK;
+}
+
+
+int vpet_abc_bank_ld(int32_t n_frames) { return n_frames <= 0 ? 0 : ((n_frames + 7) / 8) * 8; }
+
+int vpet_abc_bank_build(uint32_t model_id, const double* prior_box, int64_t n_draws, uint64_t seed,
+                        const float* input_fn, const float* frame_times, vpet_grid grid, float* out_theta,
+                        double* out_x, void* hip_stream) {
+    int kinds[kMaxModels];
+    const int M = model_list(model_id, kinds);
+    if (M < 1) return fail(VPET_E_MODEL, "unknown or empty model bitmask 0x%x", model_id);
+    if (!prior_box) return fail(VPET_E_ARG, "prior_box must not be NULL");
+    if (n_draws < 1) return fail(VPET_E_ARG, "n_draws must be >= 1");
+    if ((double)M * (double)n_draws > 4294967295.0) return fail(VPET_E_LIMIT, "M * n_draws must stay below 2^32");
+    ModelDev md[kMaxModels] = {};
+    int rc;
+    for (int m = 0; m < M; ++m)
+        if ((rc = fill_model(kinds[m], prior_box + (size_t)m * VPET_PSTRIDE * 2, md[m])) != VPET_OK) return rc;
+    HostTab T;
+    if ((rc = make_tables(input_fn, frame_times, grid, 0.0, T)) != VPET_OK) return rc;
+    if (T.F > VPET_BANK_MAX_FRAMES)
+        return fail(VPET_E_LIMIT, "the bank form supports up to %d frames", VPET_BANK_MAX_FRAMES);
+    if (!out_theta || !out_x) return fail(VPET_E_ARG, "out_theta and out_x must not be NULL");
+    const int ld = vpet_abc_bank_ld(T.F);
+    DevCtx* ctx;
+    if ((rc = current_ctx(&ctx)) != VPET_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    Tab tab;
+    int slot;
+    if ((rc = upload_tables(*ctx, T, st, tab, slot)) != VPET_OK) return rc;
+    const unsigned threads = 256, blocks = (unsigned)((n_draws + threads - 1) / threads);
+    const unsigned k0 = (unsigned)(seed & 0xffffffffu), k1 = (unsigned)(seed >> 32);
+    for (int m = 0; m < M; ++m) {
+        if (kinds[m] == KIND_1TCM)
+            hipLaunchKernelGGL(vpet_bank_kernel<KIND_1TCM>, dim3(blocks), dim3(threads), 0, st, md[m], m,
+                               (unsigned)n_draws, k0, k1, tab, T.C0, T.h, T.F, T.k0, ld, out_theta, out_x);
+        else if (kinds[m] == KIND_IRR)
+            hipLaunchKernelGGL(vpet_bank_kernel<KIND_IRR>, dim3(blocks), dim3(threads), 0, st, md[m], m,
+                               (unsigned)n_draws, k0, k1, tab, T.C0, T.h, T.F, T.k0, ld, out_theta, out_x);
+        else
+            hipLaunchKernelGGL(vpet_bank_kernel<KIND_REV>, dim3(blocks), dim3(threads), 0, st, md[m], m,
+                               (unsigned)n_draws, k0, k1, tab, T.C0, T.h, T.F, T.k0, ld, out_theta, out_x);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "bank launch");
+    }
+    hipError_t e = hipEventRecord(ctx->ev[slot], st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return VPET_OK;
+}
+
+int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_times, vpet_grid grid,
+                        uint32_t model_id, int64_t n_draws, double accept_frac, const float* bank_theta,
+                        const double* bank_x, float* out_moments, float* out_model_prob, const vpet_abc_opts* opts,
+                        void* hip_stream) {
+    int kinds[kMaxModels];
+    const int M = model_list(model_id, kinds);
+    if (M < 1) return fail(VPET_E_MODEL, "unknown or empty model bitmask 0x%x", model_id);
+    if (n_voxels < 0) return fail(VPET_E_ARG, "n_voxels must be >= 0");
+    if (n_draws < 1) return fail(VPET_E_ARG, "n_draws must be >= 1");
+    if ((double)M * (double)n_draws > 4294967295.0) return fail(VPET_E_LIMIT, "M * n_draws must stay below 2^32");
+    vpet_abc_opts o{};
+    if (opts) o = *opts;
+    if (o.distance != 0 && o.distance != 1) return fail(VPET_E_ARG, "opts.distance must be 0 (L2) or 1 (L1)");
+    if (!(std::isfinite(o.decay_lambda) && o.decay_lambda >= 0.0))
+        return fail(VPET_E_ARG, "opts.decay_lambda must be finite and >= 0");
+    if (!(std::isfinite(o.weight_floor_frac) && o.weight_floor_frac >= 0.0f))
+        return fail(VPET_E_ARG, "opts.weight_floor_frac must be finite and >= 0");
+    if (o.bank_pilot < 0) return fail(VPET_E_ARG, "opts.bank_pilot must be >= 0");
+    int64_t n_acc = 0;
+    int rc = vpet_abc_accept_count((int64_t)M * n_draws, accept_frac, &n_acc);
+    if (rc != VPET_OK) return rc;
+    if (n_acc > VPET_BANK_MAX_ACCEPT)
+        return fail(VPET_E_LIMIT, "n = %lld exceeds VPET_BANK_MAX_ACCEPT = %d", (long long)n_acc,
+                    VPET_BANK_MAX_ACCEPT);
+    // frame bounds and weights' decay factors (the input function is not needed)
+    if (!frame_times) return fail(VPET_E_ARG, "frame_times must not be NULL");
+    if (!(std::isfinite(grid.dt) && grid.dt > 0.0f)) return fail(VPET_E_GRID, "grid.dt must be finite and > 0");
+    if (grid.n_nodes < 2 || grid.n_frames < 1) return fail(VPET_E_GRID, "grid needs n_nodes >= 2, n_frames >= 1");
+    if (grid.n_frames > VPET_BANK_MAX_FRAMES)
+        return fail(VPET_E_LIMIT, "the bank form supports up to %d frames", VPET_BANK_MAX_FRAMES);
+    const double h = (double)grid.dt, lambda = o.decay_lambda > 0.0 ? o.decay_lambda : std::log(2.0) / 109.8;
+    const int F = grid.n_frames, K = grid.n_nodes - 1;
+    std::vector<double> omega(F);
+    int kprev = -1;
+    for (int f = 0; f <= F; ++f) {
+        const double tau = (double)frame_times[f];
+        if (!std::isfinite(tau)) return fail(VPET_E_GRID, "frame_times[%d] is not finite", f);
+        const double kd = std::nearbyint(tau / h);
+        if (std::fabs(kd * h - tau) > 1e-6 * std::fmax(1.0, std::fabs(tau)))
+            return fail(VPET_E_GRID, "frame bound %g is not on the %g-min grid", tau, h);
+        if (kd < 0.0 || kd > (double)K) return fail(VPET_E_GRID, "frame bound %g lies outside the grid", tau);
+        const int k = (int)kd;
+        if (f > 0) {
+            if (k <= kprev) return fail(VPET_E_GRID, "frame bounds must increase strictly");
+            omega[f - 1] = (double)(k - kprev) * h * std::exp(-lambda * 0.5 * (double)(k + kprev) * h);
+        }
+        kprev = k;
+    }
+    if (n_voxels == 0) return VPET_OK;
+    if (!tacs || !out_moments || !out_model_prob || !bank_theta || !bank_x)
+        return fail(VPET_E_ARG, "tacs, bank and output pointers must not be NULL");
+    const int64_t n_tot = (int64_t)M * n_draws;
+    const int cap = std::max(256, pow2_at_least(8 * (int)n_acc));
+    int64_t pilot = o.bank_pilot > 0 ? o.bank_pilot : (4 * n_tot + n_acc - 1) / n_acc;
+    pilot = std::min<int64_t>(pilot, n_tot);
+    const int ld = vpet_abc_bank_ld(F);
+
+    BankArgs A{};
+    A.weights = o.weights;
+    A.bank_x = bank_x;
+    A.bank_theta = bank_theta;
+    A.floor_frac = o.weight_floor_frac > 0.0f ? (double)o.weight_floor_frac : 0.01;
+    A.F = F;
+    A.ld = ld;
+    A.l1 = o.distance;
+    A.M = M;
+    A.cap = cap;
+    A.n_tot = (unsigned)n_tot;
+    A.n_draws = (unsigned)n_draws;
+    A.n_acc = (unsigned)n_acc;
+    A.n_pilot = (unsigned)pilot;
+    for (int m = 0; m < M; ++m) A.kinds[m] = kinds[m];
+
+    DevCtx* ctx;
+    if ((rc = current_ctx(&ctx)) != VPET_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int slot;
+    const void* dom;
+    if ((rc = upload_blob(*ctx, omega.data(), sizeof(double) * F, st, &dom, slot)) != VPET_OK) return rc;
+    A.omega = static_cast<const double*>(dom);
+
+    // voxel chunks bound the candidate scratch to ~2 GiB
+    const long long chunk = std::max<long long>(256, (1LL << 31) / ((long long)cap * 8));
+    const long long cv = std::min<long long>(n_voxels, chunk);
+    char* scratch = nullptr;
+    const size_t sz_tau = align256(sizeof(float) * cv), sz_cnt = align256(sizeof(int) * cv);
+    const size_t sz_fb = align256(sizeof(int) * cv), sz_cand = sizeof(uint64_t) * (size_t)cap * cv;
+    hipError_t e = hipMallocAsync((void**)&scratch, sz_tau + sz_cnt + sz_fb + sz_cand, st);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "bank scratch: %s", hipGetErrorString(e));
+    A.tau = reinterpret_cast<float*>(scratch);
+    A.cnt = reinterpret_cast<int*>(scratch + sz_tau);
+    A.fallback = reinterpret_cast<int*>(scratch + sz_tau + sz_cnt);
+    A.cand = reinterpret_cast<uint64_t*>(scratch + sz_tau + sz_cnt + sz_fb);
+    const size_t lds = sizeof(uint64_t) * cap + sizeof(double) * 8 * kMaxWpv;
+    for (long long base = 0; base < n_voxels && rc == VPET_OK; base += cv) {
+        BankArgs Q = A;
+        Q.V = std::min<long long>(n_voxels - base, cv);
+        Q.tacs = tacs + (size_t)base * F;
+        Q.weights = o.weights ? o.weights + (size_t)base * F : nullptr;
+        Q.out_mom = out_moments + (size_t)base * M * 16;
+        Q.out_prob = out_model_prob + (size_t)base * M;
+        Q.out_idx = o.out_accept_idx ? o.out_accept_idx + (size_t)base * n_acc : nullptr;
+        Q.out_dist = o.out_accept_dist ? o.out_accept_dist + (size_t)base * n_acc : nullptr;
+        Q.out_thr = o.out_threshold ? o.out_threshold + base : nullptr;
+        const dim3 lanes((unsigned)((Q.V + 255) / 256)), b256(256), per_voxel((unsigned)Q.V), b64(64);
+#define VPET_BANK_LAUNCH(LDV, L1V)                                                                        \
+    do {                                                                                                  \
+        hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, true>), lanes, b256, 0, st, Q);               \
+        hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, false>), lanes, b256, 0, st, Q);              \
+        hipLaunchKernelGGL(vpet_bank_select_kernel, per_voxel, b64, lds, st, Q);                          \
+        hipLaunchKernelGGL((vpet_bank_fallback_kernel<LDV, L1V>), per_voxel, b64, lds, st, Q);            \
+    } while (0)
+        const int sel = (ld / 8) * 2 + (o.distance == 1 ? 1 : 0);
+        switch (sel) {
+            case 2: VPET_BANK_LAUNCH(8, false); break;
+            case 3: VPET_BANK_LAUNCH(8, true); break;
+            case 4: VPET_BANK_LAUNCH(16, false); break;
+            case 5: VPET_BANK_LAUNCH(16, true); break;
+            case 6: VPET_BANK_LAUNCH(24, false); break;
+            case 7: VPET_BANK_LAUNCH(24, true); break;
+            case 8: VPET_BANK_LAUNCH(32, false); break;
+            default: VPET_BANK_LAUNCH(32, true); break;
+        }
+#undef VPET_BANK_LAUNCH
+        e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_fail(e, "bank infer launch");
+    }
+    e = hipFreeAsync(scratch, st);
+    if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipFreeAsync");
+    e = hipEventRecord(ctx->ev[slot], st);
+    if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipEventRecord");
+    return rc;
 }
 
 }  // extern "C"

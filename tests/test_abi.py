@@ -114,3 +114,35 @@ def test_simulate_and_draws_validation_without_gpu(V):
     assert V.lib.vpet_abc_draws(2, P(box), 1, None, None, None, 0, None, None, None) == V.OK
     assert V.lib.vpet_abc_draws(2, P(box), 1, None, None, None, 5, None, None, None) == V.E_ARG
     assert V.lib.vpet_abc_last_error().decode() != ""
+
+
+def test_bank_validation_without_gpu(V):
+    ft = W.frame_times(W.SCHED_22x60)
+    cp = W.grid(0.2, 60.0)[1]
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    g = V._binding.Grid(0.2, cp.size, ft.size - 1)
+    box = W.box_array([2])
+    assert V.lib.vpet_abc_bank_ld(22) == 24 and V.lib.vpet_abc_bank_ld(32) == 32 and V.lib.vpet_abc_bank_ld(0) == 0
+    assert V.lib.vpet_abc_bank_build(0, P(box), 10, 1, P(cp), P(ft), g, None, None, None) == V.E_MODEL
+    assert V.lib.vpet_abc_bank_build(2, P(box), 0, 1, P(cp), P(ft), g, None, None, None) == V.E_ARG
+    assert V.lib.vpet_abc_bank_build(2, P(box), 10, 1, P(cp), P(ft), g, None, None, None) == V.E_ARG  # NULL outs
+    ft40 = W.frame_times([1.0] * 40)
+    g40 = V._binding.Grid(0.2, 201, 40)
+    cp40 = W.grid(0.2, 40.0)[1]
+    assert V.lib.vpet_abc_bank_build(2, P(box), 10, 1, P(cp40), P(ft40), g40, None, None, None) == V.E_LIMIT
+
+    def ib(model=2, n_draws=1000, p=0.05, grid=g, frames=ft, V_=0, opts=None):
+        return V.lib.vpet_abc_infer_bank(None, V_, P(frames), grid, model, n_draws, p, None, None, None, None,
+                                         ctypes.byref(opts) if opts is not None else None, None)
+    assert ib() == V.OK                                   # no voxels: nothing to do
+    assert ib(model=0) == V.E_MODEL
+    assert ib(p=0.9) == V.E_LIMIT                         # n = 900 > 512
+    assert ib(p=0.0001) == V.E_ARG                        # n = 0
+    bad = ft.copy()
+    bad[2] += np.float32(0.07)
+    assert ib(frames=bad) == V.E_GRID
+    assert ib(grid=g40, frames=ft40) == V.E_LIMIT
+    o = V._binding.Opts()
+    o.bank_pilot = -1
+    assert ib(opts=o) == V.E_ARG
+    assert ib(V_=3) == V.E_ARG                            # NULL device pointers

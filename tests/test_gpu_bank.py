@@ -1,0 +1,174 @@
+"""GPU parity of the shared-bank form (Alg. 1 as printed: one bank of draws and
+curves for every voxel) against the oracle's bank form, through the C ABI."""
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import MEAN_RTOL, THRESH_RTOL  # noqa: F401
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2603_14859_amd as V  # noqa: E402
+
+DEV = torch.device("cuda:0")
+H = 0.2
+
+
+def _inputs(sched, n_vox, model=W.M_2TCM_IRR, seed=5):
+    import oracle as ora
+    ft = W.frame_times(sched)
+    _, cp = W.grid(H, float(np.sum(sched)))
+    rng = np.random.default_rng(seed)
+    th = W.true_params(rng, n_vox, model, W.box_array([model])[0])
+    clean = ora.simulate(model, th, cp, H, ft)
+    return ft, cp, W.add_noise(clean, ft, rng.standard_normal(clean.shape))
+
+
+def _bank_moments(models, th_bank, idx, n_draws):
+    """FP64 summaries of an explicit accepted set drawn from the bank."""
+    M = len(models)
+    t = th_bank[np.asarray(idx)].astype(np.float64)
+    t[:, 5] = t[:, 0] * t[:, 2] / (t[:, 1] + t[:, 2])
+    m = np.asarray(idx) // n_draws
+    mom = np.full((M, 8, 2), np.nan)
+    prob = np.zeros(M)
+    for mm in range(M):
+        sel = t[m == mm]
+        prob[mm] = sel.shape[0] / len(idx)
+        if sel.shape[0]:
+            mom[mm, :, 0] = sel.mean(axis=0)
+            mom[mm, :, 1] = sel.var(axis=0, ddof=1) if sel.shape[0] > 1 else 0.0
+            if models[mm] == W.M_1TCM:
+                mom[mm, [2, 3, 5]] = np.nan
+            elif models[mm] == W.M_2TCM_IRR:
+                mom[mm, 3] = np.nan
+            mom[mm, 6:] = np.nan
+    return mom, prob
+
+
+def _check(y, ft, cp, models, n_draws, p, seed, l1=False, weights=None, bank_pilot=0):
+    import oracle as ora
+    boxes = W.box_array(list(models))
+    th_g, x_g = V.bank_build(models, boxes, n_draws, seed, cp, ft, H)
+    res = V.infer_bank(torch.from_numpy(y).to(DEV), ft, H, cp.size, models, n_draws, p, th_g, x_g,
+                       distance="l1" if l1 else "l2", debug=True, bank_pilot=bank_pilot,
+                       weights=None if weights is None else torch.from_numpy(weights).to(DEV))
+    torch.cuda.synchronize()
+    g = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()}
+    o = ora.infer_bank(y, ft, cp, H, list(models), boxes, n_draws, p, seed, l1=l1, weights=weights)
+    th_o, x_o = ora.bank(list(models), boxes, n_draws, seed, cp, H, ft)
+    assert g["n"] == o["n"]
+    swaps = 0
+    for v in range(y.shape[0]):
+        a_g, a_o = set(g["accept_idx"][v].tolist()), set(o["accept_idx"][v].tolist())
+        if a_g != a_o:
+            w = (ora.weights(y[v], ft, H, cp.size) if weights is None else weights[v].astype(np.float64))
+            r = y[v].astype(np.float64) - x_o
+            d = (np.sqrt(w) * np.abs(r)).sum(1) if l1 else (w * r * r).sum(1)
+            h = o["threshold"][v]
+            for gg in a_g ^ a_o:
+                assert abs(d[gg] - h) <= THRESH_RTOL * h, f"voxel {v}: draw {gg} swapped far from the threshold"
+            swaps += 1
+            ref_mom, ref_prob = _bank_moments(list(models), th_o, g["accept_idx"][v], n_draws)
+        else:
+            ref_mom, ref_prob = o["moments"][v], o["model_prob"][v]
+        gm = g["moments"][v].astype(np.float64)
+        assert np.array_equal(np.isnan(gm), np.isnan(ref_mom)), f"voxel {v}: NaN pattern"
+        ok = ~np.isnan(ref_mom)
+        assert np.allclose(gm[ok], ref_mom[ok], rtol=1e-5, atol=1e-7), f"voxel {v}: moments"
+        assert np.allclose(g["model_prob"][v], ref_prob, atol=1e-7, equal_nan=True)
+    print(f"[bank parity] V={y.shape[0]} n={o['n']} voxels with threshold swaps: {swaps}")
+    return g, o
+
+
+def test_bank_build_matches_oracle():
+    import oracle as ora
+    models = [W.M_1TCM, W.M_2TCM_IRR, W.M_2TCM_REV]
+    boxes = W.box_array(models)
+    for sched in (W.SCHED_22x60, W.SCHED_30x50, [1.0, 2.0, 5.0]):
+        ft = W.frame_times(sched)
+        _, cp = W.grid(H, float(np.sum(sched)))
+        th_g, x_g = V.bank_build(models, boxes, 3000, 77, cp, ft, H)
+        th_o, x_o = ora.bank(models, boxes, 3000, 77, cp, H, ft)
+        F = ft.size - 1
+        xg = x_g.cpu().numpy()
+        assert np.array_equal(th_g.cpu().numpy().view(np.uint32), th_o.view(np.uint32))
+        err = np.abs(xg[:, :F] - x_o).max(axis=1) / np.abs(x_o).max(axis=1)
+        assert err.max() < 1e-11, err.max()
+        assert (xg[:, F:] == 0).all()
+
+
+def test_infer_bank_parity_30_frames():
+    ft, cp, y = _inputs(W.SCHED_30x50, 300)
+    _check(y, ft, cp, [W.M_2TCM_IRR], 20_000, 0.005, 14859)
+
+
+@pytest.mark.parametrize("models", [(W.M_2TCM_IRR, W.M_2TCM_REV), (W.M_1TCM, W.M_2TCM_IRR, W.M_2TCM_REV)])
+def test_infer_bank_parity_model_selection(models):
+    ft, cp, y = _inputs(W.SCHED_22x60, 120, model=W.M_2TCM_REV, seed=9)
+    _check(y, ft, cp, list(models), 6000, 0.01, 3)
+
+
+def test_infer_bank_l1_weights_and_short_schedule():
+    ft, cp, y = _inputs([1.0, 2.0, 3.0, 6.0], 70, seed=2)
+    _check(y, ft, cp, [W.M_2TCM_IRR], 5000, 0.01, 4, l1=True)
+    w = np.random.default_rng(3).uniform(0.3, 2.0, y.shape).astype(np.float32)
+    _check(y, ft, cp, [W.M_2TCM_IRR], 5000, 0.01, 4, weights=w)
+
+
+def test_infer_bank_forced_fallback_and_edges():
+    ft, cp, y = _inputs(W.SCHED_22x60, 40, seed=7)
+    y[5, 2] = np.nan
+    y[6] = -1.0
+    # a pilot over the whole bank keeps only 16 candidates per voxel, fewer
+    # than n = 60: every voxel takes the exact fallback path
+    g, _ = _check(y, ft, cp, [W.M_2TCM_IRR], 3000, 0.02, 11, bank_pilot=3000)
+    for v in (5, 6):
+        assert np.isnan(g["moments"][v]).all() and (g["accept_idx"][v] == -1).all()
+    _check(y[:8], ft, cp, [W.M_2TCM_IRR, W.M_2TCM_REV], 150, 1.0, 5)       # p = 1: n = N = 300
+    _check(y[:8], ft, cp, [W.M_2TCM_IRR], 7, 0.2, 5)                        # tiny bank, n = 1
+
+
+def test_infer_bank_limits():
+    ft, cp, y = _inputs(W.SCHED_22x60, 2)
+    th, x = V.bank_build([W.M_2TCM_IRR], W.box_array([W.M_2TCM_IRR]), 1000, 1, cp, ft, H)
+    with pytest.raises(V.VpetError) as e:
+        V.infer_bank(torch.from_numpy(y).to(DEV), ft, H, cp.size, [W.M_2TCM_IRR], 1000, 0.6, th, x)
+    assert e.value.status == V.E_LIMIT
+    ft40 = W.frame_times([1.0] * 40)
+    with pytest.raises(V.VpetError) as e:
+        V.bank_build([W.M_2TCM_IRR], W.box_array([W.M_2TCM_IRR]), 10, 1, W.grid(H, 40.0)[1], ft40, H)
+    assert e.value.status == V.E_LIMIT
+
+
+def test_infer_bank_full_size_sampled():
+    """1,048,576 voxels against a 100,000-draw bank (30 frames, 0.1 % accepted), sampled voxels vs the oracle."""
+    import oracle as ora
+    cfg = W.CFG_LARGE
+    ft, cp = cfg.frame_times, cfg.input_fn()
+    th, eps = cfg.truth()
+    rng = np.random.default_rng(4)
+    sample = np.sort(rng.choice(cfg.n_voxels, 5, replace=False))
+    y_s = W.add_noise(ora.simulate(W.M_2TCM_IRR, th[sample], cp, H, ft), ft, eps[sample])
+    y = np.tile(y_s, (cfg.n_voxels // len(sample) + 1, 1))[:cfg.n_voxels]
+    y[sample] = y_s
+    models = list(cfg.models)
+    boxes = cfg.box_array()
+    th_g, x_g = V.bank_build(models, boxes, cfg.n_draws, cfg.infer_seed, cp, ft, H)
+    res = V.infer_bank(torch.from_numpy(y).to(DEV), ft, H, cp.size, models, cfg.n_draws, cfg.accept_frac, th_g, x_g,
+                       debug=True)
+    torch.cuda.synchronize()
+    o = ora.infer_bank(y_s, ft, cp, H, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed)
+    idx = res["accept_idx"][torch.from_numpy(sample).to(DEV)].cpu().numpy()
+    mom = res["moments"][torch.from_numpy(sample).to(DEV)].cpu().numpy()
+    for j in range(len(sample)):
+        if set(idx[j].tolist()) == set(o["accept_idx"][j].tolist()):
+            ok = ~np.isnan(o["moments"][j])
+            assert np.allclose(mom[j][ok], o["moments"][j][ok], rtol=1e-5, atol=1e-7)
+    same = sum(set(idx[j].tolist()) == set(o["accept_idx"][j].tolist()) for j in range(len(sample)))
+    assert same >= len(sample) - 1
+    assert torch.isfinite(res["model_prob"]).all()

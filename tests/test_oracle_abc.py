@@ -252,3 +252,72 @@ def test_invalid_voxels_give_nan_and_offset_is_global(ora):
     # the thread count does not change the result
     par = ora.infer(y, ft, cp, H, models, boxes, 500, 0.02, 9, nthreads=3)
     assert np.array_equal(par["accept_idx"], res["accept_idx"])
+
+
+# ---------------------------------------------------------------------------
+# Shared-bank form (Alg. 1 as printed: one bank of draws for all voxels)
+# ---------------------------------------------------------------------------
+def test_bank_draws_and_curves(ora):
+    ft, cp = _setup()
+    models = np.array([W.M_2TCM_IRR, W.M_2TCM_REV], dtype=np.uint32)
+    boxes = W.box_array(list(models))
+    th, x = ora.bank(models, boxes, 300, 42, cp, H, ft)
+    # bank draw i of model m is the Philox draw of counter (i, 0, 1, m<<16|blk)
+    m = np.repeat([0, 1], 300)
+    i = np.tile(np.arange(300), 2)
+    _, _, th2 = ora.draws(models, boxes, 42, np.zeros(600), i, m, stream=1)
+    assert np.array_equal(th.view(np.uint32), th2.view(np.uint32))
+    assert np.array_equal(x[:300], ora.simulate(W.M_2TCM_IRR, th[:300], cp, H, ft))
+    assert np.array_equal(x[300:], ora.simulate(W.M_2TCM_REV, th[300:], cp, H, ft))
+
+
+def test_bank_selection_matches_brute_force(ora):
+    ft, cp = _setup()
+    models = np.array([W.M_2TCM_IRR, W.M_1TCM], dtype=np.uint32)
+    boxes = W.box_array(list(models))
+    y = _observed(ora, W.M_2TCM_IRR, W.CFG_SMALL.truth(4)[0], ft, cp)
+    y[2] = y[1]                                    # identical voxels share the bank's answer
+    n_draws, p = 200, 0.05
+    res = ora.infer_bank(y, ft, cp, H, models, boxes, n_draws, p, 17)
+    _, x = ora.bank(models, boxes, n_draws, 17, cp, H, ft)
+    for v in range(4):
+        w = ora.weights(y[v], ft, H, cp.size)
+        d = np.sum(w * (y[v].astype(np.float64) - x) ** 2, axis=1)
+        keys = list(zip(d, range(d.size)))
+        rank = np.array([sum(1 for k2 in keys if k2 < k) for k in keys])
+        order = np.argsort(rank)
+        assert np.array_equal(res["accept_idx"][v], order[:res["n"]])
+        assert np.allclose(res["accept_dist"][v], d[order[:res["n"]]], rtol=1e-13)
+    assert np.array_equal(res["accept_idx"][1], res["accept_idx"][2])
+    assert np.array_equal(res["moments"][1], res["moments"][2], equal_nan=True)
+
+
+def test_bank_linear_target_interval(ora):
+    # the exact-interval pin of the per-voxel form, for the shared bank
+    ft, cp = _setup()
+    models = np.array([W.M_2TCM_IRR], dtype=np.uint32)
+    fixed = {1: 0.25, 2: 0.06, 4: 0.05}
+    boxes = _box([W.M_2TCM_IRR], fixed={(0, s): v for s, v in fixed.items()})
+    base = np.full((2, 8), np.nan)
+    for r, k1 in enumerate((0.0, 1.0)):
+        base[r, [0, 1, 2, 4]] = (k1, fixed[1], fixed[2], fixed[4])
+    xb = ora.simulate(W.M_2TCM_IRR, base, cp, H, ft)
+    c0, g = xb[0], xb[1] - xb[0]
+    truth = np.full((3, 8), np.nan, dtype=np.float32)
+    truth[:, [0, 1, 2, 4]] = [(0.3, 0.25, 0.06, 0.05), (0.5, 0.25, 0.06, 0.05), (0.8, 0.25, 0.06, 0.05)]
+    y = _observed(ora, W.M_2TCM_IRR, truth, ft, cp, seed=5)
+    n_draws, p = 50_000, 0.01
+    res = ora.infer_bank(y, ft, cp, H, models, boxes, n_draws, p, 9)
+    th, _ = ora.bank(models, boxes, n_draws, 9, cp, H, ft)
+    k1 = th[:, 0].astype(np.float64)
+    for v in range(3):
+        w = ora.weights(y[v], ft, H, cp.size)
+        yd = y[v].astype(np.float64)
+        A, B = np.sum(w * g * g), np.sum(w * g * (yd - c0))
+        C = np.sum(w * (yd - c0) ** 2)
+        r = np.sqrt((res["threshold"][v] - (C - B * B / A)) / A)
+        lo, hi = B / A - r, B / A + r
+        acc = k1[res["accept_idx"][v]]
+        tol = 1e-6 * (hi - lo)   # the edges carry the cancellation of C - B^2/A
+        assert acc.min() >= lo - tol and acc.max() <= hi + tol
+        assert res["n"] - 2 <= np.sum((k1 > lo + tol) & (k1 < hi - tol)) <= res["n"]
