@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "posterior voxels/s at fixed draws & error vs FP64 oracle; % of roofline"
 # MI355X: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s FP64 vector.
 PEAK_F64_VECTOR_TFLOPS = 78.6
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense BF16 matrix-core peak (no sparsity)
 KERNEL_NAME = "vpet_infer_kernel"
 SRC = os.path.join(ROOT, "paper_2603_14859_amd", "csrc", "vpet_abc.hip")
 
@@ -121,7 +122,7 @@ def cpu_baseline(cfg, ft, cp, y, y_dev, budget_s: float):
     return base, err
 
 
-def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, budget_s: float):
+def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, budget_s: float, scan: str = "bf16"):
     """The shared-bank form (one bank of cfg.n_draws prior draws for every voxel) on the same volume."""
     import torch
 
@@ -139,36 +140,51 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
     res = {"moments": torch.empty((cfg.n_voxels, M, 8, 2), dtype=torch.float32, device=y_dev.device),
            "model_prob": torch.empty((cfg.n_voxels, M), dtype=torch.float32, device=y_dev.device)}
 
-    def step():
-        V.infer_bank(y_dev, ft, cfg.dt, n_nodes, models, cfg.n_draws, cfg.accept_frac, thb, xb, out=res)
+    scan_ms = []
+
+    def step(timed):
+        r = V.infer_bank(y_dev, ft, cfg.dt, n_nodes, models, cfg.n_draws, cfg.accept_frac, thb, xb, out=res,
+                         bank_scan=scan, time_scan=timed)
+        if timed:
+            scan_ms.append(r["scan_ms"])
 
     for _ in range(warmup):
-        step()
+        step(False)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
         ev[k][0].record(stream)
-        step()
+        step(True)  # the scan kernel is bracketed by HIP events inside the call
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     call_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    ld = int(V.lib.vpet_abc_bank_ld(F))
+    kern_ms = float(np.mean(scan_ms))
     n = V.accept_count(M * cfg.n_draws, cfg.accept_frac)
-    pilot = min(M * cfg.n_draws, -(-4 * M * cfg.n_draws // n))
-    pairs = cfg.n_voxels * (M * cfg.n_draws + pilot)
-    fl = pairs * 4 * ld  # per (voxel, bank row) and frame: subtract, weight, fused multiply-add
-    achieved = fl / (call_ms * 1e-3) / 1e12
+    n_tot = M * cfg.n_draws
+    pairs = cfg.n_voxels * n_tot
+    if scan == "bf16":
+        # the contraction d - a = sum_k A_vk B_gk over K = 2F real terms: one
+        # multiply-add per term and pair (the hi/lo split, the error-bound
+        # product and the padding of F to a multiple of 8 are not counted)
+        fpp = 2 * 2 * F
+        peak, bound, kname = PEAK_BF16_MFMA_TFLOPS, "mfma", "vpet_bank_mfma_kernel<64, false> (BF16 contraction scan)"
+        pilot = min(n_tot, -(-11 * n_tot // (2 * n)))
+    else:
+        fpp = 4 * F  # per frame: subtract, weight, fused multiply-add
+        peak, bound, kname = PEAK_F64_VECTOR_TFLOPS, "alu", "vpet_bank_scan_kernel<32, false, false> (FP64 scan)"
+        pilot = min(n_tot, -(-4 * n_tot // n))
+    achieved = pairs * fpp / (kern_ms * 1e-3) / 1e12
     out = {"value": cfg.n_voxels / (ms * 1e-3), "unit": "voxels/s", "ms_per_step": round(ms, 3),
-           "bank_build_ms": round(build_ms, 3), "dtype": "f64",
-           "config": {"bank_draws": M * cfg.n_draws, "draws": "one Philox4x32-10 bank (stream 1) for all voxels",
-                      "n_accept": n, "pilot_rows": pilot},
-           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_F64_VECTOR_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_VECTOR_TFLOPS, 4), "traffic": None,
-                        "kernel": "vpet_bank_scan_kernel (pilot + scan; timed with select/fallback)",
-                        "kernel_ms": round(call_ms, 3), "flops_per_pair": 4 * ld}}
+           "call_ms_hip_events": round(call_ms, 3), "bank_build_ms": round(build_ms, 3),
+           "dtype": "bf16x3 contraction + f64 re-rank" if scan == "bf16" else "f64",
+           "config": {"bank_draws": n_tot, "draws": "one Philox4x32-10 bank (stream 1) for all voxels",
+                      "n_accept": n, "pilot_rows": pilot, "scan": scan},
+           "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
+                        "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                        "kernel": kname, "kernel_ms": round(kern_ms, 3), "flops_per_pair": fpp}}
     if cpu:
         import oracle
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
@@ -213,6 +229,8 @@ def main():
     ap.add_argument("--workload", choices=["large", "small"], default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bank", action="store_true", help="skip the shared-bank form")
+    ap.add_argument("--bank-scan", choices=["bf16", "f64"], default="bf16",
+                    help="pair screening of the shared-bank form: BF16 matrix cores or FP64 vector ALUs")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
@@ -249,10 +267,15 @@ def main():
         step(res)
     torch.cuda.synchronize()
     if args.copy_calibration:
-        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        # a plain copy of 1 GiB whose source was evicted from the 256 MB
+        # last-level cache by 1 GiB of other writes (reads 1 GiB, writes 1 GiB)
+        a = torch.empty(256 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        flush = torch.empty_like(a).fill_(2.0)
         b = torch.empty_like(a)
+        torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b, flush
 
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
@@ -291,7 +314,7 @@ def main():
         out["error_vs_oracle"] = err
     if not args.no_bank and F <= V.BANK_MAX_FRAMES:
         out["bank_form"] = bank_form(cfg, ft, cp, y_host, y, args.steps, args.warmup, not args.no_cpu_baseline,
-                                     args.cpu_budget / 3)
+                                     args.cpu_budget / 3, args.bank_scan)
     print(json.dumps(out), flush=True)
 
 

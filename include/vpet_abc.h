@@ -112,8 +112,23 @@ typedef struct {
     /* Waves cooperating on one voxel (1, 2 or 4); 0 = chosen from V. */
     int32_t waves_per_voxel;
     /* Shared-bank form only: bank rows in the pilot that sets each voxel's
-     * candidate threshold; 0 = ceil(4 N / n), so that about 4 n rows pass. */
+     * candidate threshold; 0 = a default that lets about 4 n rows pass
+     * (FP64 scan: the 16th smallest distance of the first ceil(4 N / n)
+     * rows; BF16 scan: the 16th smallest of 32 column minima of the first
+     * ceil(5.5 N / n) rows). */
     int64_t bank_pilot;
+    /* Shared-bank form only: how every (voxel, bank row) pair is screened.
+     * 0 = auto (1 for L1, 2 for L2); 1 = FP64 distances on the vector ALUs;
+     * 2 = the L2 distance as a voxels x rows x frames contraction on BF16
+     * matrix cores (hi/lo split operands, FP32 accumulation, a per-pair error
+     * bound), candidates re-ranked with exact FP64 distances.  Both give the
+     * same accepted sets. */
+    int32_t bank_scan;
+    /* Shared-bank form only: host pointer; when set, the call brackets each
+     * voxel chunk's scan kernel (the one that screens every (voxel, bank row)
+     * pair) with HIP events on hip_stream, waits for them, and writes the
+     * summed kernel time in milliseconds here.  Makes the call synchronous. */
+    float* out_scan_ms;
 } vpet_abc_opts;
 
 /*
@@ -215,10 +230,14 @@ int vpet_abc_bank_build(uint32_t model_id, const double* prior_box, int64_t n_dr
  * grid); frame_times and grid give the frames (the input function is not
  * needed).  Distances are FP64; the accepted set is the n smallest keys
  * (fp32(d), g), n = floor(M n_draws p + 1e-6) <= VPET_BANK_MAX_ACCEPT.
- * opts: weights, weight_floor_frac, decay_lambda, distance, the debug outputs
- * and bank_pilot are honoured; voxel_offset and waves_per_voxel do not apply.
- * Device scratch (about 8 n keys per voxel, in chunks of at most 2 GiB) is
- * allocated and freed in stream order.
+ * opts: weights, weight_floor_frac, decay_lambda, distance, the debug outputs,
+ * bank_pilot and bank_scan are honoured; voxel_offset and waves_per_voxel do
+ * not apply.  Whatever the scan, the accepted set is the exact one: a voxel
+ * whose candidate list cannot prove it holds the n smallest keys is redone
+ * by an exact pass over the whole bank.
+ * Device scratch (a candidate list of 8 n keys, or 16 n bank rows for the
+ * BF16 scan, per voxel, in voxel chunks of at most 4 GiB; the BF16 operands,
+ * 8 M n_draws ld bytes) is allocated and freed in stream order.
  * Errors: VPET_E_ARG, VPET_E_MODEL, VPET_E_GRID, VPET_E_LIMIT, VPET_E_NOMEM,
  * VPET_E_HIP.
  */

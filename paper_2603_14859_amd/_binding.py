@@ -43,7 +43,8 @@ class Opts(ctypes.Structure):
                 ("weight_floor_frac", ctypes.c_float), ("distance", ctypes.c_int32),
                 ("out_accept_idx", ctypes.c_void_p), ("out_accept_dist", ctypes.c_void_p),
                 ("out_threshold", ctypes.c_void_p), ("voxel_offset", ctypes.c_int64),
-                ("waves_per_voxel", ctypes.c_int32), ("bank_pilot", ctypes.c_int64)]
+                ("waves_per_voxel", ctypes.c_int32), ("bank_pilot", ctypes.c_int64),
+                ("bank_scan", ctypes.c_int32), ("out_scan_ms", ctypes.POINTER(ctypes.c_float))]
 
 
 def _load():
@@ -220,8 +221,11 @@ def bank_build(models, prior_box, n_draws: int, seed: int, input_fn, frame_times
 
 def infer_bank(tacs, frame_times, dt: float, n_nodes: int, models, n_draws: int, accept_frac: float, bank_theta,
                bank_x, *, weights=None, weight_floor=0.0, decay_lambda=0.0, distance="l2", debug=False,
-               bank_pilot=0, out=None, stream=None) -> dict:
-    """Rejection ABC of every voxel against one shared bank (see bank_build)."""
+               bank_pilot=0, bank_scan="auto", time_scan=False, out=None, stream=None) -> dict:
+    """Rejection ABC of every voxel against one shared bank (see bank_build).
+
+    time_scan: also return "scan_ms", the HIP-event time of the pair-screening
+    kernel(s) (the call then waits for the stream)."""
     import torch
     tacs = _dev_f32(tacs, "tacs")
     V, F = tacs.shape
@@ -253,10 +257,16 @@ def infer_bank(tacs, frame_times, dt: float, n_nodes: int, models, n_draws: int,
         o.out_accept_dist = res["accept_dist"].data_ptr()
         o.out_threshold = res["threshold"].data_ptr()
     o.bank_pilot = int(bank_pilot)
+    o.bank_scan = {"auto": 0, "f64": 1, "bf16": 2}[bank_scan]
+    scan_ms = ctypes.c_float(0.0)
+    if time_scan:
+        o.out_scan_ms = ctypes.pointer(scan_ms)
     _check(lib.vpet_abc_infer_bank(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p), Grid(float(dt), int(n_nodes), F),
                                    mask, int(n_draws), float(accept_frac), _ptr(bank_theta), _ptr(bank_x),
                                    _ptr(res["moments"]), _ptr(res["model_prob"]), ctypes.byref(o), _stream(stream)))
     res["n"] = n
+    if time_scan:
+        res["scan_ms"] = float(scan_ms.value)
     return res
 
 

@@ -810,8 +810,18 @@ struct BankArgs {
     int kinds[kMaxModels];
     float* tau;             // [V] pilot threshold (fp32 distance), NaN for an invalid voxel
     int* cnt;               // [V] candidates found (may exceed cap)
-    uint64_t* cand;         // [V][cap] candidate keys
+    uint64_t* cand;         // [V][cap] candidate keys (FP64 scan)
+    uint32_t* cand_row;     // [V][cap] candidate bank rows (contraction scan; same memory)
     int* fallback;          // [V] 1 if the candidate set cannot certify the top n
+    // BF16 contraction (L2 only): d = a_v + sum_k A_vk B_gk with
+    // A_v = [-2 w y, w], B_g = [x, x^2], each split into bf16 hi + lo parts
+    int K;                  // 2 * ld
+    uint16_t* bhi;          // [N][K]
+    uint16_t* blo;
+    uint16_t* ahi;          // [V][K]
+    uint16_t* alo;
+    float* cthr;            // [V] candidate test: sum_k A B - margin <= cthr
+    double* aval;           // [V] a_v = sum_f w y^2; NaN for an invalid voxel
     float* out_mom;
     float* out_prob;
     int* out_idx;
@@ -988,9 +998,14 @@ __device__ void bank_invalid(const BankArgs& P, long long row) {
     if (P.out_thr && threadIdx.x == 0) P.out_thr[row] = qnan;
 }
 
-// One wavefront per voxel: sort the candidates, keep the n smallest.  When
-// the candidate count is below n or above the buffer, the voxel is marked
-// for the exact fallback instead.
+// One wavefront per voxel: sort the candidates, keep the n smallest.  With
+// RECOMPUTE the candidates carry only their bank row and the exact FP64
+// distance is computed here.  The result is certified when at least n
+// candidates have fp32 distance <= the pilot threshold (every bank row below
+// the threshold is a candidate, so the n smallest keys are among them);
+// otherwise -- or when the buffer overflowed -- the voxel is marked for the
+// exact fallback.
+template <int LD, bool L1, bool RECOMPUTE>
 __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
     extern __shared__ __align__(16) unsigned char lds[];
     uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
@@ -1007,10 +1022,47 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
         if (threadIdx.x == 0) P.fallback[row] = 1;
         return;
     }
+    const float tau = P.tau[row];
+    int below = 0;
+    if (RECOMPUTE) {
+        // exact FP64 distances of the candidate rows; keys above the
+        // threshold are dropped, the rest packed to the front
+        double Y[LD], Wt[LD];
+        lane_curve<LD, L1>(P, row, Y, Wt);  // every lane holds the voxel
+        const uint32_t* src = P.cand_row + (size_t)row * P.cap;
+        for (int j0 = 0; j0 < c; j0 += kWave) {
+            const int j = j0 + lane_id();
+            uint64_t key = kNoKey;
+            if (j < c) {
+                const uint32_t g = src[j];
+                const double* xr = P.bank_x + (size_t)g * LD;
+                double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                for (int f = 0; f < LD; f += 2) {
+                    const double r0 = Y[f] - xr[f], r1 = Y[f + 1] - xr[f + 1];
+                    d0 = L1 ? fma(Wt[f], fabs(r0), d0) : fma(Wt[f] * r0, r0, d0);
+                    d1 = L1 ? fma(Wt[f + 1], fabs(r1), d1) : fma(Wt[f + 1] * r1, r1, d1);
+                }
+                const float fd = key_dist(d0 + d1);
+                key = ((uint64_t)__float_as_uint(fd) << 32) | g;
+            }
+            const bool keep = j < c && __uint_as_float((uint32_t)(key >> 32)) <= tau;
+            const uint64_t b = __ballot(keep);
+            if (keep) keys[below + (int)mbcnt(b)] = key;
+            below += __popcll(b);
+        }
+    } else {
+        const uint64_t* src = P.cand + (size_t)row * P.cap;
+        for (int j = lane_id(); j < c; j += kWave) keys[j] = src[j];
+        below = c;
+    }
+    if (below < (int)P.n_acc) {
+        if (threadIdx.x == 0) P.fallback[row] = 1;
+        return;
+    }
     if (threadIdx.x == 0) P.fallback[row] = 0;
-    const int len = c <= 1 ? 2 : (1 << (32 - __clz(c - 1)));
-    const uint64_t* src = P.cand + (size_t)row * P.cap;
-    for (int j = threadIdx.x; j < len; j += kWave) keys[j] = j < c ? src[j] : kNoKey;
+    const int len = below <= 1 ? 2 : (1 << (32 - __clz(below - 1)));
+    for (int j = below + lane_id(); j < len; j += kWave) keys[j] = kNoKey;
     wave_lds_sync();
     wave_bitonic_sort(keys, len);
     bank_outputs(P, row, keys, red);
@@ -1053,6 +1105,221 @@ __global__ __launch_bounds__(64) void vpet_bank_fallback_kernel(BankArgs P) {
     }
     top.merge();
     bank_outputs(P, row, keys, red);
+}
+
+// --- BF16 contraction -------------------------------------------------------
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+constexpr int kMfmaVox = 256;  // voxels per block: 8 wavefronts x 32 rows
+constexpr int kMfmaRows = 32;  // bank rows per tile
+
+__device__ __forceinline__ uint16_t bf16_rn(float f) {  // round to nearest even
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ void split_bf16(double v, uint16_t& hi, uint16_t& lo) {
+    hi = bf16_rn((float)v);
+    lo = bf16_rn((float)(v - (double)bf16_to_f(hi)));
+}
+
+// Bank operands B_g = [x_g, x_g^2] as bf16 hi/lo parts.
+__global__ __launch_bounds__(256) void vpet_bank_bops_kernel(BankArgs P) {
+    const unsigned g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= P.n_tot) return;
+    const double* xr = P.bank_x + (size_t)g * P.ld;
+    for (int k = 0; k < P.K; ++k) {
+        const double xv = xr[k < P.ld ? k : k - P.ld];
+        uint16_t hi, lo;
+        split_bf16(k < P.ld ? xv : xv * xv, hi, lo);
+        P.bhi[(size_t)g * P.K + k] = hi;
+        P.blo[(size_t)g * P.K + k] = lo;
+    }
+}
+
+// Voxel operands A_v = [-2 w y, w] (bf16 hi/lo) and a_v = sum w y^2 (FP64),
+// so that d_vg = a_v + sum_k A_vk B_gk.  An invalid voxel gets zero operands,
+// a_v = NaN, threshold NaN and count -1.
+template <int LD>
+__global__ __launch_bounds__(256) void vpet_bank_aops_kernel(BankArgs P) {
+    const long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= P.V) return;
+    double Y[LD], Wt[LD];
+    const bool valid = lane_curve<LD, false>(P, row, Y, Wt);
+    uint16_t* ah = P.ahi + (size_t)row * P.K;
+    uint16_t* al = P.alo + (size_t)row * P.K;
+    if (!valid) {
+        for (int k = 0; k < P.K; ++k) ah[k] = al[k] = 0;
+        P.aval[row] = __builtin_nan("");
+        P.tau[row] = __builtin_nanf("");
+        P.cthr[row] = -__builtin_inff();
+        P.cnt[row] = -1;
+        return;
+    }
+    double a = 0.0;
+#pragma unroll
+    for (int f = 0; f < LD; ++f) {
+        a = fma(Wt[f] * Y[f], Y[f], a);
+        uint16_t hi, lo;
+        split_bf16(-2.0 * Wt[f] * Y[f], hi, lo);
+        ah[f] = hi;
+        al[f] = lo;
+        split_bf16(Wt[f], hi, lo);
+        ah[LD + f] = hi;
+        al[LD + f] = lo;
+    }
+    P.aval[row] = a;
+}
+
+// One block = 256 voxels (8 wavefronts, 32 each) against the bank, in tiles of
+// 32 rows staged in LDS (double-buffered).  Per tile and k-step a wavefront
+// issues v_mfma_f32_32x32x16_bf16 on the hi/lo parts: hi*hi + hi*lo + lo*hi
+// gives S ~ sum_k A B.
+//
+// PILOT (the first n_pilot rows): lane l keeps, for each of its 16 voxels, the
+// minimum of S over the rows = l mod 32; the 16th smallest of a voxel's 32
+// column minima, plus a_v, is its threshold tau_v (rounded to fp32), and
+// cthr_v = tau_v - a_v widened by 1e-6 (a_v + |tau_v|), which covers the fp32
+// roundings of tau_v, a_v and cthr_v.  With n_pilot = 5.5 N / n about 4 n bank
+// rows fall below tau_v (order statistics of the column minima); tau_v only
+// steers the work -- the selection certifies or falls back.
+//
+// SCAN (every row): a fourth MFMA gives E ~ sum_k |A_hi| |B_hi|, which bounds
+// the error of S: the dropped lo*lo product and the two splitting residuals
+// (3 * 2^-16 |A||B|) and the FP32 accumulation of 3K products
+// (3K * 2^-24 |A||B|), doubled, and widened by 2^-7 for |hi| vs |A|.  A
+// (voxel, row) pair is a candidate when S - m E <= cthr_v, so every row whose
+// exact distance is <= tau_v is a candidate; the bank rows are appended to the
+// voxel's list (LDS counters, at most cap stored, the full count kept).
+// Lane layout (32x32x16): A row = lane % 32, B column = lane % 32,
+// k = 16 ks + 8 (lane / 32) + e; result r of a lane is row 8 (r/4) + 4 (lane/32) + r%4.
+template <int K, bool PILOT>
+__global__ __launch_bounds__(512) void vpet_bank_mfma_kernel(BankArgs P) {
+    constexpr int KS = K / 16;
+    constexpr int RS = 2 * K + 16;  // LDS row stride (bytes), padded against bank conflicts
+    constexpr float kErr = (float)(2.0 * (3.0 * 0x1p-16 + 3.0 * K * 0x1p-24) * (1.0 + 0x1p-7) * (1.0 + 0x1p-7));
+    __shared__ __align__(16) unsigned char tile[2][2][kMfmaRows * RS];
+    __shared__ unsigned cntl[kMfmaVox];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long vbase = (long long)blockIdx.x * kMfmaVox;
+    if (!PILOT)
+        for (int i = tid; i < kMfmaVox; i += blockDim.x) cntl[i] = 0u;
+
+    const long long arow = vbase + wave * 32 + (lane & 31);
+    bf16x8_t ah[KS], al[KS], aa[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        uint4 h = make_uint4(0, 0, 0, 0), l = make_uint4(0, 0, 0, 0);
+        if (arow < P.V) {
+            const size_t off = (size_t)arow * K + ks * 16 + (lane >> 5) * 8;
+            h = *reinterpret_cast<const uint4*>(P.ahi + off);
+            l = *reinterpret_cast<const uint4*>(P.alo + off);
+        }
+        ah[ks] = __builtin_bit_cast(bf16x8_t, h);
+        al[ks] = __builtin_bit_cast(bf16x8_t, l);
+        const uint4 hab = make_uint4(h.x & 0x7FFF7FFFu, h.y & 0x7FFF7FFFu, h.z & 0x7FFF7FFFu, h.w & 0x7FFF7FFFu);
+        aa[ks] = __builtin_bit_cast(bf16x8_t, hab);
+    }
+    float cth[16];  // SCAN: candidate thresholds; PILOT: running column minima
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const long long v = vbase + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        cth[r] = PILOT ? __builtin_inff() : (v < P.V ? P.cthr[v] : -__builtin_inff());
+    }
+
+    const unsigned n_rows = PILOT ? P.n_pilot : P.n_tot;
+    const unsigned ntiles = (n_rows + kMfmaRows - 1) / kMfmaRows;
+    constexpr int CH = kMfmaRows * K / 8;  // 16-byte chunks per array per tile
+    auto load_tile = [&](unsigned t, int buf) {
+        for (int c = tid; c < 2 * CH; c += blockDim.x) {
+            const int arr = c / CH, rem = c - arr * CH;
+            const int r = rem / (K / 8), c8 = rem - r * (K / 8);
+            const unsigned g = t * kMfmaRows + r;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (g < n_rows) v = *reinterpret_cast<const uint4*>((arr ? P.blo : P.bhi) + (size_t)g * K + c8 * 8);
+            *reinterpret_cast<uint4*>(&tile[buf][arr][r * RS + c8 * 16]) = v;
+        }
+    };
+    load_tile(0, 0);
+    __syncthreads();
+    for (unsigned t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntiles) load_tile(t + 1, buf ^ 1);
+        f32x16_t acc = {}, err = {};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int off = (lane & 31) * RS + (ks * 16 + (lane >> 5) * 8) * 2;
+            const uint4 hb = *reinterpret_cast<const uint4*>(&tile[buf][0][off]);
+            const bf16x8_t bh = __builtin_bit_cast(bf16x8_t, hb);
+            const bf16x8_t bl = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(&tile[buf][1][off]));
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ks], bh, acc, 0, 0, 0);
+            if (!PILOT) {
+                const bf16x8_t ba = __builtin_bit_cast(
+                    bf16x8_t, make_uint4(hb.x & 0x7FFF7FFFu, hb.y & 0x7FFF7FFFu, hb.z & 0x7FFF7FFFu, hb.w & 0x7FFF7FFFu));
+                err = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa[ks], ba, err, 0, 0, 0);
+            }
+        }
+        const unsigned g = t * kMfmaRows + (lane & 31);
+        if (PILOT) {
+            if (g < n_rows) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) cth[r] = fminf(cth[r], acc[r]);
+            }
+        } else {
+            bool any = false;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) any = any || (fmaf(-kErr, err[r], acc[r]) <= cth[r]);
+            if (any && g < n_rows) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int vr = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    if (fmaf(-kErr, err[r], acc[r]) <= cth[r] && vbase + vr < P.V) {
+                        const unsigned pos = atomicAdd(&cntl[vr], 1u);
+                        if (pos < (unsigned)P.cap) P.cand_row[(size_t)(vbase + vr) * P.cap + pos] = g;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (PILOT) {
+        // ascending bitonic sort of each voxel's 32 column minima across the
+        // 32 lanes of its half-wavefront; lane 15 of the half then holds the
+        // 16th smallest
+        const int l = lane & 31;
+#pragma unroll
+        for (int k = 2; k <= 32; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const bool keep_min = ((l & j) == 0) == ((l & k) == 0);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float o = __shfl_xor(cth[r], j, kWave);
+                    cth[r] = keep_min ? fminf(cth[r], o) : fmaxf(cth[r], o);
+                }
+            }
+        }
+        if (l == kBankTopK - 1) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const long long v = vbase + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (v >= P.V) continue;
+                const double a = P.aval[v];
+                if (!(a == a)) continue;  // invalid voxel: marked by the operand kernel
+                const float tau = (float)(a + (double)cth[r]);
+                P.tau[v] = tau;
+                P.cthr[v] = (float)((double)tau + 1e-6 * (a + fabs((double)tau)) - a);
+            }
+        }
+    } else {
+        for (int i = tid; i < kMfmaVox; i += blockDim.x) {
+            const long long v = vbase + i;
+            if (v < P.V && P.cthr[v] > -__builtin_inff()) P.cnt[v] = (int)cntl[i];
+        }
+    }
 }
 
 // ===========================================================================
@@ -1533,6 +1800,10 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     if (!(std::isfinite(o.weight_floor_frac) && o.weight_floor_frac >= 0.0f))
         return fail(VPET_E_ARG, "opts.weight_floor_frac must be finite and >= 0");
     if (o.bank_pilot < 0) return fail(VPET_E_ARG, "opts.bank_pilot must be >= 0");
+    if (o.bank_scan < 0 || o.bank_scan > 2) return fail(VPET_E_ARG, "opts.bank_scan must be 0, 1 or 2");
+    if (o.bank_scan == 2 && o.distance == 1)
+        return fail(VPET_E_ARG, "the bf16 contraction scan needs the L2 distance");
+    const bool use_mfma = o.bank_scan == 2 || (o.bank_scan == 0 && o.distance == 0);
     int64_t n_acc = 0;
     int rc = vpet_abc_accept_count((int64_t)M * n_draws, accept_frac, &n_acc);
     if (rc != VPET_OK) return rc;
@@ -1567,8 +1838,17 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     if (!tacs || !out_moments || !out_model_prob || !bank_theta || !bank_x)
         return fail(VPET_E_ARG, "tacs, bank and output pointers must not be NULL");
     const int64_t n_tot = (int64_t)M * n_draws;
-    const int cap = std::max(256, pow2_at_least(8 * (int)n_acc));
-    int64_t pilot = o.bank_pilot > 0 ? o.bank_pilot : (4 * n_tot + n_acc - 1) / n_acc;
+    // candidate buffer per voxel: the contraction's error margin admits rows
+    // somewhat above the threshold, so it gets twice the room (up to 4096)
+    const int cap = use_mfma ? std::max(512, std::min(4096, pow2_at_least(16 * (int)n_acc)))
+                             : std::max(256, pow2_at_least(8 * (int)n_acc));
+    const size_t cand_bytes = use_mfma ? sizeof(uint32_t) : sizeof(uint64_t);
+    // default pilot: about 4 n bank rows below the threshold (FP64 scan: the
+    // 16th smallest of 4 N / n rows; contraction scan: the 16th smallest of 32
+    // column minima over 5.5 N / n rows)
+    int64_t pilot = o.bank_pilot > 0 ? o.bank_pilot
+                    : use_mfma       ? (11 * n_tot + 2 * n_acc - 1) / (2 * n_acc)
+                                     : (4 * n_tot + n_acc - 1) / n_acc;
     pilot = std::min<int64_t>(pilot, n_tot);
     const int ld = vpet_abc_bank_ld(F);
 
@@ -1597,19 +1877,63 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     if ((rc = upload_blob(*ctx, omega.data(), sizeof(double) * F, st, &dom, slot)) != VPET_OK) return rc;
     A.omega = static_cast<const double*>(dom);
 
-    // voxel chunks bound the candidate scratch to ~2 GiB
-    const long long chunk = std::max<long long>(256, (1LL << 31) / ((long long)cap * 8));
+    // voxel chunks bound the candidate scratch to ~4 GiB
+    const long long chunk = std::max<long long>(256, (1LL << 32) / ((long long)cap * (long long)cand_bytes));
     const long long cv = std::min<long long>(n_voxels, chunk);
+    const int KB = 2 * ld;  // contraction length: [x, x^2] per frame
     char* scratch = nullptr;
     const size_t sz_tau = align256(sizeof(float) * cv), sz_cnt = align256(sizeof(int) * cv);
-    const size_t sz_fb = align256(sizeof(int) * cv), sz_cand = sizeof(uint64_t) * (size_t)cap * cv;
-    hipError_t e = hipMallocAsync((void**)&scratch, sz_tau + sz_cnt + sz_fb + sz_cand, st);
+    const size_t sz_fb = align256(sizeof(int) * cv), sz_cand = align256(cand_bytes * (size_t)cap * cv);
+    const size_t sz_b = use_mfma ? align256(sizeof(uint16_t) * (size_t)KB * n_tot) : 0;
+    const size_t sz_a = use_mfma ? align256(sizeof(uint16_t) * (size_t)KB * cv) : 0;
+    const size_t sz_c = use_mfma ? align256(sizeof(float) * cv) : 0;
+    const size_t sz_av = use_mfma ? align256(sizeof(double) * cv) : 0;
+    hipError_t e = hipMallocAsync((void**)&scratch, sz_tau + sz_cnt + sz_fb + sz_cand + 2 * sz_b + 2 * sz_a + sz_c + sz_av, st);
     if (e != hipSuccess) return fail(VPET_E_NOMEM, "bank scratch: %s", hipGetErrorString(e));
-    A.tau = reinterpret_cast<float*>(scratch);
-    A.cnt = reinterpret_cast<int*>(scratch + sz_tau);
-    A.fallback = reinterpret_cast<int*>(scratch + sz_tau + sz_cnt);
-    A.cand = reinterpret_cast<uint64_t*>(scratch + sz_tau + sz_cnt + sz_fb);
+    char* q = scratch;
+    A.tau = reinterpret_cast<float*>(q);
+    q += sz_tau;
+    A.cnt = reinterpret_cast<int*>(q);
+    q += sz_cnt;
+    A.fallback = reinterpret_cast<int*>(q);
+    q += sz_fb;
+    A.cand = reinterpret_cast<uint64_t*>(q);
+    A.cand_row = reinterpret_cast<uint32_t*>(q);
+    q += sz_cand;
+    A.K = KB;
+    if (use_mfma) {
+        A.bhi = reinterpret_cast<uint16_t*>(q);
+        q += sz_b;
+        A.blo = reinterpret_cast<uint16_t*>(q);
+        q += sz_b;
+        A.ahi = reinterpret_cast<uint16_t*>(q);
+        q += sz_a;
+        A.alo = reinterpret_cast<uint16_t*>(q);
+        q += sz_a;
+        A.cthr = reinterpret_cast<float*>(q);
+        q += sz_c;
+        A.aval = reinterpret_cast<double*>(q);
+    }
     const size_t lds = sizeof(uint64_t) * cap + sizeof(double) * 8 * kMaxWpv;
+    const bool mfma = use_mfma;
+    hipEvent_t tev[2] = {nullptr, nullptr};  // brackets the scan kernel of each chunk
+    if (o.out_scan_ms) {
+        *o.out_scan_ms = 0.0f;
+        for (hipEvent_t& ev : tev) {
+            e = hipEventCreate(&ev);
+            if (e != hipSuccess) rc = hip_fail(e, "hipEventCreate");
+        }
+    }
+    auto mark = [&](int k) {
+        if (!tev[k]) return;
+        const hipError_t me = hipEventRecord(tev[k], st);
+        if (me != hipSuccess && rc == VPET_OK) rc = hip_fail(me, "hipEventRecord");
+    };
+    if (mfma) {
+        hipLaunchKernelGGL(vpet_bank_bops_kernel, dim3((unsigned)((n_tot + 255) / 256)), dim3(256), 0, st, A);
+        e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_fail(e, "bank operand launch");
+    }
     for (long long base = 0; base < n_voxels && rc == VPET_OK; base += cv) {
         BankArgs Q = A;
         Q.V = std::min<long long>(n_voxels - base, cv);
@@ -1621,11 +1945,23 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         Q.out_dist = o.out_accept_dist ? o.out_accept_dist + (size_t)base * n_acc : nullptr;
         Q.out_thr = o.out_threshold ? o.out_threshold + base : nullptr;
         const dim3 lanes((unsigned)((Q.V + 255) / 256)), b256(256), per_voxel((unsigned)Q.V), b64(64);
+        const dim3 mblocks((unsigned)((Q.V + kMfmaVox - 1) / kMfmaVox)), b512(512);
 #define VPET_BANK_LAUNCH(LDV, L1V)                                                                        \
     do {                                                                                                  \
-        hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, true>), lanes, b256, 0, st, Q);               \
-        hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, false>), lanes, b256, 0, st, Q);              \
-        hipLaunchKernelGGL(vpet_bank_select_kernel, per_voxel, b64, lds, st, Q);                          \
+        if (mfma) {                                                                                       \
+            hipLaunchKernelGGL((vpet_bank_aops_kernel<LDV>), lanes, b256, 0, st, Q);                      \
+            hipLaunchKernelGGL((vpet_bank_mfma_kernel<2 * LDV, true>), mblocks, b512, 0, st, Q);          \
+            mark(0);                                                                                      \
+            hipLaunchKernelGGL((vpet_bank_mfma_kernel<2 * LDV, false>), mblocks, b512, 0, st, Q);         \
+            mark(1);                                                                                      \
+            hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, true>), per_voxel, b64, lds, st, Q);    \
+        } else {                                                                                          \
+            hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, true>), lanes, b256, 0, st, Q);           \
+            mark(0);                                                                                      \
+            hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, false>), lanes, b256, 0, st, Q);          \
+            mark(1);                                                                                      \
+            hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, false>), per_voxel, b64, lds, st, Q);   \
+        }                                                                                                 \
         hipLaunchKernelGGL((vpet_bank_fallback_kernel<LDV, L1V>), per_voxel, b64, lds, st, Q);            \
     } while (0)
         const int sel = (ld / 8) * 2 + (o.distance == 1 ? 1 : 0);
@@ -1642,7 +1978,16 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
 #undef VPET_BANK_LAUNCH
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "bank infer launch");
+        if (tev[0] && rc == VPET_OK) {
+            e = hipEventSynchronize(tev[1]);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, tev[0], tev[1]);
+            if (e != hipSuccess) rc = hip_fail(e, "scan timing");
+            *o.out_scan_ms += ms;
+        }
     }
+    for (hipEvent_t ev : tev)
+        if (ev) (void)hipEventDestroy(ev);  // after the waits above: nothing pending
     e = hipFreeAsync(scratch, st);
     if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipFreeAsync");
     e = hipEventRecord(ctx->ev[slot], st);

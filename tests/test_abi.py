@@ -145,4 +145,9 @@ def test_bank_validation_without_gpu(V):
     o = V._binding.Opts()
     o.bank_pilot = -1
     assert ib(opts=o) == V.E_ARG
+    o = V._binding.Opts()
+    o.bank_scan = 3
+    assert ib(opts=o) == V.E_ARG                          # unknown scan
+    o.bank_scan, o.distance = 2, 1
+    assert ib(opts=o) == V.E_ARG                          # bf16 contraction is L2-only
     assert ib(V_=3) == V.E_ARG                            # NULL device pointers

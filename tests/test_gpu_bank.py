@@ -50,12 +50,12 @@ def _bank_moments(models, th_bank, idx, n_draws):
     return mom, prob
 
 
-def _check(y, ft, cp, models, n_draws, p, seed, l1=False, weights=None, bank_pilot=0):
+def _check(y, ft, cp, models, n_draws, p, seed, l1=False, weights=None, bank_pilot=0, scan="auto"):
     import oracle as ora
     boxes = W.box_array(list(models))
     th_g, x_g = V.bank_build(models, boxes, n_draws, seed, cp, ft, H)
     res = V.infer_bank(torch.from_numpy(y).to(DEV), ft, H, cp.size, models, n_draws, p, th_g, x_g,
-                       distance="l1" if l1 else "l2", debug=True, bank_pilot=bank_pilot,
+                       distance="l1" if l1 else "l2", debug=True, bank_pilot=bank_pilot, bank_scan=scan,
                        weights=None if weights is None else torch.from_numpy(weights).to(DEV))
     torch.cuda.synchronize()
     g = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()}
@@ -81,7 +81,7 @@ def _check(y, ft, cp, models, n_draws, p, seed, l1=False, weights=None, bank_pil
         ok = ~np.isnan(ref_mom)
         assert np.allclose(gm[ok], ref_mom[ok], rtol=1e-5, atol=1e-7), f"voxel {v}: moments"
         assert np.allclose(g["model_prob"][v], ref_prob, atol=1e-7, equal_nan=True)
-    print(f"[bank parity] V={y.shape[0]} n={o['n']} voxels with threshold swaps: {swaps}")
+    print(f"[bank parity] scan={scan} V={y.shape[0]} n={o['n']} voxels with threshold swaps: {swaps}")
     return g, o
 
 
@@ -102,15 +102,30 @@ def test_bank_build_matches_oracle():
         assert (xg[:, F:] == 0).all()
 
 
-def test_infer_bank_parity_30_frames():
+SCANS = ["f64", "bf16"]
+
+
+@pytest.mark.parametrize("scan", SCANS)
+def test_infer_bank_parity_30_frames(scan):
+    # 300 voxels: two 256-voxel contraction blocks, the second ragged
     ft, cp, y = _inputs(W.SCHED_30x50, 300)
-    _check(y, ft, cp, [W.M_2TCM_IRR], 20_000, 0.005, 14859)
+    _check(y, ft, cp, [W.M_2TCM_IRR], 20_000, 0.005, 14859, scan=scan)
 
 
+@pytest.mark.parametrize("scan", SCANS)
 @pytest.mark.parametrize("models", [(W.M_2TCM_IRR, W.M_2TCM_REV), (W.M_1TCM, W.M_2TCM_IRR, W.M_2TCM_REV)])
-def test_infer_bank_parity_model_selection(models):
+def test_infer_bank_parity_model_selection(models, scan):
     ft, cp, y = _inputs(W.SCHED_22x60, 120, model=W.M_2TCM_REV, seed=9)
-    _check(y, ft, cp, list(models), 6000, 0.01, 3)
+    _check(y, ft, cp, list(models), 6000, 0.01, 3, scan=scan)
+
+
+def test_infer_bank_scans_agree_on_odd_bank():
+    """Bank size not a multiple of the 32-row tile; frame count 7 (padded to 8)."""
+    ft, cp, y = _inputs([2.0, 3.0, 5.0, 5.0, 10.0, 10.0, 20.0], 333, seed=12)
+    g1, _ = _check(y, ft, cp, [W.M_1TCM, W.M_2TCM_IRR], 4001, 0.01, 8, scan="f64")
+    g2, _ = _check(y, ft, cp, [W.M_1TCM, W.M_2TCM_IRR], 4001, 0.01, 8, scan="bf16")
+    same = sum(set(a.tolist()) == set(b.tolist()) for a, b in zip(g1["accept_idx"], g2["accept_idx"]))
+    assert same >= y.shape[0] - 3
 
 
 def test_infer_bank_l1_weights_and_short_schedule():
@@ -124,13 +139,15 @@ def test_infer_bank_forced_fallback_and_edges():
     ft, cp, y = _inputs(W.SCHED_22x60, 40, seed=7)
     y[5, 2] = np.nan
     y[6] = -1.0
-    # a pilot over the whole bank keeps only 16 candidates per voxel, fewer
-    # than n = 60: every voxel takes the exact fallback path
-    g, _ = _check(y, ft, cp, [W.M_2TCM_IRR], 3000, 0.02, 11, bank_pilot=3000)
-    for v in (5, 6):
-        assert np.isnan(g["moments"][v]).all() and (g["accept_idx"][v] == -1).all()
-    _check(y[:8], ft, cp, [W.M_2TCM_IRR, W.M_2TCM_REV], 150, 1.0, 5)       # p = 1: n = N = 300
-    _check(y[:8], ft, cp, [W.M_2TCM_IRR], 7, 0.2, 5)                        # tiny bank, n = 1
+    # a pilot over the whole bank leaves only about 16-25 rows below each
+    # voxel's threshold, fewer than n = 60: (nearly) every voxel takes the
+    # exact fallback path
+    for scan in SCANS:
+        g, _ = _check(y, ft, cp, [W.M_2TCM_IRR], 3000, 0.02, 11, bank_pilot=3000, scan=scan)
+        for v in (5, 6):
+            assert np.isnan(g["moments"][v]).all() and (g["accept_idx"][v] == -1).all()
+        _check(y[:8], ft, cp, [W.M_2TCM_IRR, W.M_2TCM_REV], 150, 1.0, 5, scan=scan)  # p = 1: n = N = 300
+        _check(y[:8], ft, cp, [W.M_2TCM_IRR], 7, 0.2, 5, scan=scan)                   # tiny bank, n = 1
 
 
 def test_infer_bank_limits():
@@ -139,6 +156,10 @@ def test_infer_bank_limits():
     with pytest.raises(V.VpetError) as e:
         V.infer_bank(torch.from_numpy(y).to(DEV), ft, H, cp.size, [W.M_2TCM_IRR], 1000, 0.6, th, x)
     assert e.value.status == V.E_LIMIT
+    with pytest.raises(V.VpetError) as e:
+        V.infer_bank(torch.from_numpy(y).to(DEV), ft, H, cp.size, [W.M_2TCM_IRR], 1000, 0.01, th, x,
+                     distance="l1", bank_scan="bf16")
+    assert e.value.status == V.E_ARG
     ft40 = W.frame_times([1.0] * 40)
     with pytest.raises(V.VpetError) as e:
         V.bank_build([W.M_2TCM_IRR], W.box_array([W.M_2TCM_IRR]), 10, 1, W.grid(H, 40.0)[1], ft40, H)
