@@ -129,6 +129,11 @@ typedef struct {
      * pair) with HIP events on hip_stream, waits for them, and writes the
      * summed kernel time in milliseconds here.  Makes the call synchronous. */
     float* out_scan_ms;
+    /* Shared-bank form only: host pointer; when set, receives the number of
+     * voxels whose candidate list could not certify the accepted set and
+     * that were redone by the exact pass over the whole bank.  Makes the call
+     * synchronous. */
+    int64_t* out_fallback_voxels;
 } vpet_abc_opts;
 
 /*

@@ -44,7 +44,8 @@ class Opts(ctypes.Structure):
                 ("out_accept_idx", ctypes.c_void_p), ("out_accept_dist", ctypes.c_void_p),
                 ("out_threshold", ctypes.c_void_p), ("voxel_offset", ctypes.c_int64),
                 ("waves_per_voxel", ctypes.c_int32), ("bank_pilot", ctypes.c_int64),
-                ("bank_scan", ctypes.c_int32), ("out_scan_ms", ctypes.POINTER(ctypes.c_float))]
+                ("bank_scan", ctypes.c_int32), ("out_scan_ms", ctypes.POINTER(ctypes.c_float)),
+                ("out_fallback_voxels", ctypes.POINTER(ctypes.c_int64))]
 
 
 def _load():
@@ -259,14 +260,19 @@ def infer_bank(tacs, frame_times, dt: float, n_nodes: int, models, n_draws: int,
     o.bank_pilot = int(bank_pilot)
     o.bank_scan = {"auto": 0, "f64": 1, "bf16": 2}[bank_scan]
     scan_ms = ctypes.c_float(0.0)
+    n_fallback = ctypes.c_int64(0)
     if time_scan:
         o.out_scan_ms = ctypes.pointer(scan_ms)
+    if debug:
+        o.out_fallback_voxels = ctypes.pointer(n_fallback)
     _check(lib.vpet_abc_infer_bank(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p), Grid(float(dt), int(n_nodes), F),
                                    mask, int(n_draws), float(accept_frac), _ptr(bank_theta), _ptr(bank_x),
                                    _ptr(res["moments"]), _ptr(res["model_prob"]), ctypes.byref(o), _stream(stream)))
     res["n"] = n
     if time_scan:
         res["scan_ms"] = float(scan_ms.value)
+    if debug:
+        res["fallback_voxels"] = int(n_fallback.value)
     return res
 
 

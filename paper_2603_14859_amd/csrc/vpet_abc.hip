@@ -804,7 +804,7 @@ struct BankArgs {
     const double* bank_x;   // [N][ld] frame averages (zero padding)
     const float* bank_theta;
     double floor_frac;
-    int F, ld, l1, M, cap;
+    int F, ld, l1, M, cap, fb_cap;
     long long V;            // voxels in this launch
     unsigned n_tot, n_draws, n_acc, n_pilot;
     int kinds[kMaxModels];
@@ -812,7 +812,8 @@ struct BankArgs {
     int* cnt;               // [V] candidates found (may exceed cap)
     uint64_t* cand;         // [V][cap] candidate keys (FP64 scan)
     uint32_t* cand_row;     // [V][cap] candidate bank rows (contraction scan; same memory)
-    int* fallback;          // [V] 1 if the candidate set cannot certify the top n
+    int* fb_list;           // [V] voxels whose candidate list cannot certify the top n
+    unsigned* fb_count;     // [1] entries in fb_list
     // BF16 contraction (L2 only): d = a_v + sum_k A_vk B_gk with
     // A_v = [-2 w y, w], B_g = [x, x^2], each split into bf16 hi + lo parts
     int K;                  // 2 * ld
@@ -863,6 +864,26 @@ __device__ __forceinline__ bool lane_curve(const BankArgs& P, long long row, dou
 // its values are scalar operands.
 template <int LD, bool L1>
 __device__ __forceinline__ double bank_distance(cdp xr, const double (&Y)[LD], const double (&Wt)[LD]) {
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int f = 0; f < LD; f += 2) {
+        const double r0 = Y[f] - xr[f];
+        const double r1 = Y[f + 1] - xr[f + 1];
+        if (L1) {
+            d0 = fma(Wt[f], fabs(r0), d0);
+            d1 = fma(Wt[f + 1], fabs(r1), d1);
+        } else {
+            d0 = fma(Wt[f] * r0, r0, d0);
+            d1 = fma(Wt[f + 1] * r1, r1, d1);
+        }
+    }
+    return d0 + d1;
+}
+
+// The same distance from a per-lane row pointer (identical operation order, so
+// every path ranks a row with the same FP64 value).
+template <int LD, bool L1>
+__device__ __forceinline__ double row_distance(const double* xr, const double (&Y)[LD], const double (&Wt)[LD]) {
     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
     for (int f = 0; f < LD; f += 2) {
@@ -1014,19 +1035,18 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
     if (row >= P.V) return;
     const int c = P.cnt[row];
     if (c < 0) {
-        if (threadIdx.x == 0) P.fallback[row] = 0;
         bank_invalid(P, row);
         return;
     }
     if (c < (int)P.n_acc || c > P.cap) {
-        if (threadIdx.x == 0) P.fallback[row] = 1;
+        if (threadIdx.x == 0) P.fb_list[atomicAdd(P.fb_count, 1u)] = (int)row;
         return;
     }
     const float tau = P.tau[row];
     int below = 0;
     if (RECOMPUTE) {
-        // exact FP64 distances of the candidate rows; keys above the
-        // threshold are dropped, the rest packed to the front
+        // exact FP64 distances of the candidate rows (a row per lane); keys
+        // above the threshold are dropped, the rest packed to the front
         double Y[LD], Wt[LD];
         lane_curve<LD, L1>(P, row, Y, Wt);  // every lane holds the voxel
         const uint32_t* src = P.cand_row + (size_t)row * P.cap;
@@ -1035,15 +1055,7 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
             uint64_t key = kNoKey;
             if (j < c) {
                 const uint32_t g = src[j];
-                const double* xr = P.bank_x + (size_t)g * LD;
-                double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-                for (int f = 0; f < LD; f += 2) {
-                    const double r0 = Y[f] - xr[f], r1 = Y[f + 1] - xr[f + 1];
-                    d0 = L1 ? fma(Wt[f], fabs(r0), d0) : fma(Wt[f] * r0, r0, d0);
-                    d1 = L1 ? fma(Wt[f + 1], fabs(r1), d1) : fma(Wt[f + 1] * r1, r1, d1);
-                }
-                const float fd = key_dist(d0 + d1);
+                const float fd = key_dist(row_distance<LD, L1>(P.bank_x + (size_t)g * LD, Y, Wt));
                 key = ((uint64_t)__float_as_uint(fd) << 32) | g;
             }
             const bool keep = j < c && __uint_as_float((uint32_t)(key >> 32)) <= tau;
@@ -1057,10 +1069,9 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
         below = c;
     }
     if (below < (int)P.n_acc) {
-        if (threadIdx.x == 0) P.fallback[row] = 1;
+        if (threadIdx.x == 0) P.fb_list[atomicAdd(P.fb_count, 1u)] = (int)row;
         return;
     }
-    if (threadIdx.x == 0) P.fallback[row] = 0;
     const int len = below <= 1 ? 2 : (1 << (32 - __clz(below - 1)));
     for (int j = below + lane_id(); j < len; j += kWave) keys[j] = kNoKey;
     wave_lds_sync();
@@ -1068,43 +1079,49 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
     bank_outputs(P, row, keys, red);
 }
 
-// Exact fallback: one wavefront per marked voxel streams every bank row
-// through a running top-n (the per-voxel selection of the infer kernel).
+// Exact fallback: one block per listed voxel streams every bank row; each
+// wavefront keeps a running top-n of its share of the rows (the per-voxel
+// selection of the infer kernel, in fb_cap keys), and a block-wide bitonic
+// sort merges the shares.  A fixed grid walks the list, whose length the
+// select kernel left in fb_count.
 template <int LD, bool L1>
-__global__ __launch_bounds__(64) void vpet_bank_fallback_kernel(BankArgs P) {
+__global__ __launch_bounds__(512) void vpet_bank_fallback_kernel(BankArgs P) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const long long row = blockIdx.x;
-    if (row >= P.V || P.fallback[row] == 0) return;
-    uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
-    double* red = reinterpret_cast<double*>(keys + P.cap);
-    double Y[LD], Wt[LD];
-    lane_curve<LD, L1>(P, row, Y, Wt);  // every lane holds the same voxel
-    TopN top;
-    top.keys = keys;
-    top.n = (int)P.n_acc;
-    top.cap = P.cap;
-    top.nbuf = 0;
-    top.tau = kNoKey;
-    for (int j = lane_id(); j < P.cap; j += kWave) keys[j] = kNoKey;
-    wave_lds_sync();
-    const double* X = P.bank_x;
-    for (unsigned g0 = 0; g0 < P.n_tot; g0 += kWave) {
-        const unsigned g = g0 + (unsigned)lane_id();
-        uint64_t key[1] = {kNoKey};
-        if (g < P.n_tot) {
-            const double* xr = X + (size_t)g * LD;
-            double d0 = 0.0;
-#pragma unroll
-            for (int f = 0; f < LD; ++f) {
-                const double r = Y[f] - xr[f];
-                d0 = L1 ? fma(Wt[f], fabs(r), d0) : fma(Wt[f] * r, r, d0);
+    const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6;
+    uint64_t* keys_all = reinterpret_cast<uint64_t*>(lds);
+    double* red = reinterpret_cast<double*>(keys_all + (size_t)nw * P.fb_cap);
+    const unsigned n_fb = *P.fb_count;
+    for (unsigned item = blockIdx.x; item < n_fb; item += gridDim.x) {
+        const long long row = P.fb_list[item];
+        double Y[LD], Wt[LD];
+        lane_curve<LD, L1>(P, row, Y, Wt);  // every lane holds the same voxel
+        TopN top;
+        top.keys = keys_all + (size_t)wave * P.fb_cap;
+        top.n = (int)P.n_acc;
+        top.cap = P.fb_cap;
+        top.nbuf = 0;
+        top.tau = kNoKey;
+        __syncthreads();  // the previous voxel's outputs have read the keys
+        for (int j = lane_id(); j < P.fb_cap; j += kWave) top.keys[j] = kNoKey;
+        wave_lds_sync();
+        for (unsigned g0 = (unsigned)wave * kWave; g0 < P.n_tot; g0 += (unsigned)nw * kWave) {
+            const unsigned g = g0 + (unsigned)lane_id();
+            uint64_t key[1] = {kNoKey};
+            if (g < P.n_tot) {
+                const float fd = key_dist(row_distance<LD, L1>(P.bank_x + (size_t)g * LD, Y, Wt));
+                key[0] = ((uint64_t)__float_as_uint(fd) << 32) | g;
             }
-            key[0] = ((uint64_t)__float_as_uint(key_dist(d0)) << 32) | g;
+            top.insert(key);
         }
-        top.insert(key);
+        top.merge();
+        __syncthreads();
+        if (nw > 1) block_bitonic_sort(keys_all, nw * P.fb_cap);
+        bank_outputs(P, row, keys_all, red);
     }
-    top.merge();
-    bank_outputs(P, row, keys, red);
+}
+
+__global__ void vpet_bank_reset_kernel(BankArgs P) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *P.fb_count = 0u;
 }
 
 // --- BF16 contraction -------------------------------------------------------
@@ -1158,9 +1175,11 @@ __global__ __launch_bounds__(256) void vpet_bank_aops_kernel(BankArgs P) {
         return;
     }
     double a = 0.0;
+    bool wneg = false;
 #pragma unroll
     for (int f = 0; f < LD; ++f) {
         a = fma(Wt[f] * Y[f], Y[f], a);
+        wneg = wneg || !(Wt[f] >= 0.0);
         uint16_t hi, lo;
         split_bf16(-2.0 * Wt[f] * Y[f], hi, lo);
         ah[f] = hi;
@@ -1169,45 +1188,64 @@ __global__ __launch_bounds__(256) void vpet_bank_aops_kernel(BankArgs P) {
         ah[LD + f] = hi;
         al[LD + f] = lo;
     }
-    P.aval[row] = a;
+    // the error bound assumes w >= 0: otherwise a_v = -inf makes every row a
+    // candidate (the selection is then exact or falls back)
+    P.aval[row] = wneg ? -__builtin_inf() : a;
+}
+
+// Error of the split contraction.  With A = A_hi + A_lo + e_A (|A_lo| and
+// |e_A|/|A_hi + A_lo| at most 2^-8 and 2^-16 relative) and likewise B, the sum
+// of the three products hi*hi + hi*lo + lo*hi differs from sum_k A_k B_k by the
+// dropped lo*lo product and the two residual terms, at most 3 * 2^-16 * E with
+// E = sum_k |A_k||B_k|; the products of bf16 values are exact in FP32 and
+// their FP32 accumulation (3K terms) adds at most 3K * 2^-24 * E under round to
+// nearest.  The factor 2 covers truncating accumulation in the matrix cores and
+// the second-order terms.
+template <int K>
+__host__ __device__ constexpr double contraction_rel_err() {
+    return 2.0 * (3.0 * 0x1p-16 + 3.0 * K * 0x1p-24);
 }
 
 // One block = 256 voxels (8 wavefronts, 32 each) against the bank, in tiles of
-// 32 rows staged in LDS (double-buffered).  Per tile and k-step a wavefront
-// issues v_mfma_f32_32x32x16_bf16 on the hi/lo parts: hi*hi + hi*lo + lo*hi
-// gives S ~ sum_k A B.
+// 64 rows staged in LDS (double-buffered; the global loads of tile t+2 are
+// issued while tile t is multiplied and land in LDS one tile later; two
+// independent 32-row accumulators per wavefront).  Per tile
+// and k-step a wavefront issues v_mfma_f32_32x32x16_bf16 on the hi/lo parts:
+// hi*hi + hi*lo + lo*hi gives S ~ sum_k A B.
 //
 // PILOT (the first n_pilot rows): lane l keeps, for each of its 16 voxels, the
 // minimum of S over the rows = l mod 32; the 16th smallest of a voxel's 32
-// column minima, plus a_v, is its threshold tau_v (rounded to fp32), and
-// cthr_v = tau_v - a_v widened by 1e-6 (a_v + |tau_v|), which covers the fp32
-// roundings of tau_v, a_v and cthr_v.  With n_pilot = 5.5 N / n about 4 n bank
-// rows fall below tau_v (order statistics of the column minima); tau_v only
-// steers the work -- the selection certifies or falls back.
+// column minima, plus a_v, is its threshold tau_v (rounded to fp32).  With
+// n_pilot = 5.5 N / n about 4 n bank rows fall below tau_v (order statistics of
+// the column minima); tau_v only steers the work -- the selection certifies or
+// falls back.  The candidate threshold is
+//   cthr_v = tau_v - a_v + m E_tau + 1e-6 (a_v + |tau_v|),
+// m = contraction_rel_err, E_tau = 3 a_v + 4 sqrt(a_v tau_v) + tau_v: for any
+// pair with exact distance d <= tau_v, |x| <= |y| + |y - x| and Cauchy-Schwarz
+// give E = sum w (2|y||x| + x^2) <= 3 a_v + 4 sqrt(a_v d) + d <= E_tau, so its
+// computed S is at most S + m E_tau <= cthr_v; the last term covers the fp32
+// roundings of tau_v, a_v and cthr_v.
 //
-// SCAN (every row): a fourth MFMA gives E ~ sum_k |A_hi| |B_hi|, which bounds
-// the error of S: the dropped lo*lo product and the two splitting residuals
-// (3 * 2^-16 |A||B|) and the FP32 accumulation of 3K products
-// (3K * 2^-24 |A||B|), doubled, and widened by 2^-7 for |hi| vs |A|.  A
-// (voxel, row) pair is a candidate when S - m E <= cthr_v, so every row whose
-// exact distance is <= tau_v is a candidate; the bank rows are appended to the
-// voxel's list (LDS counters, at most cap stored, the full count kept).
+// SCAN (every row): a (voxel, row) pair is a candidate when S <= cthr_v, so
+// every row whose exact distance is <= tau_v is a candidate; the bank rows are
+// appended to the voxel's list (LDS counters, at most cap stored, the full
+// count kept).
 // Lane layout (32x32x16): A row = lane % 32, B column = lane % 32,
 // k = 16 ks + 8 (lane / 32) + e; result r of a lane is row 8 (r/4) + 4 (lane/32) + r%4.
 template <int K, bool PILOT>
-__global__ __launch_bounds__(512) void vpet_bank_mfma_kernel(BankArgs P) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void vpet_bank_mfma_kernel(BankArgs P) {
     constexpr int KS = K / 16;
-    constexpr int RS = 2 * K + 16;  // LDS row stride (bytes), padded against bank conflicts
-    constexpr float kErr = (float)(2.0 * (3.0 * 0x1p-16 + 3.0 * K * 0x1p-24) * (1.0 + 0x1p-7) * (1.0 + 0x1p-7));
-    __shared__ __align__(16) unsigned char tile[2][2][kMfmaRows * RS];
-    __shared__ unsigned cntl[kMfmaVox];
+    constexpr int RS = 2 * K + 16;        // LDS row stride (bytes), padded against bank conflicts
+    constexpr int TR = 2 * kMfmaRows;     // bank rows per tile: two 32-row halves
+    constexpr int CA = TR * K / 8;        // 16-byte chunks per array (hi or lo) per tile
+    constexpr int CPT = (2 * CA + 511) / 512;  // chunks per thread and tile
+    static_assert(CA % 64 == 0 && CPT <= 2, "whole wavefronts per array, at most two chunks per thread");
+    __shared__ __align__(16) unsigned char tile[2][2][TR * RS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long vbase = (long long)blockIdx.x * kMfmaVox;
-    if (!PILOT)
-        for (int i = tid; i < kMfmaVox; i += blockDim.x) cntl[i] = 0u;
 
     const long long arow = vbase + wave * 32 + (lane & 31);
-    bf16x8_t ah[KS], al[KS], aa[KS];
+    bf16x8_t ah[KS], al[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         uint4 h = make_uint4(0, 0, 0, 0), l = make_uint4(0, 0, 0, 0);
@@ -1218,71 +1256,115 @@ __global__ __launch_bounds__(512) void vpet_bank_mfma_kernel(BankArgs P) {
         }
         ah[ks] = __builtin_bit_cast(bf16x8_t, h);
         al[ks] = __builtin_bit_cast(bf16x8_t, l);
-        const uint4 hab = make_uint4(h.x & 0x7FFF7FFFu, h.y & 0x7FFF7FFFu, h.z & 0x7FFF7FFFu, h.w & 0x7FFF7FFFu);
-        aa[ks] = __builtin_bit_cast(bf16x8_t, hab);
     }
-    float cth[16];  // SCAN: candidate thresholds; PILOT: running column minima
+    // result r of this lane belongs to voxel 8 (r/4) + 4 (lane/32) + r%4 of the
+    // wavefront.  SCAN: that voxel's candidate threshold; PILOT: the running
+    // minimum of S over this lane's column.
+    float cth[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const long long v = vbase + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         cth[r] = PILOT ? __builtin_inff() : (v < P.V ? P.cthr[v] : -__builtin_inff());
     }
+    // SCAN: candidates found so far for voxel (lane % 32) of this wavefront.
+    // A wavefront owns its 32 voxels, so the counts live in one register and
+    // are read with readlane and updated by lane (no atomics).
+    unsigned cntv = 0u;
+    uint32_t* wcand = P.cand_row + (size_t)(vbase + wave * 32) * P.cap;
+    const uint32_t lt = (1u << (lane & 31)) - 1u;  // lanes below mine in my half-wave
 
     const unsigned n_rows = PILOT ? P.n_pilot : P.n_tot;
-    const unsigned ntiles = (n_rows + kMfmaRows - 1) / kMfmaRows;
-    constexpr int CH = kMfmaRows * K / 8;  // 16-byte chunks per array per tile
-    auto load_tile = [&](unsigned t, int buf) {
-        for (int c = tid; c < 2 * CH; c += blockDim.x) {
-            const int arr = c / CH, rem = c - arr * CH;
-            const int r = rem / (K / 8), c8 = rem - r * (K / 8);
-            const unsigned g = t * kMfmaRows + r;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (g < n_rows) v = *reinterpret_cast<const uint4*>((arr ? P.blo : P.bhi) + (size_t)g * K + c8 * 8);
-            *reinterpret_cast<uint4*>(&tile[buf][arr][r * RS + c8 * 16]) = v;
+    const unsigned ntiles = (n_rows + TR - 1) / TR;
+    // this thread's 16-byte chunks of a tile: array (hi/lo; CA is a multiple of
+    // 64, so the array is the same for the whole wavefront), row, column
+    const uint16_t* c_src[CPT];
+    int c_row[CPT], c_dst[CPT];
+    bool c_has[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int c = tid + 512 * u;
+        c_has[u] = c < 2 * CA;
+        const int arr = __builtin_amdgcn_readfirstlane(c / CA), rem = c - arr * CA;
+        c_row[u] = rem / (K / 8);
+        const int col = rem - c_row[u] * (K / 8);
+        c_src[u] = (arr ? P.blo : P.bhi) + col * 8;
+        c_dst[u] = arr * TR * RS + c_row[u] * RS + col * 16;
+    }
+    uint4 pre[CPT];
+    auto fetch = [&](unsigned t) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const unsigned g = t * TR + c_row[u];
+            pre[u] = make_uint4(0, 0, 0, 0);
+            if (c_has[u] && g < n_rows) pre[u] = *reinterpret_cast<const uint4*>(c_src[u] + (size_t)g * K);
         }
     };
-    load_tile(0, 0);
-    __syncthreads();
-    for (unsigned t = 0; t < ntiles; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < ntiles) load_tile(t + 1, buf ^ 1);
-        f32x16_t acc = {}, err = {};
+    auto stash = [&](int buf) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int off = (lane & 31) * RS + (ks * 16 + (lane >> 5) * 8) * 2;
-            const uint4 hb = *reinterpret_cast<const uint4*>(&tile[buf][0][off]);
-            const bf16x8_t bh = __builtin_bit_cast(bf16x8_t, hb);
-            const bf16x8_t bl = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(&tile[buf][1][off]));
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ks], bh, acc, 0, 0, 0);
-            if (!PILOT) {
-                const bf16x8_t ba = __builtin_bit_cast(
-                    bf16x8_t, make_uint4(hb.x & 0x7FFF7FFFu, hb.y & 0x7FFF7FFFu, hb.z & 0x7FFF7FFFu, hb.w & 0x7FFF7FFFu));
-                err = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa[ks], ba, err, 0, 0, 0);
-            }
-        }
-        const unsigned g = t * kMfmaRows + (lane & 31);
+        for (int u = 0; u < CPT; ++u)
+            if (c_has[u]) *reinterpret_cast<uint4*>(&tile[buf][0][0] + c_dst[u]) = pre[u];
+    };
+    // screen one 32-row half: r-th results against the thresholds, passing
+    // rows appended to their voxel's list
+    auto screen = [&](const f32x16_t& acc, unsigned g0) {
+        const unsigned g = g0 + (lane & 31);
         if (PILOT) {
             if (g < n_rows) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) cth[r] = fminf(cth[r], acc[r]);
             }
-        } else {
-            bool any = false;
+            return;
+        }
+        const uint64_t live = __builtin_amdgcn_ballot_w64(g < n_rows);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) any = any || (fmaf(-kErr, err[r], acc[r]) <= cth[r]);
-            if (any && g < n_rows) {
+        for (int r = 0; r < 16; ++r) {
+            const uint64_t b = __builtin_amdgcn_ballot_w64(acc[r] <= cth[r]) & live;
+            if (b == 0ull) continue;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int vr = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    if (fmaf(-kErr, err[r], acc[r]) <= cth[r] && vbase + vr < P.V) {
-                        const unsigned pos = atomicAdd(&cntl[vr], 1u);
-                        if (pos < (unsigned)P.cap) P.cand_row[(size_t)(vbase + vr) * P.cap + pos] = g;
-                    }
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t bits = (uint32_t)(b >> (32 * h));
+                if (bits == 0u) continue;
+                const int i = 8 * (r >> 2) + 4 * h + (r & 3);  // voxel of this (r, half) in the wave
+                const unsigned base = __builtin_amdgcn_readlane(cntv, i);
+                if ((lane >> 5) == h && ((bits >> (lane & 31)) & 1u)) {
+                    const unsigned pos = base + (unsigned)__popc(bits & lt);
+                    if (pos < (unsigned)P.cap) wcand[(unsigned)i * (unsigned)P.cap + pos] = g;
                 }
+                cntv = lane == i ? base + (unsigned)__popc(bits) : cntv;
             }
         }
+    };
+    fetch(0);
+    stash(0);
+    if (ntiles > 1) fetch(1);
+    __syncthreads();
+    for (unsigned t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntiles) {
+            // tile t+1 (fetched one iteration ago) into the other buffer, which
+            // every wave finished reading before the last barrier
+            stash(buf ^ 1);
+            if (t + 2 < ntiles) fetch(t + 2);
+        }
+        f32x16_t acc0 = {}, acc1 = {};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int off = (lane & 31) * RS + (ks * 16 + (lane >> 5) * 8) * 2;
+            const unsigned char* hi = &tile[buf][0][0];
+            const unsigned char* lo = hi + TR * RS;
+            const bf16x8_t bh0 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(hi + off));
+            const bf16x8_t bl0 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(lo + off));
+            const bf16x8_t bh1 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(hi + 32 * RS + off));
+            const bf16x8_t bl1 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(lo + 32 * RS + off));
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bh0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bh1, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bl0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bl1, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ks], bh0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ks], bh1, acc1, 0, 0, 0);
+        }
+        screen(acc0, t * TR);
+        screen(acc1, t * TR + kMfmaRows);
         __syncthreads();
     }
     if (PILOT) {
@@ -1303,22 +1385,28 @@ __global__ __launch_bounds__(512) void vpet_bank_mfma_kernel(BankArgs P) {
             }
         }
         if (l == kBankTopK - 1) {
+            constexpr double m = contraction_rel_err<K>();
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const long long v = vbase + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                 if (v >= P.V) continue;
                 const double a = P.aval[v];
                 if (!(a == a)) continue;  // invalid voxel: marked by the operand kernel
+                if (a < 0.0) {            // negative weights: no bound, every row a candidate
+                    P.tau[v] = __builtin_inff();
+                    P.cthr[v] = __builtin_inff();
+                    continue;
+                }
                 const float tau = (float)(a + (double)cth[r]);
+                const double tp = fmax((double)tau, 0.0);
+                const double e_tau = 3.0 * a + 4.0 * sqrt(a * tp) + tp;
                 P.tau[v] = tau;
-                P.cthr[v] = (float)((double)tau + 1e-6 * (a + fabs((double)tau)) - a);
+                P.cthr[v] = (float)((double)tau - a + m * e_tau + 1e-6 * (a + fabs((double)tau)));
             }
         }
-    } else {
-        for (int i = tid; i < kMfmaVox; i += blockDim.x) {
-            const long long v = vbase + i;
-            if (v < P.V && P.cthr[v] > -__builtin_inff()) P.cnt[v] = (int)cntl[i];
-        }
+    } else if (lane < 32) {
+        const long long v = vbase + wave * 32 + lane;
+        if (v < P.V && P.cthr[v] > -__builtin_inff()) P.cnt[v] = (int)cntv;
     }
 }
 
@@ -1883,7 +1971,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     const int KB = 2 * ld;  // contraction length: [x, x^2] per frame
     char* scratch = nullptr;
     const size_t sz_tau = align256(sizeof(float) * cv), sz_cnt = align256(sizeof(int) * cv);
-    const size_t sz_fb = align256(sizeof(int) * cv), sz_cand = align256(cand_bytes * (size_t)cap * cv);
+    const size_t sz_fb = align256(sizeof(int) * cv) + 256, sz_cand = align256(cand_bytes * (size_t)cap * cv);
     const size_t sz_b = use_mfma ? align256(sizeof(uint16_t) * (size_t)KB * n_tot) : 0;
     const size_t sz_a = use_mfma ? align256(sizeof(uint16_t) * (size_t)KB * cv) : 0;
     const size_t sz_c = use_mfma ? align256(sizeof(float) * cv) : 0;
@@ -1895,7 +1983,8 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     q += sz_tau;
     A.cnt = reinterpret_cast<int*>(q);
     q += sz_cnt;
-    A.fallback = reinterpret_cast<int*>(q);
+    A.fb_count = reinterpret_cast<unsigned*>(q);
+    A.fb_list = reinterpret_cast<int*>(q + 256);
     q += sz_fb;
     A.cand = reinterpret_cast<uint64_t*>(q);
     A.cand_row = reinterpret_cast<uint32_t*>(q);
@@ -1915,7 +2004,15 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         A.aval = reinterpret_cast<double*>(q);
     }
     const size_t lds = sizeof(uint64_t) * cap + sizeof(double) * 8 * kMaxWpv;
+    // fallback blocks: up to 8 wavefronts, each with its own pow2(n + 128)-key
+    // top-n, within 48 KB of LDS
+    const int fb_cap = pow2_at_least((int)n_acc + 2 * kWave);
+    int fb_waves = 8;
+    while (fb_waves > 1 && (size_t)fb_waves * fb_cap * sizeof(uint64_t) > 48 * 1024) fb_waves >>= 1;
+    const size_t fb_lds = sizeof(uint64_t) * (size_t)fb_waves * fb_cap + sizeof(double) * 8 * fb_waves;
+    A.fb_cap = fb_cap;
     const bool mfma = use_mfma;
+    if (o.out_fallback_voxels) *o.out_fallback_voxels = 0;
     hipEvent_t tev[2] = {nullptr, nullptr};  // brackets the scan kernel of each chunk
     if (o.out_scan_ms) {
         *o.out_scan_ms = 0.0f;
@@ -1946,8 +2043,10 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         Q.out_thr = o.out_threshold ? o.out_threshold + base : nullptr;
         const dim3 lanes((unsigned)((Q.V + 255) / 256)), b256(256), per_voxel((unsigned)Q.V), b64(64);
         const dim3 mblocks((unsigned)((Q.V + kMfmaVox - 1) / kMfmaVox)), b512(512);
+        const dim3 fb_grid((unsigned)std::min<long long>(Q.V, 2048)), fb_block(64 * fb_waves), one(1);
 #define VPET_BANK_LAUNCH(LDV, L1V)                                                                        \
     do {                                                                                                  \
+        hipLaunchKernelGGL(vpet_bank_reset_kernel, one, one, 0, st, Q);                                   \
         if (mfma) {                                                                                       \
             hipLaunchKernelGGL((vpet_bank_aops_kernel<LDV>), lanes, b256, 0, st, Q);                      \
             hipLaunchKernelGGL((vpet_bank_mfma_kernel<2 * LDV, true>), mblocks, b512, 0, st, Q);          \
@@ -1962,7 +2061,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
             mark(1);                                                                                      \
             hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, false>), per_voxel, b64, lds, st, Q);   \
         }                                                                                                 \
-        hipLaunchKernelGGL((vpet_bank_fallback_kernel<LDV, L1V>), per_voxel, b64, lds, st, Q);            \
+        hipLaunchKernelGGL((vpet_bank_fallback_kernel<LDV, L1V>), fb_grid, fb_block, fb_lds, st, Q);      \
     } while (0)
         const int sel = (ld / 8) * 2 + (o.distance == 1 ? 1 : 0);
         switch (sel) {
@@ -1978,6 +2077,13 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
 #undef VPET_BANK_LAUNCH
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "bank infer launch");
+        if (o.out_fallback_voxels && rc == VPET_OK) {
+            unsigned nfb = 0;
+            e = hipMemcpyAsync(&nfb, Q.fb_count, sizeof nfb, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) rc = hip_fail(e, "fallback count");
+            *o.out_fallback_voxels += nfb;
+        }
         if (tev[0] && rc == VPET_OK) {
             e = hipEventSynchronize(tev[1]);
             float ms = 0.0f;

@@ -81,7 +81,8 @@ def _check(y, ft, cp, models, n_draws, p, seed, l1=False, weights=None, bank_pil
         ok = ~np.isnan(ref_mom)
         assert np.allclose(gm[ok], ref_mom[ok], rtol=1e-5, atol=1e-7), f"voxel {v}: moments"
         assert np.allclose(g["model_prob"][v], ref_prob, atol=1e-7, equal_nan=True)
-    print(f"[bank parity] scan={scan} V={y.shape[0]} n={o['n']} voxels with threshold swaps: {swaps}")
+    print(f"[bank parity] scan={scan} V={y.shape[0]} n={o['n']} voxels with threshold swaps: {swaps}, "
+          f"exact fallbacks: {g['fallback_voxels']}")
     return g, o
 
 
@@ -146,6 +147,10 @@ def test_infer_bank_forced_fallback_and_edges():
         g, _ = _check(y, ft, cp, [W.M_2TCM_IRR], 3000, 0.02, 11, bank_pilot=3000, scan=scan)
         for v in (5, 6):
             assert np.isnan(g["moments"][v]).all() and (g["accept_idx"][v] == -1).all()
+        if scan == "f64":  # exactly 16 rows below each threshold: every valid voxel falls back
+            assert g["fallback_voxels"] == y.shape[0] - 2
+        else:
+            assert g["fallback_voxels"] > (y.shape[0] - 2) // 2
         _check(y[:8], ft, cp, [W.M_2TCM_IRR, W.M_2TCM_REV], 150, 1.0, 5, scan=scan)  # p = 1: n = N = 300
         _check(y[:8], ft, cp, [W.M_2TCM_IRR], 7, 0.2, 5, scan=scan)                   # tiny bank, n = 1
 
