@@ -44,10 +44,10 @@ def source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(workload_name: str):
+def traffic_from_profiles(workload_name: str, kernel: str = KERNEL_NAME):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"{KERNEL_NAME}_{workload_name}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -183,7 +183,8 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
            "config": {"bank_draws": n_tot, "draws": "one Philox4x32-10 bank (stream 1) for all voxels",
                       "n_accept": n, "pilot_rows": pilot, "scan": scan},
            "roofline": {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
-                        "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                        "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                        "traffic": traffic_from_profiles(cfg.name, "vpet_bank_mfma_kernel") if scan == "bf16" else None,
                         "kernel": kname, "kernel_ms": round(kern_ms, 3), "flops_per_pair": fpp}}
     if cpu:
         import oracle
@@ -197,7 +198,7 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
         oracle.infer_bank(y_host[:nv], ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed,
                           nthreads=threads)
         per_vox = max(time.perf_counter() - t0 - bank_s, 1e-6) / nv
-        nv = int(max(threads, min(4096, budget_s / per_vox)))
+        nv = int(min(cfg.n_voxels, max(threads, min(4096, budget_s / per_vox))))
         t0 = time.perf_counter()
         ref = oracle.infer_bank(y_host[:nv], ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac,
                                 cfg.infer_seed, nthreads=threads)

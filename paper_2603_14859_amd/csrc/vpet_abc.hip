@@ -811,7 +811,6 @@ struct BankArgs {
     float* tau;             // [V] pilot threshold (fp32 distance), NaN for an invalid voxel
     int* cnt;               // [V] candidates found (may exceed cap)
     uint64_t* cand;         // [V][cap] candidate keys (FP64 scan)
-    uint32_t* cand_row;     // [V][cap] candidate bank rows (contraction scan; same memory)
     int* fb_list;           // [V] voxels whose candidate list cannot certify the top n
     unsigned* fb_count;     // [1] entries in fb_list
     // BF16 contraction (L2 only): d = a_v + sum_k A_vk B_gk with
@@ -821,7 +820,9 @@ struct BankArgs {
     uint16_t* blo;
     uint16_t* ahi;          // [V][K]
     uint16_t* alo;
-    float* cthr;            // [V] candidate test: sum_k A B - margin <= cthr
+    float* cthr;            // [V] candidate test: computed sum_k A B <= cthr
+    float* tau1;            // [V] a tighter first threshold (contraction scan), with
+    float* cthr1;           // [V] its candidate test; rows passing it are re-ranked first
     double* aval;           // [V] a_v = sum_f w y^2; NaN for an invalid voxel
     float* out_mom;
     float* out_prob;
@@ -1045,23 +1046,38 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
     const float tau = P.tau[row];
     int below = 0;
     if (RECOMPUTE) {
-        // exact FP64 distances of the candidate rows (a row per lane); keys
-        // above the threshold are dropped, the rest packed to the front
+        // exact FP64 distances of the candidate rows (a row per lane), keys up
+        // to tau packed to the front.  Pass 1 takes the rows that passed the
+        // tighter test (computed S <= cthr1); if at least n of them lie at or
+        // below tau1, the n smallest keys are among them.  Otherwise pass 2
+        // adds the remaining candidates and the certificate is taken at tau.
         double Y[LD], Wt[LD];
         lane_curve<LD, L1>(P, row, Y, Wt);  // every lane holds the voxel
-        const uint32_t* src = P.cand_row + (size_t)row * P.cap;
-        for (int j0 = 0; j0 < c; j0 += kWave) {
-            const int j = j0 + lane_id();
-            uint64_t key = kNoKey;
-            if (j < c) {
-                const uint32_t g = src[j];
-                const float fd = key_dist(row_distance<LD, L1>(P.bank_x + (size_t)g * LD, Y, Wt));
-                key = ((uint64_t)__float_as_uint(fd) << 32) | g;
+        const uint64_t* src = P.cand + (size_t)row * P.cap;
+        const float tau1 = P.tau1[row], cthr1 = P.cthr1[row];
+        int below1 = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int j0 = 0; j0 < c; j0 += kWave) {
+                const int j = j0 + lane_id();
+                uint64_t key = kNoKey;
+                bool take = false;
+                if (j < c) {
+                    const uint64_t e = src[j];
+                    take = (__uint_as_float((uint32_t)(e >> 32)) <= cthr1) == (pass == 0);
+                    if (take) {
+                        const uint32_t g = (uint32_t)e;
+                        const float fd = key_dist(row_distance<LD, L1>(P.bank_x + (size_t)g * LD, Y, Wt));
+                        key = ((uint64_t)__float_as_uint(fd) << 32) | g;
+                    }
+                }
+                const float fd = __uint_as_float((uint32_t)(key >> 32));
+                const bool keep = take && fd <= tau;
+                const uint64_t b = __ballot(keep);
+                if (keep) keys[below + (int)mbcnt(b)] = key;
+                below += __popcll(b);
+                below1 += __popcll(__ballot(take && fd <= tau1));
             }
-            const bool keep = j < c && __uint_as_float((uint32_t)(key >> 32)) <= tau;
-            const uint64_t b = __ballot(keep);
-            if (keep) keys[below + (int)mbcnt(b)] = key;
-            below += __popcll(b);
+            if (below1 >= (int)P.n_acc) break;  // certified at tau1
         }
     } else {
         const uint64_t* src = P.cand + (size_t)row * P.cap;
@@ -1141,18 +1157,36 @@ __device__ __forceinline__ void split_bf16(double v, uint16_t& hi, uint16_t& lo)
     lo = bf16_rn((float)(v - (double)bf16_to_f(hi)));
 }
 
+// A row of 2 LD bf16 values (LD words) written as 16-byte stores.
+template <int LD>
+__device__ __forceinline__ void store_words(uint16_t* dst, const uint32_t (&w)[LD]) {
+    uint4* d = reinterpret_cast<uint4*>(dst);
+#pragma unroll
+    for (int q = 0; q < LD / 4; ++q) d[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
 // Bank operands B_g = [x_g, x_g^2] as bf16 hi/lo parts.
+template <int LD>
 __global__ __launch_bounds__(256) void vpet_bank_bops_kernel(BankArgs P) {
     const unsigned g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= P.n_tot) return;
-    const double* xr = P.bank_x + (size_t)g * P.ld;
-    for (int k = 0; k < P.K; ++k) {
-        const double xv = xr[k < P.ld ? k : k - P.ld];
+    const double* xr = P.bank_x + (size_t)g * LD;
+    uint32_t wh[LD], wl[LD];  // K = 2 LD bf16 values, two per word
+#pragma unroll
+    for (int k = 0; k < 2 * LD; ++k) {
+        const double xv = xr[k < LD ? k : k - LD];
         uint16_t hi, lo;
-        split_bf16(k < P.ld ? xv : xv * xv, hi, lo);
-        P.bhi[(size_t)g * P.K + k] = hi;
-        P.blo[(size_t)g * P.K + k] = lo;
+        split_bf16(k < LD ? xv : xv * xv, hi, lo);
+        if (k & 1) {
+            wh[k >> 1] |= (uint32_t)hi << 16;
+            wl[k >> 1] |= (uint32_t)lo << 16;
+        } else {
+            wh[k >> 1] = hi;
+            wl[k >> 1] = lo;
+        }
     }
+    store_words<LD>(P.bhi + (size_t)g * 2 * LD, wh);
+    store_words<LD>(P.blo + (size_t)g * 2 * LD, wl);
 }
 
 // Voxel operands A_v = [-2 w y, w] (bf16 hi/lo) and a_v = sum w y^2 (FP64),
@@ -1164,30 +1198,41 @@ __global__ __launch_bounds__(256) void vpet_bank_aops_kernel(BankArgs P) {
     if (row >= P.V) return;
     double Y[LD], Wt[LD];
     const bool valid = lane_curve<LD, false>(P, row, Y, Wt);
-    uint16_t* ah = P.ahi + (size_t)row * P.K;
-    uint16_t* al = P.alo + (size_t)row * P.K;
+    uint16_t* ah = P.ahi + (size_t)row * 2 * LD;
+    uint16_t* al = P.alo + (size_t)row * 2 * LD;
+    uint32_t wh[LD], wl[LD];  // K = 2 LD bf16 values, two per word
     if (!valid) {
-        for (int k = 0; k < P.K; ++k) ah[k] = al[k] = 0;
+#pragma unroll
+        for (int q = 0; q < LD; ++q) wh[q] = wl[q] = 0u;
+        store_words<LD>(ah, wh);
+        store_words<LD>(al, wl);
         P.aval[row] = __builtin_nan("");
-        P.tau[row] = __builtin_nanf("");
-        P.cthr[row] = -__builtin_inff();
+        P.tau[row] = P.tau1[row] = __builtin_nanf("");
+        P.cthr[row] = P.cthr1[row] = -__builtin_inff();
         P.cnt[row] = -1;
         return;
     }
     double a = 0.0;
     bool wneg = false;
 #pragma unroll
-    for (int f = 0; f < LD; ++f) {
-        a = fma(Wt[f] * Y[f], Y[f], a);
-        wneg = wneg || !(Wt[f] >= 0.0);
+    for (int k = 0; k < 2 * LD; ++k) {
+        const int f = k < LD ? k : k - LD;
+        if (k < LD) {
+            a = fma(Wt[f] * Y[f], Y[f], a);
+            wneg = wneg || !(Wt[f] >= 0.0);
+        }
         uint16_t hi, lo;
-        split_bf16(-2.0 * Wt[f] * Y[f], hi, lo);
-        ah[f] = hi;
-        al[f] = lo;
-        split_bf16(Wt[f], hi, lo);
-        ah[LD + f] = hi;
-        al[LD + f] = lo;
+        split_bf16(k < LD ? -2.0 * Wt[f] * Y[f] : Wt[f], hi, lo);
+        if (k & 1) {
+            wh[k >> 1] |= (uint32_t)hi << 16;
+            wl[k >> 1] |= (uint32_t)lo << 16;
+        } else {
+            wh[k >> 1] = hi;
+            wl[k >> 1] = lo;
+        }
     }
+    store_words<LD>(ah, wh);
+    store_words<LD>(al, wl);
     // the error bound assumes w >= 0: otherwise a_v = -inf makes every row a
     // candidate (the selection is then exact or falls back)
     P.aval[row] = wneg ? -__builtin_inf() : a;
@@ -1270,7 +1315,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void v
     // A wavefront owns its 32 voxels, so the counts live in one register and
     // are read with readlane and updated by lane (no atomics).
     unsigned cntv = 0u;
-    uint32_t* wcand = P.cand_row + (size_t)(vbase + wave * 32) * P.cap;
+    uint64_t* wcand = P.cand + (size_t)(vbase + wave * 32) * P.cap;
     const uint32_t lt = (1u << (lane & 31)) - 1u;  // lanes below mine in my half-wave
 
     const unsigned n_rows = PILOT ? P.n_pilot : P.n_tot;
@@ -1328,7 +1373,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void v
                 const unsigned base = __builtin_amdgcn_readlane(cntv, i);
                 if ((lane >> 5) == h && ((bits >> (lane & 31)) & 1u)) {
                     const unsigned pos = base + (unsigned)__popc(bits & lt);
-                    if (pos < (unsigned)P.cap) wcand[(unsigned)i * (unsigned)P.cap + pos] = g;
+                    if (pos < (unsigned)P.cap)
+                        wcand[(unsigned)i * (unsigned)P.cap + pos] = ((uint64_t)__float_as_uint(acc[r]) << 32) | g;
                 }
                 cntv = lane == i ? base + (unsigned)__popc(bits) : cntv;
             }
@@ -1384,8 +1430,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void v
                 }
             }
         }
+        // the 8th smallest (lane 7 of the half) gives the first threshold
+        float c8[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c8[r] = __shfl(cth[r], (lane & 32) + kBankTopK / 2 - 1, kWave);
         if (l == kBankTopK - 1) {
             constexpr double m = contraction_rel_err<K>();
+            // candidate test of threshold t: t - a + m E_t, E_t = 3a + 4 sqrt(a t) + t
+            auto test_of = [&](float t, double a) {
+                const double tp = fmax((double)t, 0.0);
+                const double e_t = 3.0 * a + 4.0 * sqrt(a * tp) + tp;
+                return (float)((double)t - a + m * e_t + 1e-6 * (a + fabs((double)t)));
+            };
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const long long v = vbase + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -1393,15 +1449,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void v
                 const double a = P.aval[v];
                 if (!(a == a)) continue;  // invalid voxel: marked by the operand kernel
                 if (a < 0.0) {            // negative weights: no bound, every row a candidate
-                    P.tau[v] = __builtin_inff();
-                    P.cthr[v] = __builtin_inff();
+                    P.tau[v] = P.tau1[v] = __builtin_inff();
+                    P.cthr[v] = P.cthr1[v] = __builtin_inff();
                     continue;
                 }
-                const float tau = (float)(a + (double)cth[r]);
-                const double tp = fmax((double)tau, 0.0);
-                const double e_tau = 3.0 * a + 4.0 * sqrt(a * tp) + tp;
+                const float tau = (float)(a + (double)cth[r]), tau1 = (float)(a + (double)c8[r]);
                 P.tau[v] = tau;
-                P.cthr[v] = (float)((double)tau - a + m * e_tau + 1e-6 * (a + fabs((double)tau)));
+                P.cthr[v] = test_of(tau, a);
+                P.tau1[v] = tau1;
+                P.cthr1[v] = test_of(tau1, a);
             }
         }
     } else if (lane < 32) {
@@ -1930,7 +1986,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     // somewhat above the threshold, so it gets twice the room (up to 4096)
     const int cap = use_mfma ? std::max(512, std::min(4096, pow2_at_least(16 * (int)n_acc)))
                              : std::max(256, pow2_at_least(8 * (int)n_acc));
-    const size_t cand_bytes = use_mfma ? sizeof(uint32_t) : sizeof(uint64_t);
+    const size_t cand_bytes = sizeof(uint64_t);  // (fp32 distance or computed S, bank row)
     // default pilot: about 4 n bank rows below the threshold (FP64 scan: the
     // 16th smallest of 4 N / n rows; contraction scan: the 16th smallest of 32
     // column minima over 5.5 N / n rows)
@@ -1976,7 +2032,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     const size_t sz_a = use_mfma ? align256(sizeof(uint16_t) * (size_t)KB * cv) : 0;
     const size_t sz_c = use_mfma ? align256(sizeof(float) * cv) : 0;
     const size_t sz_av = use_mfma ? align256(sizeof(double) * cv) : 0;
-    hipError_t e = hipMallocAsync((void**)&scratch, sz_tau + sz_cnt + sz_fb + sz_cand + 2 * sz_b + 2 * sz_a + sz_c + sz_av, st);
+    hipError_t e = hipMallocAsync((void**)&scratch, sz_tau + sz_cnt + sz_fb + sz_cand + 2 * sz_b + 2 * sz_a + 3 * sz_c + sz_av, st);
     if (e != hipSuccess) return fail(VPET_E_NOMEM, "bank scratch: %s", hipGetErrorString(e));
     char* q = scratch;
     A.tau = reinterpret_cast<float*>(q);
@@ -1987,7 +2043,6 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     A.fb_list = reinterpret_cast<int*>(q + 256);
     q += sz_fb;
     A.cand = reinterpret_cast<uint64_t*>(q);
-    A.cand_row = reinterpret_cast<uint32_t*>(q);
     q += sz_cand;
     A.K = KB;
     if (use_mfma) {
@@ -2000,6 +2055,10 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         A.alo = reinterpret_cast<uint16_t*>(q);
         q += sz_a;
         A.cthr = reinterpret_cast<float*>(q);
+        q += sz_c;
+        A.cthr1 = reinterpret_cast<float*>(q);
+        q += sz_c;
+        A.tau1 = reinterpret_cast<float*>(q);
         q += sz_c;
         A.aval = reinterpret_cast<double*>(q);
     }
@@ -2027,7 +2086,13 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         if (me != hipSuccess && rc == VPET_OK) rc = hip_fail(me, "hipEventRecord");
     };
     if (mfma) {
-        hipLaunchKernelGGL(vpet_bank_bops_kernel, dim3((unsigned)((n_tot + 255) / 256)), dim3(256), 0, st, A);
+        const dim3 gb((unsigned)((n_tot + 255) / 256)), b256(256);
+        switch (ld) {
+            case 8: hipLaunchKernelGGL((vpet_bank_bops_kernel<8>), gb, b256, 0, st, A); break;
+            case 16: hipLaunchKernelGGL((vpet_bank_bops_kernel<16>), gb, b256, 0, st, A); break;
+            case 24: hipLaunchKernelGGL((vpet_bank_bops_kernel<24>), gb, b256, 0, st, A); break;
+            default: hipLaunchKernelGGL((vpet_bank_bops_kernel<32>), gb, b256, 0, st, A); break;
+        }
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "bank operand launch");
     }
