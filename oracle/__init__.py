@@ -27,8 +27,11 @@ _LIB_PATH = os.path.join(_HERE, "libvpet_oracle.so")
 M_1TCM = 1
 M_2TCM_IRR = 2
 M_2TCM_REV = 4
+M_MRTM = 8      # reference-tissue models: the input is the reference TAC C_r
+M_LPNTPET = 16
 NSLOT = 8
 SLOT = {"K1": 0, "k2": 1, "k3": 2, "k4": 3, "vB": 4, "Ki": 5}
+SLOT_REF = {"R1": 0, "k2": 1, "k2a": 2, "gamma": 3, "tD": 4, "tP": 5, "alpha": 6, "BP": 7}
 DEFAULT_LAMBDA = math.log(2.0) / 109.8  # 18F, min^-1 (Sec. III-A1)
 DEFAULT_FLOOR = 0.01
 
@@ -74,6 +77,8 @@ def lib():
         L.ora_infer_bank.argtypes = [P, i64, i32, P, i32, f64, P, P, i32, P, i64, f64, u64, f64, f64, i32, P, i32,
                                      P, P, P, P, P]
         L.ora_infer_bank.restype = i64
+        L.ora_gamma_variate.argtypes = [f64, f64, f64, f64]
+        L.ora_gamma_variate.restype = f64
         _lib = L
     return _lib
 
@@ -132,6 +137,11 @@ def draws(models, boxes, seed, v, i, m, stream=0):
 # --------------------------------------------------------------------------
 # Forward model (Eq. (1)-(2); reading R2 for the discretisation).
 # --------------------------------------------------------------------------
+def gamma_variate(t: float, tD: float, tP: float, alpha: float) -> float:
+    """lp-ntPET activation g(t) (0 up to tD, peak 1 at tP)."""
+    return float(lib().ora_gamma_variate(float(t), float(tD), float(tP), float(alpha)))
+
+
 def step_coeffs(beta: float, h: float):
     e, a, b = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     lib().ora_step_coeffs(float(beta), float(h), ctypes.byref(e), ctypes.byref(a), ctypes.byref(b))

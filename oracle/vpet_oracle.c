@@ -24,6 +24,9 @@
  *     Sec. III-B2 (TB-PET study).
  *   - Counter-based generator: Philox4x32-10 of Salmon, Moraes, Dror and Shaw,
  *     "Parallel random numbers: as easy as 1, 2, 3", SC'11.
+ *   - Reference-tissue models: lp-ntPET, Eq. (3)-(4) (Sec. II-A2); MRTM is its
+ *     gamma = 0 case; the activation g(t) is the gamma variate of the lp-ntPET
+ *     literature the section cites (peak 1 at t_P).
  *
  * Readings where the paper is silent (each is one line of the numerics spec):
  *   R1 draws: counter (i, v, stream, m<<16 | blk), key = seed; word -> u =
@@ -36,6 +39,16 @@
  *   R5 selection: keep the n smallest (d, g); ties go to the lower index g.
  *   R6 models: stratified, exactly n_draws per model; g = m n_draws + i.
  *   R7 variance: 1/(cnt-1); cnt = 1 -> 0; cnt = 0 -> NaN (and prob 0).
+ *   R12 reference-tissue models: the input is the reference TAC C_r, linear
+ *      between nodes.  Eq. (3)-(4) are the ODE C_t' = R1 C_r' + k2 C_r - kappa C_t,
+ *      kappa(t) = k2a + gamma g(t), C_t(0) = R1 C_r(0); with C_t = R1 C_r + z,
+ *      z' = (k2 - R1 kappa) C_r - kappa z.  MRTM (gamma = 0) is one exponential
+ *      exp(-k2a t) of amplitude k2 - R1 k2a plus the direct term R1 C_r.  For
+ *      lp-ntPET kappa is frozen at each step's midpoint and the step is then
+ *      integrated exactly (the R2 step weights with rate kappa).
+ *      g(t) = s^alpha exp(alpha (1 - s)), s = (t - tD)/(tP - tD), for t > tD.
+ *   R13 lp-ntPET draws: the t_P box is relative to the drawn t_D:
+ *      lo = tD + box_lo (fp32), t_P = fmaf((float)box_hi - lo, u, lo).
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,6 +65,8 @@
 #define ORA_M_1TCM 1u
 #define ORA_M_2TCM_IRR 2u
 #define ORA_M_2TCM_REV 4u
+#define ORA_M_MRTM 8u
+#define ORA_M_LPNT 16u
 #define ORA_NSLOT 8 /* K1, k2, k3, k4, vB, Ki, unused, unused */
 #define SLOT_K1 0
 #define SLOT_K2 1
@@ -59,6 +74,15 @@
 #define SLOT_K4 3
 #define SLOT_VB 4
 #define SLOT_KI 5
+/* reference-tissue models: R1, k2, k2a, gamma, tD, tP, alpha, BP_ND = k2/k2a - 1 */
+#define SLOT_R1 0
+#define SLOT_RK2 1
+#define SLOT_K2A 2
+#define SLOT_GAMMA 3
+#define SLOT_TD 4
+#define SLOT_TP 5
+#define SLOT_ALPHA 6
+#define SLOT_BP 7
 
 /* The slots a model draws, in the order its Philox words are consumed. */
 static int model_params(uint32_t model, int slots[8]) {
@@ -74,6 +98,14 @@ static int model_params(uint32_t model, int slots[8]) {
         slots[0] = SLOT_K1; slots[1] = SLOT_K2; slots[2] = SLOT_K3; slots[3] = SLOT_K4;
         slots[4] = SLOT_VB;
         return 5;
+    }
+    if (model == ORA_M_MRTM) {
+        slots[0] = SLOT_R1; slots[1] = SLOT_RK2; slots[2] = SLOT_K2A;
+        return 3;
+    }
+    if (model == ORA_M_LPNT) {
+        for (int j = 0; j < 7; ++j) slots[j] = j; /* R1, k2, k2a, gamma, tD, tP, alpha */
+        return 7;
     }
     return 0;
 }
@@ -139,6 +171,10 @@ void ora_draw(uint32_t model, const double* box, uint64_t seed, uint64_t v, uint
         double lo = box[2 * s], hi = box[2 * s + 1];
         float lo_f = (float)lo;
         float wid_f = (float)(hi - lo);
+        if (model == ORA_M_LPNT && s == SLOT_TP) { /* R13: t_P in [tD + lo, hi] */
+            lo_f = theta[SLOT_TD] + (float)lo;
+            wid_f = (float)hi - lo_f;
+        }
         float u = word_to_unit(w[j]);
         theta[s] = fmaf(wid_f, u, lo_f);
         if (u_out) u_out[j] = u;
@@ -239,10 +275,48 @@ int ora_exp_terms(uint32_t model, const double* th, double rate[2], double amp[2
     return 0;
 }
 
+/* Gamma-variate activation of lp-ntPET (R12): 0 up to tD, peak 1 at tP. */
+double ora_gamma_variate(double t, double tD, double tP, double alpha) {
+    if (!(t > tD)) return 0.0;
+    double s = (t - tD) / (tP - tD);
+    return pow(s, alpha) * exp(alpha * (1.0 - s));
+}
+
+/* Reference-tissue models (R12): node TAC from the reference TAC cr[0..K]. */
+static void simulate_reference(uint32_t model, const double* th, const double* cr, int K, double h,
+                               double* out) {
+    double R1 = th[SLOT_R1], k2 = th[SLOT_RK2], k2a = th[SLOT_K2A];
+    if (model == ORA_M_MRTM) {
+        /* C_t = R1 C_r + (k2 - R1 k2a) (exp(-k2a t) * C_r) */
+        double* I = (double*)malloc(sizeof(double) * (size_t)(K + 1));
+        ora_convolve_exp(k2a, cr, K, h, I);
+        for (int k = 0; k <= K; ++k) out[k] = R1 * cr[k] + (k2 - R1 * k2a) * I[k];
+        free(I);
+        return;
+    }
+    /* lp-ntPET: z' = (k2 - R1 kappa) C_r - kappa z, kappa frozen at the midpoint */
+    double gam = th[SLOT_GAMMA], tD = th[SLOT_TD], tP = th[SLOT_TP], alpha = th[SLOT_ALPHA];
+    double z = 0.0;
+    out[0] = R1 * cr[0];
+    for (int k = 0; k < K; ++k) {
+        double tm = ((double)k + 0.5) * h;
+        double kappa = k2a + gam * ora_gamma_variate(tm, tD, tP, alpha);
+        double e, a, b;
+        ora_step_coeffs(kappa, h, &e, &a, &b);
+        z = e * z + (k2 - R1 * kappa) * (a * cr[k] + b * cr[k + 1]);
+        out[k + 1] = R1 * cr[k + 1] + z;
+    }
+}
+
 /* Node TAC (Eq. (2) with C_wb = C_p for FDG):
- * C_T(t_k) = (1 - vB) sum_j A_j I_j(t_k) + vB C_p(t_k),  k = 0..K. */
+ * C_T(t_k) = (1 - vB) sum_j A_j I_j(t_k) + vB C_p(t_k),  k = 0..K.
+ * For the reference-tissue models cp is the reference TAC (R12). */
 void ora_simulate_nodes(uint32_t model, const double* th, const double* cp, int K, double h,
                         double* out) {
+    if (model == ORA_M_MRTM || model == ORA_M_LPNT) {
+        simulate_reference(model, th, cp, K, h, out);
+        return;
+    }
     double rate[2], amp[2];
     int nt = ora_exp_terms(model, th, rate, amp);
     double vB = th[SLOT_VB];
@@ -365,7 +439,11 @@ static void summarize(const ora_cand* cand, int64_t n, int M, const uint32_t* mo
         int np = model_params(models[m], slots);
         int use[8] = {0};
         for (int j = 0; j < np; ++j) use[slots[j]] = 1;
-        if (models[m] != ORA_M_1TCM) use[SLOT_KI] = 1;
+        const int reference = models[m] == ORA_M_MRTM || models[m] == ORA_M_LPNT;
+        if (reference)
+            use[SLOT_BP] = 1; /* BP_ND = k2 / k2a - 1 (Sec. II-A2) */
+        else if (models[m] != ORA_M_1TCM)
+            use[SLOT_KI] = 1;
         double sum[8] = {0}, sq[8] = {0};
         int64_t cnt = 0;
         for (int pass = 0; pass < 2; ++pass) {
@@ -380,7 +458,9 @@ static void summarize(const ora_cand* cand, int64_t n, int M, const uint32_t* mo
                              NULL, NULL);
                 double val[8];
                 for (int s = 0; s < 8; ++s) val[s] = (double)thf[s];
-                if (use[SLOT_KI]) {
+                if (reference) {
+                    val[SLOT_BP] = val[SLOT_RK2] / val[SLOT_K2A] - 1.0;
+                } else if (use[SLOT_KI]) {
                     double K1 = val[SLOT_K1], k2 = val[SLOT_K2], k3 = val[SLOT_K3];
                     val[SLOT_KI] = K1 * k3 / (k2 + k3);
                 }

@@ -63,3 +63,43 @@ def rk4_2tcm_nodes(theta, cp, h, sub=40):
         out[k + 1] = (1 - vB) * (y[0] + y[1]) + vB * c1
     out[0] = vB * cp[0]
     return out
+
+
+def rk4_reference_nodes(theta, cr, h, sub=40):
+    """Node TAC of the lp-ntPET ODE behind Eq. (3)-(4),
+        C_t' = R1 C_r' + k2 C_r - (k2a + gamma g(t)) C_t,   C_t(0) = R1 C_r(0),
+    by classical RK4 with `sub` steps per grid interval, the reference TAC being
+    the straight line between nodes and g(t) the peak-normalised gamma variate
+    s^alpha exp(alpha (1 - s)), s = (t - tD)/(tP - tD), zero before tD.
+    theta = (R1, k2, k2a, gamma, tD, tP, alpha)."""
+    R1, k2, k2a, gam, tD, tP, alpha = theta
+    cr = np.asarray(cr, dtype=np.float64)
+    K = cr.shape[0] - 1
+
+    def g(t):
+        if t <= tD:
+            return 0.0
+        s = (t - tD) / (tP - tD)
+        return s ** alpha * np.exp(alpha * (1.0 - s))
+
+    out = np.zeros(K + 1)
+    y = R1 * cr[0]
+    out[0] = y
+    dtau = h / sub
+    for k in range(K):
+        c0, c1 = cr[k], cr[k + 1]
+        slope = (c1 - c0) / h
+
+        def f(t, yv):
+            c = c0 + slope * (t - k * h)
+            return R1 * slope + k2 * c - (k2a + gam * g(t)) * yv
+
+        for s in range(sub):
+            t = k * h + s * dtau
+            q1 = f(t, y)
+            q2 = f(t + 0.5 * dtau, y + 0.5 * dtau * q1)
+            q3 = f(t + 0.5 * dtau, y + 0.5 * dtau * q2)
+            q4 = f(t + dtau, y + dtau * q3)
+            y = y + dtau / 6.0 * (q1 + 2 * q2 + 2 * q3 + q4)
+        out[k + 1] = y
+    return out
