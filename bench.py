@@ -144,7 +144,7 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
 
     def step(timed):
         r = V.infer_bank(y_dev, ft, cfg.dt, n_nodes, models, cfg.n_draws, cfg.accept_frac, thb, xb, out=res,
-                         bank_scan=scan, time_scan=timed)
+                         bank_scan=scan, time_scan=timed, decay_lambda=cfg.decay_lambda)
         if timed:
             scan_ms.append(r["scan_ms"])
 
@@ -170,11 +170,14 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
         # multiply-add per term and pair (the hi/lo split, the error-bound
         # product and the padding of F to a multiple of 8 are not counted)
         fpp = 2 * 2 * F
-        peak, bound, kname = PEAK_BF16_MFMA_TFLOPS, "mfma", "vpet_bank_mfma_kernel<64, false> (BF16 contraction scan)"
+        ld = int(V.lib.vpet_abc_bank_ld(F))
+        peak, bound = PEAK_BF16_MFMA_TFLOPS, "mfma"
+        kname = f"vpet_bank_mfma{'' if ld <= 32 else '_wide'}_kernel<{2 * ld}, false> (BF16 contraction scan)"
         pilot = min(n_tot, -(-11 * n_tot // (2 * n)))
     else:
         fpp = 4 * F  # per frame: subtract, weight, fused multiply-add
-        peak, bound, kname = PEAK_F64_VECTOR_TFLOPS, "alu", "vpet_bank_scan_kernel<32, false, false> (FP64 scan)"
+        ld = int(V.lib.vpet_abc_bank_ld(F))
+        peak, bound, kname = PEAK_F64_VECTOR_TFLOPS, "alu", f"vpet_bank_scan_kernel<{ld}, false, false> (FP64 scan)"
         pilot = min(n_tot, -(-4 * n_tot // n))
     achieved = pairs * fpp / (kern_ms * 1e-3) / 1e12
     out = {"value": cfg.n_voxels / (ms * 1e-3), "unit": "voxels/s", "ms_per_step": round(ms, 3),
@@ -196,15 +199,15 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
         nv = threads
         t0 = time.perf_counter()
         oracle.infer_bank(y_host[:nv], ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed,
-                          nthreads=threads)
+                          nthreads=threads, lam=cfg.decay_lambda)
         per_vox = max(time.perf_counter() - t0 - bank_s, 1e-6) / nv
         nv = int(min(cfg.n_voxels, max(threads, min(4096, budget_s / per_vox))))
         t0 = time.perf_counter()
         ref = oracle.infer_bank(y_host[:nv], ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac,
-                                cfg.infer_seed, nthreads=threads)
+                                cfg.infer_seed, nthreads=threads, lam=cfg.decay_lambda)
         dt = time.perf_counter() - t0
         g = V.infer_bank(y_dev[:nv].contiguous(), ft, cfg.dt, n_nodes, models, cfg.n_draws, cfg.accept_frac, thb, xb,
-                         debug=True)
+                         debug=True, decay_lambda=cfg.decay_lambda)
         torch.cuda.synchronize()
         idx = g["accept_idx"].cpu().numpy()
         mom = g["moments"].cpu().numpy().astype(np.float64)
@@ -227,7 +230,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--workload", choices=["large", "small", "lpnt"], default="large",
+                    help="large: 1M voxels x 100k draws (default); small: 1024 voxels x 2000 draws; lpnt: MRTM vs "
+                         "lp-ntPET model selection, 1.56M voxels against a 400k-row shared bank (bank form only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bank", action="store_true", help="skip the shared-bank form")
     ap.add_argument("--bank-scan", choices=["bf16", "f64"], default="bf16",
@@ -250,6 +255,9 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.workload == "lpnt":
+        main_reference(args, dev)
+        return
     cfg = W.CFG_LARGE if args.workload == "large" else W.CFG_SMALL
     ft, cp, y_host = make_inputs(cfg, dev)
     y = torch.from_numpy(y_host).to(dev)
@@ -316,6 +324,52 @@ def main():
     if not args.no_bank and F <= V.BANK_MAX_FRAMES:
         out["bank_form"] = bank_form(cfg, ft, cp, y_host, y, args.steps, args.warmup, not args.no_cpu_baseline,
                                      args.cpu_budget / 3, args.bank_scan)
+    print(json.dumps(out), flush=True)
+
+
+def main_reference(args, dev):
+    """MRTM vs lp-ntPET model selection on a reference-region input (the
+    shared-bank form; the per-voxel path does not run these models)."""
+    import torch
+
+    import paper_2603_14859_amd as V
+    import workloads as W
+    cfg = W.CFG_LPNT
+    ft, cr = cfg.frame_times, cfg.input_fn()
+    th, active, eps = cfg.truth_reference()
+    F = ft.size - 1
+    clean = np.empty((cfg.n_voxels, F), dtype=np.float32)
+    a, z = np.nonzero(active)[0], np.nonzero(~active)[0]
+    clean[a] = V.simulate(W.M_LPNTPET, torch.from_numpy(th[a]).to(dev), cr, ft, cfg.dt).cpu().numpy()
+    clean[z] = V.simulate(W.M_MRTM, torch.from_numpy(th[z]).to(dev), cr, ft, cfg.dt).cpu().numpy()
+    y_host = W.add_noise(clean, ft, eps, lam=cfg.decay_lambda)
+    y = torch.from_numpy(y_host).to(dev)
+    bank = bank_form(cfg, ft, cr, y_host, y, args.steps, args.warmup, not args.no_cpu_baseline, args.cpu_budget,
+                     args.bank_scan)
+    models = list(cfg.models)
+    thb, xb = V.bank_build(models, cfg.box_array(), cfg.n_draws, cfg.infer_seed, cr, ft, cfg.dt)
+    r = V.infer_bank(y, ft, cfg.dt, cr.size, models, cfg.n_draws, cfg.accept_frac, thb, xb,
+                     decay_lambda=cfg.decay_lambda, bank_scan=args.bank_scan)
+    p = r["model_prob"][:, 1].cpu().numpy()
+    out = {"metric": METRIC, "value": bank["value"], "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": bank["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": bank["dtype"],
+           "data": "synthetic (one-tissue reference TAC of the seeded Feng input, half the voxels activated, "
+                   "Gaussian frame noise, 11C decay)",
+           "config": {"workload": cfg.name, "voxels": cfg.n_voxels, "frames": F, "minutes": float(ft[-1]),
+                      "grid_dt_min": cfg.dt, "models": ["MRTM", "lp-ntPET"], "bank_draws_per_model": cfg.n_draws,
+                      "accept_frac": cfg.accept_frac, "n_accept": bank["config"]["n_accept"],
+                      "pilot_rows": bank["config"]["pilot_rows"], "scan": args.bank_scan,
+                      "parallelism": "single GPU"},
+           "roofline": bank["roofline"],
+           "model_selection": {"activated_voxels": int(active.sum()),
+                               "mean_p_lpntpet_activated": float(p[active].mean()),
+                               "mean_p_lpntpet_null": float(p[~active].mean()),
+                               "sensitivity_p_gt_half": float(np.mean(p[active] > 0.5)),
+                               "specificity_p_le_half": float(np.mean(p[~active] <= 0.5))}}
+    for k in ("cpu_baseline", "error_vs_oracle"):
+        if k in bank:
+            out[k] = bank[k]
     print(json.dumps(out), flush=True)
 
 

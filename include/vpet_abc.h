@@ -53,7 +53,8 @@ extern "C" {
 typedef enum {
     VPET_OK = 0,
     VPET_E_ARG = 1,    /* invalid argument (sizes, pointers, prior box, p)      */
-    VPET_E_MODEL = 2,  /* unknown or empty model bitmask                         */
+    VPET_E_MODEL = 2,  /* unknown or empty model bitmask, or a model the call
+                        * does not run                                          */
     VPET_E_GRID = 3,   /* frame bound off the grid, outside it, or not increasing */
     VPET_E_HIP = 4,    /* HIP runtime or launch failure                          */
     VPET_E_NOMEM = 5,  /* device or pinned-host allocation failed                */
@@ -63,6 +64,16 @@ typedef enum {
 #define VPET_M_1TCM (1u << 0)     /* one-tissue model: K1 exp(-k2 t)                 */
 #define VPET_M_2TCM_IRR (1u << 1) /* two-tissue, irreversible (k4 = 0), Eq. (1)-(2)   */
 #define VPET_M_2TCM_REV (1u << 2) /* two-tissue, reversible, Eq. (1)-(2)              */
+/* Reference-tissue models (Sec. II-A2): the input is the reference-region TAC
+ * C_r, and Eq. (3)-(4) is read as the ODE C_t' = R1 C_r' + k2 C_r - kappa C_t,
+ * kappa(t) = k2a + gamma g(t), C_t(0) = R1 C_r(0), with the activation
+ * g(t) = s^alpha exp(alpha (1 - s)), s = (t - tD)/(tP - tD), zero up to tD
+ * (peak 1 at tP).  lp-ntPET freezes kappa at each grid step's midpoint and
+ * integrates the step exactly; MRTM is the gamma = 0 case, one exponential
+ * exp(-k2a t) of amplitude k2 - R1 k2a plus the direct term R1 C_r.  The two
+ * families cannot be mixed in one model_id (their inputs differ). */
+#define VPET_M_MRTM (1u << 3)
+#define VPET_M_LPNTPET (1u << 4)
 
 #define VPET_PSTRIDE 8
 #define VPET_SLOT_K1 0
@@ -71,13 +82,25 @@ typedef enum {
 #define VPET_SLOT_K4 3
 #define VPET_SLOT_VB 4
 #define VPET_SLOT_KI 5
+/* Slots of the reference-tissue models (MRTM uses R1, k2, k2a).  The prior box
+ * entry of tP is relative: tP is drawn in [tD + lo, hi] (lo > 0, tD_hi + lo <=
+ * hi) as fmaf((float)hi - l, u, l), l = tD + (float)lo in fp32.  BP_ND =
+ * k2 / k2a - 1 is reported in its slot per accepted sample. */
+#define VPET_SLOT_R1 0
+#define VPET_SLOT_RK2 1
+#define VPET_SLOT_K2A 2
+#define VPET_SLOT_GAMMA 3
+#define VPET_SLOT_TD 4
+#define VPET_SLOT_TP 5
+#define VPET_SLOT_ALPHA 6
+#define VPET_SLOT_BP 7
 
 /* Capacities.  VPET_MAX_ACCEPT bounds n = floor(N p) (the accepted set of a
  * voxel is kept on chip); larger n returns VPET_E_LIMIT. */
 #define VPET_MAX_ACCEPT 3968
 #define VPET_MAX_NODES 16385
 #define VPET_MAX_FRAMES 1024
-#define VPET_BANK_MAX_FRAMES 32
+#define VPET_BANK_MAX_FRAMES 48
 #define VPET_BANK_MAX_ACCEPT 512
 
 typedef struct {
@@ -113,9 +136,10 @@ typedef struct {
     int32_t waves_per_voxel;
     /* Shared-bank form only: bank rows in the pilot that sets each voxel's
      * candidate threshold; 0 = a default that lets about 4 n rows pass
-     * (FP64 scan: the 16th smallest distance of the first ceil(4 N / n)
-     * rows; BF16 scan: the 16th smallest of 32 column minima of the first
-     * ceil(5.5 N / n) rows). */
+     * (FP64 scan: the 16th smallest distance of ceil(4 N / n) rows; BF16
+     * scan: the 16th smallest of 32 column minima of ceil(5.5 N / n) rows);
+     * the pilot rows are spread evenly over the bank, which is ordered by
+     * model. */
     int64_t bank_pilot;
     /* Shared-bank form only: how every (voxel, bank row) pair is screened.
      * 0 = auto (1 for L1, 2 for L2); 1 = FP64 distances on the vector ALUs;
@@ -149,9 +173,9 @@ int vpet_abc_accept_count(int64_t n_total, double accept_frac, int64_t* out_n);
  * Alg. 1, line 3).  Each row is run in FP64 from its fp32 values; the frame
  * value is the trapezoid rule over the frame's nodes of the exact response to
  * the piecewise-linear input, divided by the frame length.
- *   model_id    exactly one VPET_M_* bit
+ *   model_id    exactly one VPET_M_* bit (any model)
  *   theta       device [n][VPET_PSTRIDE] fp32, slots as above (others ignored)
- *   input_fn    host [grid.n_nodes] fp32
+ *   input_fn    host [grid.n_nodes] fp32 (the reference TAC for MRTM, lp-ntPET)
  *   frame_times host [grid.n_frames + 1] fp32
  *   out_tacs    device [n][grid.n_frames] fp32
  * Errors: VPET_E_MODEL (not exactly one known bit), VPET_E_GRID, VPET_E_ARG
@@ -165,7 +189,10 @@ int vpet_abc_simulate(uint32_t model_id, const float* theta, int64_t n, const fl
  * Voxelwise fixed-budget rejection ABC (Alg. 1).
  *   tacs          device [n_voxels][F] fp32 observed TACs
  *   frame_times   host [F + 1] fp32;  input_fn host [grid.n_nodes] fp32
- *   model_id      bitmask of VPET_M_*; M = popcount, listed in bit order
+ *   model_id      bitmask of the plasma-input VPET_M_* bits (1TCM, 2TCMs); M =
+ *                 popcount, listed in bit order.  The reference-tissue models
+ *                 run in the shared-bank form only (VPET_E_MODEL here): with a
+ *                 subject-level reference TAC one bank serves every voxel.
  *   prior_box     host [M][VPET_PSTRIDE][2] FP64 (lo, hi) per slot; lo == hi
  *                 fixes a parameter.  Rate constants need lo >= 0, vB needs
  *                 0 <= lo and hi < 1; 2TCM models need k2_lo + k3_lo > 0 and the
@@ -212,7 +239,9 @@ int vpet_abc_draws(uint32_t model_id, const double* prior_box, uint64_t seed,
  * of draws and curves serves every voxel).  Bank draw i of list position m is
  * the Philox draw of counter (i, 0, 1, m << 16 | blk) -- stream 1, no voxel
  * index -- so a bank is a function of (model_id, prior_box, n_draws, seed,
- * grid) only and may be reused across calls and voxel chunks.
+ * grid) only and may be reused across calls and voxel chunks.  Every model,
+ * including the reference-tissue ones (input_fn = reference TAC), runs here;
+ * the moments of the reference-tissue models carry BP_ND in slot 7.
  *
  * vpet_abc_bank_ld(F): row stride (frames rounded up to a multiple of 8) of the
  * bank curves.  Host-only; 0 for F <= 0.

@@ -5,5 +5,5 @@ ABI of ``include/vpet_abc.h``; this package is the thin ctypes binding with the
 same entry points (``simulate``, ``infer``, ``draws``, ``accept_count``).
 """
 from ._binding import (E_ARG, E_GRID, E_HIP, E_LIMIT, E_MODEL, E_NOMEM, EXPORTED, LIB_PATH, M_1TCM,  # noqa: F401
-                       M_2TCM_IRR, M_2TCM_REV, MAX_ACCEPT, OK, PSTRIDE, VpetError, accept_count, draws, infer,
+                       M_2TCM_IRR, M_2TCM_REV, M_LPNTPET, M_MRTM, MAX_ACCEPT, OK, PSTRIDE, VpetError, accept_count, draws, infer,
                        lib, model_mask, simulate, version, bank_build, infer_bank, BANK_MAX_ACCEPT, BANK_MAX_FRAMES)

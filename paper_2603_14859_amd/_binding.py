@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libvpetabc.so")
 
 OK, E_ARG, E_MODEL, E_GRID, E_HIP, E_NOMEM, E_LIMIT = range(7)
 M_1TCM, M_2TCM_IRR, M_2TCM_REV = 1, 2, 4
+M_MRTM, M_LPNTPET = 8, 16  # reference-tissue models (input = reference TAC)
+_ALL_MODELS = (M_1TCM, M_2TCM_IRR, M_2TCM_REV, M_MRTM, M_LPNTPET)
 PSTRIDE = 8
 MAX_ACCEPT = 3968
 
@@ -25,7 +27,7 @@ EXPORTED = ("vpet_abc_accept_count", "vpet_abc_simulate", "vpet_abc_infer", "vpe
             "vpet_abc_bank_ld", "vpet_abc_bank_build", "vpet_abc_infer_bank",
             "vpet_abc_last_error", "vpet_abc_version")
 BANK_MAX_ACCEPT = 512
-BANK_MAX_FRAMES = 32
+BANK_MAX_FRAMES = 48
 
 
 class VpetError(RuntimeError):
@@ -79,11 +81,11 @@ def _check(status: int):
 def model_mask(models) -> int:
     mask = 0
     for m in models:
-        if m not in (M_1TCM, M_2TCM_IRR, M_2TCM_REV):
+        if m not in _ALL_MODELS:
             raise ValueError(f"unknown model {m}")
         mask |= int(m)
-    if [m for m in (M_1TCM, M_2TCM_IRR, M_2TCM_REV) if mask & m] != list(models):
-        raise ValueError("models must be distinct and listed in bit order (1TCM, IRR, REV)")
+    if [m for m in _ALL_MODELS if mask & m] != list(models):
+        raise ValueError("models must be distinct and listed in bit order (1TCM, IRR, REV, MRTM, lp-ntPET)")
     return mask
 
 

@@ -65,21 +65,27 @@ constexpr int draws_per_lane() { return (KINDS == 1 || KINDS == 2) ? kUmax : 2; 
 constexpr double kCmin = 1e-5;        // 1 - z below which frame sums are accumulated
 constexpr int kMaxModels = 3;
 constexpr int kMaxWpv = 4;
+constexpr int kRedStride = 16;  // doubles per wavefront in a block reduction's scratch
 constexpr uint64_t kNoKey = ~0ull;
 constexpr int kLdsLimit = 65536;
 
-enum ModelKind { KIND_1TCM = 1, KIND_IRR = 2, KIND_REV = 4 };
+enum ModelKind { KIND_1TCM = 1, KIND_IRR = 2, KIND_REV = 4, KIND_MRTM = 8, KIND_LPNT = 16 };
+constexpr int kMaxParams = 7;  // lp-ntPET: R1, k2, k2a, gamma, tD, tP, alpha
 
+// Prior box of one model in its draw order.  rel_tp (lp-ntPET): parameter 5
+// (tP) is drawn in [tD + lo[5], wid[5]], i.e. lo[5] is an offset after the
+// drawn tD and wid[5] holds the absolute upper bound.
 struct ModelDev {
     int kind;
     int np;
-    int slot[5];
-    float lo[5];
-    float wid[5];
+    int rel_tp;
+    int slot[kMaxParams];
+    float lo[kMaxParams];
+    float wid[kMaxParams];
 };
 
 struct Tab {
-    const double* C;   // C_k, k = 0 .. kend-1 (input at the start of each step)
+    const double* C;   // C_k, k = 0 .. kend (input at the grid nodes up to the last frame's end)
     const double* fr;  // per frame: SS (trapezoid sum of the running integral Q),
                        // PP (trapezoid sum of C), R (sum of C over the frame's steps), omega
     const int* nf;     // steps per frame
@@ -130,7 +136,7 @@ __device__ __forceinline__ float unit24(uint32_t w) { return (float)(w >> 8) * 0
 
 // Parameters of draw i of list position m for voxel v, in the model's order.
 __device__ __forceinline__ void draw_params(const ModelDev& md, uint32_t key0, uint32_t key1,
-                                            uint32_t v, uint32_t i, uint32_t m, float th[5],
+                                            uint32_t v, uint32_t i, uint32_t m, float th[kMaxParams],
                                             uint32_t* words = nullptr, uint32_t stream = 0u) {
     uint32_t w[8];
     philox10(i, v, stream, m << 16, key0, key1, w);
@@ -140,7 +146,14 @@ __device__ __forceinline__ void draw_params(const ModelDev& md, uint32_t key0, u
         w[4] = w[5] = w[6] = w[7] = 0u;
     }
 #pragma unroll
-    for (int j = 0; j < 5; ++j) th[j] = (j < md.np) ? __builtin_fmaf(md.wid[j], unit24(w[j]), md.lo[j]) : 0.0f;
+    for (int j = 0; j < kMaxParams; ++j) {
+        float lo = md.lo[j], wid = md.wid[j];
+        if (j == 5 && md.rel_tp) {  // tP in [tD + offset, hi]
+            lo = th[4] + md.lo[5];
+            wid = md.wid[5] - lo;
+        }
+        th[j] = (j < md.np) ? __builtin_fmaf(wid, unit24(w[j]), lo) : 0.0f;
+    }
     if (words) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) words[j] = (j < 4 * ((md.np + 3) / 4)) ? w[j] : 0u;
@@ -194,6 +207,11 @@ struct ModelTraits<KIND_REV> {
     static constexpr int NE = 2;
     static constexpr bool Q = false;
 };
+template <>
+struct ModelTraits<KIND_MRTM> {
+    static constexpr int NE = 1;
+    static constexpr bool Q = false;
+};
 
 template <int NE, int U>
 struct DrawState {
@@ -203,10 +221,18 @@ struct DrawState {
 
 // th: parameters in model order.  Fills the per-draw state for column u.
 template <int KIND, int NE, int U>
-__device__ __forceinline__ void setup(const float th[5], double h, double C0, DrawState<NE, U>& s,
+__device__ __forceinline__ void setup(const float* th, double h, double C0, DrawState<NE, U>& s,
                                       int u) {
     const double K1 = th[0], k2 = th[1];
-    if constexpr (KIND == KIND_1TCM) {
+    if constexpr (KIND == KIND_MRTM) {
+        // Eq. (3) with gamma = 0: C_t = R1 C_r + (k2 - R1 k2a) exp(-k2a t) * C_r
+        const double R1 = th[0], k2a = th[2];
+        double bA;
+        Exp1 e = exp_setup(k2a, k2 - R1 * k2a, h, C0, &bA);
+        s.z[0][u] = e.z; s.H[0][u] = e.H0; s.c[0][u] = e.c; s.rc[0][u] = e.rc; s.eT[0][u] = e.eT;
+        s.e0[u] = 0.0;
+        s.eP[u] = R1 + bA;
+    } else if constexpr (KIND == KIND_1TCM) {
         const double vB = th[2];
         const double w = 1.0 - vB;
         double bA;
@@ -366,6 +392,76 @@ __device__ __forceinline__ void simulate_draws(const Tab& T, int F, int k0, Draw
 }
 
 // ---------------------------------------------------------------------------
+// lp-ntPET (Eq. (3)-(4)) as the ODE C_t' = R1 C_r' + k2 C_r - kappa(t) C_t with
+// kappa = k2a + gamma g(t): with C_t = R1 C_r + z, z' = (k2 - R1 kappa) C_r -
+// kappa z.  kappa is frozen at each step's midpoint and the step is integrated
+// exactly for the reference TAC C_r linear between nodes:
+//   z_{k+1} = e^{-x} z_k + (k2 - R1 kappa) (a C_k + b C_{k+1}),  x = kappa h,
+//   a = h (1 - (1 + x) e^{-x}) / x^2,  b = h (e^{-x} - 1 + x) / x^2.
+// g(t) = s^alpha e^{alpha (1 - s)}, s = (t - tD) / (tP - tD), for t > tD.  The
+// frame value is the trapezoid sum of the node TAC.  One draw per lane.
+// ---------------------------------------------------------------------------
+struct StepW {
+    double e, a, b;
+};
+
+__device__ __forceinline__ StepW step_weights(double kappa, double h) {
+    const double x = kappa * h;
+    const double c = -expm1(-x);  // 1 - e^{-x}
+    const double rx2 = 1.0 / (x * x);
+    // a/h = (c - x (1 - c)) / x^2 and b/h = (x - c) / x^2 lose digits for small
+    // x: Taylor series below 0.01
+    const double as = 0.5 + x * (-1.0 / 3.0 + x * (1.0 / 8.0 + x * (-1.0 / 30.0 + x * (1.0 / 144.0))));
+    const double bs = 0.5 + x * (-1.0 / 6.0 + x * (1.0 / 24.0 + x * (-1.0 / 120.0 + x * (1.0 / 720.0))));
+    StepW w;
+    w.e = 1.0 - c;
+    w.a = h * ((x < 0.01) ? as : (c - x * (1.0 - c)) * rx2);
+    w.b = h * ((x < 0.01) ? bs : (x - c) * rx2);
+    return w;
+}
+
+template <class Sink>
+__device__ void simulate_lpnt(const float* th, const Tab& T, int F, int k0, double h, Sink& sink) {
+    const double R1 = th[0], k2 = th[1], k2a = th[2], gam = th[3], tD = th[4], tP = th[5], alpha = th[6];
+    const double rspan = 1.0 / (tP - tD);
+    const StepW w0 = step_weights(k2a, h);  // the steps without activation
+    const double src0 = k2 - R1 * k2a;
+    const cdp C = (cdp)T.C;
+    const cdp FR = (cdp)T.fr;
+    const cip NF = (cip)T.nf;
+    (void)FR;
+    double z = 0.0, c_prev = C[0];
+    int k = 0;
+    auto step = [&]() {
+        const double c_next = C[k + 1];
+        const double tm = ((double)k + 0.5) * h;
+        if (tm > tD) {
+            const double sv = (tm - tD) * rspan;
+            const double kap = k2a + gam * exp(alpha * (log(sv) + 1.0 - sv));
+            const StepW w = step_weights(kap, h);
+            z = fma(w.e, z, (k2 - R1 * kap) * fma(w.a, c_prev, w.b * c_next));
+        } else {
+            z = fma(w0.e, z, src0 * fma(w0.a, c_prev, w0.b * c_next));
+        }
+        c_prev = c_next;
+        ++k;
+        return fma(R1, c_next, z);  // node TAC at t_k
+    };
+    double ct = R1 * c_prev;
+    while (k < k0) ct = step();
+    for (int f = 0; f < F; ++f) {
+        const int n = NF[f];
+        double x = 0.5 * ct;
+        for (int q = 0; q < n; ++q) {
+            ct = step();
+            x += (q + 1 < n) ? ct : 0.5 * ct;
+        }
+        const double X[1] = {x};
+        sink(f, n, X);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Wavefront / block helpers.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_lds_sync() {
@@ -462,17 +558,18 @@ __device__ __forceinline__ T wave_sum(T v) {
 // Sum of NV values over the block; every thread gets the totals.
 template <int NV>
 __device__ void block_sum(double (&v)[NV], double* red, int wpv) {
+    static_assert(NV <= kRedStride, "reduction scratch per wavefront");
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
     if (lane_id() == 0)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) red[wave * 8 + q] = v[q];
+        for (int q = 0; q < NV; ++q) red[wave * kRedStride + q] = v[q];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         double t = 0.0;
-        for (int w = 0; w < wpv; ++w) t += red[w * 8 + q];
+        for (int w = 0; w < wpv; ++w) t += red[w * kRedStride + q];
         v[q] = t;
     }
     __syncthreads();
@@ -518,7 +615,7 @@ __device__ __forceinline__ void tile_keys(const InferArgs& P, int m, uint32_t v,
         const uint32_t i = i0 + (uint32_t)(u * kWave + lane_id());
         ok[u] = i < P.n_draws;
         idx[u] = ok[u] ? i : P.n_draws - 1;
-        float th[5];
+        float th[kMaxParams];
         draw_params(md, P.key0, P.key1, v, idx[u], (uint32_t)m, th);
         setup<KIND, NE, U>(th, P.h, P.C0, s, u);
     }
@@ -572,7 +669,7 @@ __global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
     const int yw_bytes = (16 * F + 15) & ~15;
     uint64_t* keys_all = reinterpret_cast<uint64_t*>(lds + yw_bytes);
     double* red = reinterpret_cast<double*>(keys_all + (size_t)P.wpv * P.cap);
-    int* flag = reinterpret_cast<int*>(red + 8 * kMaxWpv);
+    int* flag = reinterpret_cast<int*>(red + kRedStride * kMaxWpv);
     const int n = (int)P.n_acc;
 
     // Observed curve, validity and scaled weights (wave 0).
@@ -671,7 +768,7 @@ __global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
         for (int j = tid; j < n; j += blockDim.x) {
             const uint32_t g = (uint32_t)acc[j];
             if (g / P.n_draws != (uint32_t)m) continue;
-            float th[5];
+            float th[kMaxParams];
             draw_params(md, P.key0, P.key1, vg, g - (uint32_t)m * P.n_draws, (uint32_t)m, th);
             double val[6];
             slot_values(md.kind, th, val);
@@ -690,7 +787,7 @@ __global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
         for (int j = tid; j < n; j += blockDim.x) {
             const uint32_t g = (uint32_t)acc[j];
             if (g / P.n_draws != (uint32_t)m) continue;
-            float th[5];
+            float th[kMaxParams];
             draw_params(md, P.key0, P.key1, vg, g - (uint32_t)m * P.n_draws, (uint32_t)m, th);
             double val[6];
             slot_values(md.kind, th, val);
@@ -722,20 +819,26 @@ __global__ __launch_bounds__(256) void vpet_simulate_kernel(const float* __restr
     const long long row = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool ok = row < n;
     const long long r = ok ? row : n - 1;
-    float th[5];
+    float th[kMaxParams] = {};
     const float* t = theta + (size_t)r * VPET_PSTRIDE;
     if (KIND == KIND_1TCM) {
-        th[0] = t[0]; th[1] = t[1]; th[2] = t[4]; th[3] = 0.f; th[4] = 0.f;
+        th[0] = t[0]; th[1] = t[1]; th[2] = t[4];
     } else if (KIND == KIND_IRR) {
-        th[0] = t[0]; th[1] = t[1]; th[2] = t[2]; th[3] = t[4]; th[4] = 0.f;
-    } else {
+        th[0] = t[0]; th[1] = t[1]; th[2] = t[2]; th[3] = t[4];
+    } else if (KIND == KIND_REV) {
         th[0] = t[0]; th[1] = t[1]; th[2] = t[2]; th[3] = t[3]; th[4] = t[4];
+    } else {  // reference-tissue models: slots are the draw order
+        for (int j = 0; j < (KIND == KIND_LPNT ? 7 : 3); ++j) th[j] = t[j];
     }
-    constexpr int NE = ModelTraits<KIND>::NE;
-    DrawState<NE, 1> s;
-    setup<KIND, NE, 1>(th, h, C0, s, 0);
     TacSink sink{ok ? out + (size_t)row * F : nullptr};
-    simulate_draws<KIND, 1>(T, F, k0, s, sink);
+    if constexpr (KIND == KIND_LPNT) {
+        simulate_lpnt(th, T, F, k0, h, sink);
+    } else {
+        constexpr int NE = ModelTraits<KIND>::NE;
+        DrawState<NE, 1> s;
+        setup<KIND, NE, 1>(th, h, C0, s, 0);
+        simulate_draws<KIND, 1>(T, F, k0, s, sink);
+    }
 }
 
 __global__ __launch_bounds__(256) void vpet_draws_kernel(ModelDev md0, ModelDev md1, ModelDev md2, int M,
@@ -751,7 +854,7 @@ __global__ __launch_bounds__(256) void vpet_draws_kernel(ModelDev md0, ModelDev 
     for (int q = 0; q < 8; ++q) w_out[q] = 0u;
     if (m < 0 || m >= M) return;
     const ModelDev& md = (m == 0) ? md0 : (m == 1 ? md1 : md2);
-    float th[5];
+    float th[kMaxParams];
     uint32_t words[8];
     draw_params(md, key0, key1, (uint32_t)voxel[j], (uint32_t)draw[j], (uint32_t)m, th, words);
     for (int q = 0; q < 8; ++q) w_out[q] = words[q];
@@ -781,7 +884,7 @@ __global__ __launch_bounds__(256) void vpet_bank_kernel(ModelDev md, int m, unsi
     const bool ok = i < n_draws;
     const unsigned ii = ok ? i : n_draws - 1;
     const size_t g = (size_t)m * n_draws + ii;
-    float th[5];
+    float th[kMaxParams];
     draw_params(md, key0, key1, 0u, ii, (uint32_t)m, th, nullptr, 1u);
     if (ok) {
         float* to = theta_out + g * VPET_PSTRIDE;
@@ -790,11 +893,15 @@ __global__ __launch_bounds__(256) void vpet_bank_kernel(ModelDev md, int m, unsi
         double* row = x_out + g * (size_t)ld;
         for (int f = F; f < ld; ++f) row[f] = 0.0;  // padding frames contribute nothing
     }
-    constexpr int NE = ModelTraits<KIND>::NE;
-    DrawState<NE, 1> s;
-    setup<KIND, NE, 1>(th, h, C0, s, 0);
     BankSink sink{ok ? x_out + g * (size_t)ld : nullptr};
-    simulate_draws<KIND, 1>(T, F, k0, s, sink);
+    if constexpr (KIND == KIND_LPNT) {
+        simulate_lpnt(th, T, F, k0, h, sink);
+    } else {
+        constexpr int NE = ModelTraits<KIND>::NE;
+        DrawState<NE, 1> s;
+        setup<KIND, NE, 1>(th, h, C0, s, 0);
+        simulate_draws<KIND, 1>(T, F, k0, s, sink);
+    }
 }
 
 struct BankArgs {
@@ -906,7 +1013,8 @@ __device__ __forceinline__ float key_dist(double d) {
     return (fd == fd) ? fd : __builtin_inff();
 }
 
-// PILOT: each lane's 16 smallest distances over the first n_pilot bank rows ->
+// PILOT: each lane's 16 smallest distances over n_pilot bank rows spread evenly
+// over the bank (it is ordered by model) ->
 // tau.  SCAN: every bank row; rows with fp32 distance <= tau are appended to
 // the voxel's candidate list.
 template <int LD, bool L1, bool PILOT>
@@ -921,7 +1029,9 @@ __global__ __launch_bounds__(256) void vpet_bank_scan_kernel(BankArgs P) {
         float top[kBankTopK];
 #pragma unroll
         for (int q = 0; q < kBankTopK; ++q) top[q] = __builtin_inff();
-        for (unsigned g = 0; g < P.n_pilot; ++g) {
+        for (unsigned j = 0; j < P.n_pilot; ++j) {
+            // pilot rows spread evenly over the bank (it is ordered by model)
+            const unsigned g = (unsigned)(((uint64_t)j * P.n_tot) / P.n_pilot);
             const float fd = key_dist(bank_distance<LD, L1>(X + (size_t)g * LD, Y, Wt));
             if (fd < top[kBankTopK - 1]) {  // insert into the sorted list
 #pragma unroll
@@ -946,6 +1056,26 @@ __global__ __launch_bounds__(256) void vpet_bank_scan_kernel(BankArgs P) {
     }
 }
 
+// Canonical slot values of a bank draw (bank_theta rows are already in slot
+// order) with the derived slot: Ki = K1 k3 / (k2 + k3) for the 2TCMs, BP_ND =
+// k2 / k2a - 1 for the reference-tissue models; unused slots 0.
+__device__ __forceinline__ bool bank_slot_used(int kind, int q) {
+    switch (kind) {
+        case KIND_1TCM: return q == 0 || q == 1 || q == 4;
+        case KIND_IRR: return q <= 5 && q != 3;
+        case KIND_REV: return q <= 5;
+        case KIND_MRTM: return q <= 2 || q == 7;
+        default: return true;  // lp-ntPET: all seven parameters and BP_ND
+    }
+}
+
+__device__ __forceinline__ void bank_slot_values(int kind, const float* t, double (&val)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) val[q] = bank_slot_used(kind, q) ? (double)t[q] : 0.0;
+    if (kind == KIND_IRR || kind == KIND_REV) val[5] = val[0] * val[2] / (val[1] + val[2]);
+    if (kind == KIND_MRTM || kind == KIND_LPNT) val[7] = val[1] / val[2] - 1.0;
+}
+
 // Outputs of one voxel from its n accepted keys (sorted, in LDS).
 __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* acc, double* red) {
     const int n = (int)P.n_acc;
@@ -958,45 +1088,41 @@ __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* a
     if (P.out_thr && tid == 0) P.out_thr[row] = __uint_as_float((uint32_t)(acc[n - 1] >> 32));
     for (int m = 0; m < P.M; ++m) {
         const int kind = P.kinds[m];
-        double s1[7];
+        double s1[9];
 #pragma unroll
-        for (int q = 0; q < 7; ++q) s1[q] = 0.0;
-        double val[6];
+        for (int q = 0; q < 9; ++q) s1[q] = 0.0;
+        double val[8];
         for (int j = tid; j < n; j += blockDim.x) {
             const uint32_t g = (uint32_t)acc[j];
             if (g / P.n_draws != (uint32_t)m) continue;
-            const float* t = P.bank_theta + (size_t)g * VPET_PSTRIDE;
-            const float th[5] = {t[0], t[1], kind == KIND_1TCM ? t[4] : t[2], kind == KIND_REV ? t[3] : t[4], t[4]};
-            slot_values(kind, th, val);
+            bank_slot_values(kind, P.bank_theta + (size_t)g * VPET_PSTRIDE, val);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) s1[q] += val[q];
-            s1[6] += 1.0;
+            for (int q = 0; q < 8; ++q) s1[q] += val[q];
+            s1[8] += 1.0;
         }
-        block_sum<7>(s1, red, blockDim.x >> 6);
-        const double cnt = s1[6];
-        double mean[6], s2[6];
+        block_sum<9>(s1, red, blockDim.x >> 6);
+        const double cnt = s1[8];
+        double mean[8], s2[8];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
+        for (int q = 0; q < 8; ++q) {
             mean[q] = s1[q] / cnt;
             s2[q] = 0.0;
         }
         for (int j = tid; j < n; j += blockDim.x) {
             const uint32_t g = (uint32_t)acc[j];
             if (g / P.n_draws != (uint32_t)m) continue;
-            const float* t = P.bank_theta + (size_t)g * VPET_PSTRIDE;
-            const float th[5] = {t[0], t[1], kind == KIND_1TCM ? t[4] : t[2], kind == KIND_REV ? t[3] : t[4], t[4]};
-            slot_values(kind, th, val);
+            bank_slot_values(kind, P.bank_theta + (size_t)g * VPET_PSTRIDE, val);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 const double dv = val[q] - mean[q];
                 s2[q] = fma(dv, dv, s2[q]);
             }
         }
-        block_sum<6>(s2, red, blockDim.x >> 6);
+        block_sum<8>(s2, red, blockDim.x >> 6);
         if (tid < 16) {
             const int q = tid >> 1;
             float outv = __builtin_nanf("");
-            if (q < 6 && slot_used(kind, q) && cnt > 0.0) {
+            if (bank_slot_used(kind, q) && cnt > 0.0) {
                 if ((tid & 1) == 0)
                     outv = (float)mean[q];
                 else
@@ -1258,7 +1384,8 @@ __host__ __device__ constexpr double contraction_rel_err() {
 // and k-step a wavefront issues v_mfma_f32_32x32x16_bf16 on the hi/lo parts:
 // hi*hi + hi*lo + lo*hi gives S ~ sum_k A B.
 //
-// PILOT (the first n_pilot rows): lane l keeps, for each of its 16 voxels, the
+// PILOT (n_pilot rows, taken from tiles spread evenly over the bank, which is
+// ordered by model): lane l keeps, for each of its 16 voxels, the
 // minimum of S over the rows = l mod 32; the 16th smallest of a voxel's 32
 // column minima, plus a_v, is its threshold tau_v (rounded to fp32).  With
 // n_pilot = 5.5 N / n about 4 n bank rows fall below tau_v (order statistics of
@@ -1278,13 +1405,13 @@ __host__ __device__ constexpr double contraction_rel_err() {
 // Lane layout (32x32x16): A row = lane % 32, B column = lane % 32,
 // k = 16 ks + 8 (lane / 32) + e; result r of a lane is row 8 (r/4) + 4 (lane/32) + r%4.
 template <int K, bool PILOT>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void vpet_bank_mfma_kernel(BankArgs P) {
+__device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
     constexpr int KS = K / 16;
     constexpr int RS = 2 * K + 16;        // LDS row stride (bytes), padded against bank conflicts
     constexpr int TR = 2 * kMfmaRows;     // bank rows per tile: two 32-row halves
     constexpr int CA = TR * K / 8;        // 16-byte chunks per array (hi or lo) per tile
     constexpr int CPT = (2 * CA + 511) / 512;  // chunks per thread and tile
-    static_assert(CA % 64 == 0 && CPT <= 2, "whole wavefronts per array, at most two chunks per thread");
+    static_assert(CA % 64 == 0 && CPT <= 3, "whole wavefronts per array, at most three chunks per thread");
     __shared__ __align__(16) unsigned char tile[2][2][TR * RS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long vbase = (long long)blockIdx.x * kMfmaVox;
@@ -1318,8 +1445,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void v
     uint64_t* wcand = P.cand + (size_t)(vbase + wave * 32) * P.cap;
     const uint32_t lt = (1u << (lane & 31)) - 1u;  // lanes below mine in my half-wave
 
-    const unsigned n_rows = PILOT ? P.n_pilot : P.n_tot;
-    const unsigned ntiles = (n_rows + TR - 1) / TR;
+    // PILOT: ceil(n_pilot / TR) tiles spread evenly over the bank (it is
+    // ordered by model, so a prefix would see one model only)
+    const unsigned n_rows = P.n_tot;
+    const unsigned all_tiles = (n_rows + TR - 1) / TR;
+    const unsigned pilot_tiles = (P.n_pilot + TR - 1) / TR;
+    const unsigned ntiles = (PILOT && pilot_tiles < all_tiles) ? pilot_tiles : all_tiles;
+    auto tile_row0 = [&](unsigned t) {
+        return (PILOT ? (unsigned)(((uint64_t)t * all_tiles) / ntiles) : t) * (unsigned)TR;
+    };
     // this thread's 16-byte chunks of a tile: array (hi/lo; CA is a multiple of
     // 64, so the array is the same for the whole wavefront), row, column
     const uint16_t* c_src[CPT];
@@ -1339,7 +1473,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void v
     auto fetch = [&](unsigned t) {
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
-            const unsigned g = t * TR + c_row[u];
+            const unsigned g = tile_row0(t) + c_row[u];
             pre[u] = make_uint4(0, 0, 0, 0);
             if (c_has[u] && g < n_rows) pre[u] = *reinterpret_cast<const uint4*>(c_src[u] + (size_t)g * K);
         }
@@ -1351,10 +1485,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void v
     };
     // screen one 32-row half: r-th results against the thresholds, passing
     // rows appended to their voxel's list
-    auto screen = [&](const f32x16_t& acc, unsigned g0) {
+    // j0: position of the half's first row in the pilot sample (PILOT only)
+    auto screen = [&](const f32x16_t& acc, unsigned g0, unsigned j0) {
         const unsigned g = g0 + (lane & 31);
         if (PILOT) {
-            if (g < n_rows) {
+            if (g < n_rows && j0 + (lane & 31) < P.n_pilot) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) cth[r] = fminf(cth[r], acc[r]);
             }
@@ -1409,8 +1544,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void v
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ks], bh0, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ks], bh1, acc1, 0, 0, 0);
         }
-        screen(acc0, t * TR);
-        screen(acc1, t * TR + kMfmaRows);
+        screen(acc0, tile_row0(t), t * TR);
+        screen(acc1, tile_row0(t) + kMfmaRows, t * TR + kMfmaRows);
         __syncthreads();
     }
     if (PILOT) {
@@ -1464,6 +1599,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void v
         const long long v = vbase + wave * 32 + lane;
         if (v < P.V && P.cthr[v] > -__builtin_inff()) P.cnt[v] = (int)cntv;
     }
+}
+
+// Up to 32 frames the kernel fits 128 VGPRs (4 wavefronts per SIMD, two
+// blocks per CU); 40 and 48 frames need more registers and run at 3.
+template <int K, bool PILOT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void vpet_bank_mfma_kernel(BankArgs P) {
+    bank_mfma_body<K, PILOT>(P);
+}
+template <int K, bool PILOT>
+__global__ __launch_bounds__(512) void vpet_bank_mfma_wide_kernel(BankArgs P) {
+    bank_mfma_body<K, PILOT>(P);
+}
+
+template <int K, bool PILOT>
+void launch_mfma(dim3 grid, hipStream_t st, const BankArgs& Q) {
+    if constexpr (K <= 64)
+        hipLaunchKernelGGL((vpet_bank_mfma_kernel<K, PILOT>), grid, dim3(512), 0, st, Q);
+    else
+        hipLaunchKernelGGL((vpet_bank_mfma_wide_kernel<K, PILOT>), grid, dim3(512), 0, st, Q);
 }
 
 // ===========================================================================
@@ -1526,7 +1680,7 @@ int make_tables(const float* input_fn, const float* frame_times, vpet_grid g, do
     for (int k = 0; k <= T.kend; ++k) Cn[k] = (double)input_fn[k];
     Q[0] = 0.0;
     for (int k = 0; k < T.kend; ++k) Q[k + 1] = Q[k] + 0.5 * T.h * (Cn[k] + Cn[k + 1]);
-    T.C.assign(Cn.begin(), Cn.begin() + T.kend);
+    T.C.assign(Cn.begin(), Cn.begin() + T.kend + 1);
     T.fr.assign(4 * (size_t)T.F, 0.0);
     T.nf.assign(T.F, 0);
     for (int f = 0; f < T.F; ++f) {
@@ -1548,15 +1702,53 @@ int make_tables(const float* input_fn, const float* frame_times, vpet_grid g, do
     return VPET_OK;
 }
 
+// Model kinds in bit order; -1 for unknown bits or a mix of the plasma-input
+// family (1TCM, 2TCMs) and the reference-tissue family (MRTM, lp-ntPET),
+// whose inputs differ.
 int model_list(uint32_t model_id, int kinds[kMaxModels]) {
-    if (model_id == 0u || (model_id & ~(VPET_M_1TCM | VPET_M_2TCM_IRR | VPET_M_2TCM_REV)) != 0u) return -1;
+    constexpr uint32_t plasma = VPET_M_1TCM | VPET_M_2TCM_IRR | VPET_M_2TCM_REV;
+    constexpr uint32_t reference = VPET_M_MRTM | VPET_M_LPNTPET;
+    if (model_id == 0u || (model_id & ~(plasma | reference)) != 0u) return -1;
+    if ((model_id & plasma) && (model_id & reference)) return -1;
     int M = 0;
-    for (uint32_t b = 1u; b <= VPET_M_2TCM_REV; b <<= 1)
+    for (uint32_t b = 1u; b <= VPET_M_LPNTPET; b <<= 1)
         if (model_id & b) kinds[M++] = (int)b;
     return M;
 }
 
+bool is_reference(int kind) { return kind == KIND_MRTM || kind == KIND_LPNT; }
+
+int fill_reference_model(int kind, const double* box, ModelDev& md) {
+    md = ModelDev{};
+    md.kind = kind;
+    md.np = kind == KIND_MRTM ? 3 : 7;
+    md.rel_tp = kind == KIND_LPNT;
+    for (int j = 0; j < md.np; ++j) {
+        const double lo = box[2 * j], hi = box[2 * j + 1];
+        if (!(std::isfinite(lo) && std::isfinite(hi))) return fail(VPET_E_ARG, "prior box slot %d is not finite", j);
+        if (lo > hi) return fail(VPET_E_ARG, "prior box slot %d has lo > hi", j);
+        if (lo < 0.0) return fail(VPET_E_ARG, "prior box slot %d must be >= 0", j);
+        md.slot[j] = j;
+        md.lo[j] = (float)lo;
+        md.wid[j] = (float)(hi - lo);
+    }
+    if (!(box[2 * VPET_SLOT_K2A] > 0.0)) return fail(VPET_E_ARG, "k2a prior needs lo > 0");
+    if (kind == KIND_LPNT) {
+        // tP in [tD + lo, hi]: lo is an offset; the interval must be non-empty
+        // for every tD in its box
+        const double off = box[2 * VPET_SLOT_TP], hi = box[2 * VPET_SLOT_TP + 1];
+        if (!(off > 0.0)) return fail(VPET_E_ARG, "the tP offset after tD (box lo) must be > 0");
+        if (!(box[2 * VPET_SLOT_TD + 1] + off <= hi))
+            return fail(VPET_E_ARG, "tP box: tD_hi + offset must not exceed tP_hi");
+        if (!(box[2 * VPET_SLOT_ALPHA] > 0.0)) return fail(VPET_E_ARG, "alpha prior needs lo > 0");
+        md.lo[VPET_SLOT_TP] = (float)off;
+        md.wid[VPET_SLOT_TP] = (float)hi;
+    }
+    return VPET_OK;
+}
+
 int fill_model(int kind, const double* box, ModelDev& md) {
+    if (is_reference(kind)) return fill_reference_model(kind, box, md);
     static const int s1[3] = {VPET_SLOT_K1, VPET_SLOT_K2, VPET_SLOT_VB};
     static const int s2[4] = {VPET_SLOT_K1, VPET_SLOT_K2, VPET_SLOT_K3, VPET_SLOT_VB};
     static const int s3[5] = {VPET_SLOT_K1, VPET_SLOT_K2, VPET_SLOT_K3, VPET_SLOT_K4, VPET_SLOT_VB};
@@ -1721,15 +1913,17 @@ int vpet_abc_simulate(uint32_t model_id, const float* theta, int64_t n, const fl
         const unsigned blocks = (unsigned)((cnt + threads - 1) / threads);
         const float* th = theta + (size_t)base * VPET_PSTRIDE;
         float* out = out_tacs + (size_t)base * T.F;
-        if (kinds[0] == KIND_1TCM)
-            hipLaunchKernelGGL(vpet_simulate_kernel<KIND_1TCM>, dim3(blocks), dim3(threads), 0, st, th, cnt, tab, T.C0,
-                               T.h, T.F, T.k0, out);
-        else if (kinds[0] == KIND_IRR)
-            hipLaunchKernelGGL(vpet_simulate_kernel<KIND_IRR>, dim3(blocks), dim3(threads), 0, st, th, cnt, tab, T.C0,
-                               T.h, T.F, T.k0, out);
-        else
-            hipLaunchKernelGGL(vpet_simulate_kernel<KIND_REV>, dim3(blocks), dim3(threads), 0, st, th, cnt, tab, T.C0,
-                               T.h, T.F, T.k0, out);
+#define VPET_SIM(KD)                                                                                  \
+    hipLaunchKernelGGL(vpet_simulate_kernel<KD>, dim3(blocks), dim3(threads), 0, st, th, cnt, tab, T.C0, T.h, \
+                       T.F, T.k0, out)
+        switch (kinds[0]) {
+            case KIND_1TCM: VPET_SIM(KIND_1TCM); break;
+            case KIND_IRR: VPET_SIM(KIND_IRR); break;
+            case KIND_REV: VPET_SIM(KIND_REV); break;
+            case KIND_MRTM: VPET_SIM(KIND_MRTM); break;
+            default: VPET_SIM(KIND_LPNT); break;
+        }
+#undef VPET_SIM
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "simulate launch");
     }
@@ -1745,6 +1939,8 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
     int kinds[kMaxModels];
     const int M = model_list(model_id, kinds);
     if (M < 1) return fail(VPET_E_MODEL, "unknown or empty model bitmask 0x%x", model_id);
+    if (is_reference(kinds[0]))
+        return fail(VPET_E_MODEL, "reference-tissue models run in the shared-bank form (vpet_abc_infer_bank)");
     if (n_voxels < 0) return fail(VPET_E_ARG, "n_voxels must be >= 0");
     if (!prior_box) return fail(VPET_E_ARG, "prior_box must not be NULL");
     if (n_draws < 1) return fail(VPET_E_ARG, "n_draws must be >= 1");
@@ -1784,7 +1980,7 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
         while (wpv < kMaxWpv && (double)n_voxels * wpv < 8192.0) wpv <<= 1;
     }
     auto lds_for = [&](int w) {
-        return (size_t)((16 * T.F + 15) & ~15) + sizeof(uint64_t) * (size_t)w * cap + sizeof(double) * 8 * kMaxWpv + 16;
+        return (size_t)((16 * T.F + 15) & ~15) + sizeof(uint64_t) * (size_t)w * cap + sizeof(double) * kRedStride * kMaxWpv + 16;
     };
     while (wpv > 1 && lds_for(wpv) > (size_t)kLdsLimit) wpv >>= 1;
     if (lds_for(wpv) > (size_t)kLdsLimit) return fail(VPET_E_LIMIT, "selection buffer exceeds LDS");
@@ -1909,15 +2105,17 @@ int vpet_abc_bank_build(uint32_t model_id, const double* prior_box, int64_t n_dr
     const unsigned threads = 256, blocks = (unsigned)((n_draws + threads - 1) / threads);
     const unsigned k0 = (unsigned)(seed & 0xffffffffu), k1 = (unsigned)(seed >> 32);
     for (int m = 0; m < M; ++m) {
-        if (kinds[m] == KIND_1TCM)
-            hipLaunchKernelGGL(vpet_bank_kernel<KIND_1TCM>, dim3(blocks), dim3(threads), 0, st, md[m], m,
-                               (unsigned)n_draws, k0, k1, tab, T.C0, T.h, T.F, T.k0, ld, out_theta, out_x);
-        else if (kinds[m] == KIND_IRR)
-            hipLaunchKernelGGL(vpet_bank_kernel<KIND_IRR>, dim3(blocks), dim3(threads), 0, st, md[m], m,
-                               (unsigned)n_draws, k0, k1, tab, T.C0, T.h, T.F, T.k0, ld, out_theta, out_x);
-        else
-            hipLaunchKernelGGL(vpet_bank_kernel<KIND_REV>, dim3(blocks), dim3(threads), 0, st, md[m], m,
-                               (unsigned)n_draws, k0, k1, tab, T.C0, T.h, T.F, T.k0, ld, out_theta, out_x);
+#define VPET_BANK(KD)                                                                                  \
+    hipLaunchKernelGGL(vpet_bank_kernel<KD>, dim3(blocks), dim3(threads), 0, st, md[m], m, (unsigned)n_draws, k0, \
+                       k1, tab, T.C0, T.h, T.F, T.k0, ld, out_theta, out_x)
+        switch (kinds[m]) {
+            case KIND_1TCM: VPET_BANK(KIND_1TCM); break;
+            case KIND_IRR: VPET_BANK(KIND_IRR); break;
+            case KIND_REV: VPET_BANK(KIND_REV); break;
+            case KIND_MRTM: VPET_BANK(KIND_MRTM); break;
+            default: VPET_BANK(KIND_LPNT); break;
+        }
+#undef VPET_BANK
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "bank launch");
     }
@@ -2062,13 +2260,13 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         q += sz_c;
         A.aval = reinterpret_cast<double*>(q);
     }
-    const size_t lds = sizeof(uint64_t) * cap + sizeof(double) * 8 * kMaxWpv;
+    const size_t lds = sizeof(uint64_t) * cap + sizeof(double) * kRedStride * kMaxWpv;
     // fallback blocks: up to 8 wavefronts, each with its own pow2(n + 128)-key
     // top-n, within 48 KB of LDS
     const int fb_cap = pow2_at_least((int)n_acc + 2 * kWave);
     int fb_waves = 8;
     while (fb_waves > 1 && (size_t)fb_waves * fb_cap * sizeof(uint64_t) > 48 * 1024) fb_waves >>= 1;
-    const size_t fb_lds = sizeof(uint64_t) * (size_t)fb_waves * fb_cap + sizeof(double) * 8 * fb_waves;
+    const size_t fb_lds = sizeof(uint64_t) * (size_t)fb_waves * fb_cap + sizeof(double) * kRedStride * fb_waves;
     A.fb_cap = fb_cap;
     const bool mfma = use_mfma;
     if (o.out_fallback_voxels) *o.out_fallback_voxels = 0;
@@ -2091,7 +2289,9 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
             case 8: hipLaunchKernelGGL((vpet_bank_bops_kernel<8>), gb, b256, 0, st, A); break;
             case 16: hipLaunchKernelGGL((vpet_bank_bops_kernel<16>), gb, b256, 0, st, A); break;
             case 24: hipLaunchKernelGGL((vpet_bank_bops_kernel<24>), gb, b256, 0, st, A); break;
-            default: hipLaunchKernelGGL((vpet_bank_bops_kernel<32>), gb, b256, 0, st, A); break;
+            case 32: hipLaunchKernelGGL((vpet_bank_bops_kernel<32>), gb, b256, 0, st, A); break;
+            case 40: hipLaunchKernelGGL((vpet_bank_bops_kernel<40>), gb, b256, 0, st, A); break;
+            default: hipLaunchKernelGGL((vpet_bank_bops_kernel<48>), gb, b256, 0, st, A); break;
         }
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "bank operand launch");
@@ -2114,9 +2314,9 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         hipLaunchKernelGGL(vpet_bank_reset_kernel, one, one, 0, st, Q);                                   \
         if (mfma) {                                                                                       \
             hipLaunchKernelGGL((vpet_bank_aops_kernel<LDV>), lanes, b256, 0, st, Q);                      \
-            hipLaunchKernelGGL((vpet_bank_mfma_kernel<2 * LDV, true>), mblocks, b512, 0, st, Q);          \
+            launch_mfma<2 * LDV, true>(mblocks, st, Q);                                                   \
             mark(0);                                                                                      \
-            hipLaunchKernelGGL((vpet_bank_mfma_kernel<2 * LDV, false>), mblocks, b512, 0, st, Q);         \
+            launch_mfma<2 * LDV, false>(mblocks, st, Q);                                                  \
             mark(1);                                                                                      \
             hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, true>), per_voxel, b64, lds, st, Q);    \
         } else {                                                                                          \
@@ -2137,7 +2337,11 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
             case 6: VPET_BANK_LAUNCH(24, false); break;
             case 7: VPET_BANK_LAUNCH(24, true); break;
             case 8: VPET_BANK_LAUNCH(32, false); break;
-            default: VPET_BANK_LAUNCH(32, true); break;
+            case 9: VPET_BANK_LAUNCH(32, true); break;
+            case 10: VPET_BANK_LAUNCH(40, false); break;
+            case 11: VPET_BANK_LAUNCH(40, true); break;
+            case 12: VPET_BANK_LAUNCH(48, false); break;
+            default: VPET_BANK_LAUNCH(48, true); break;
         }
 #undef VPET_BANK_LAUNCH
         e = hipGetLastError();

@@ -126,9 +126,9 @@ def test_bank_validation_without_gpu(V):
     assert V.lib.vpet_abc_bank_build(0, P(box), 10, 1, P(cp), P(ft), g, None, None, None) == V.E_MODEL
     assert V.lib.vpet_abc_bank_build(2, P(box), 0, 1, P(cp), P(ft), g, None, None, None) == V.E_ARG
     assert V.lib.vpet_abc_bank_build(2, P(box), 10, 1, P(cp), P(ft), g, None, None, None) == V.E_ARG  # NULL outs
-    ft40 = W.frame_times([1.0] * 40)
-    g40 = V._binding.Grid(0.2, 201, 40)
-    cp40 = W.grid(0.2, 40.0)[1]
+    ft40 = W.frame_times([1.0] * 50)
+    g40 = V._binding.Grid(0.2, 251, 50)
+    cp40 = W.grid(0.2, 50.0)[1]
     assert V.lib.vpet_abc_bank_build(2, P(box), 10, 1, P(cp40), P(ft40), g40, None, None, None) == V.E_LIMIT
 
     def ib(model=2, n_draws=1000, p=0.05, grid=g, frames=ft, V_=0, opts=None):
@@ -150,4 +150,15 @@ def test_bank_validation_without_gpu(V):
     assert ib(opts=o) == V.E_ARG                          # unknown scan
     o.bank_scan, o.distance = 2, 1
     assert ib(opts=o) == V.E_ARG                          # bf16 contraction is L2-only
+    # reference-tissue models: no mixing with plasma-input models, valid tP box
+    assert V.lib.vpet_abc_bank_build(2 | 8, P(W.box_array([2, 8])), 10, 1, P(cp), P(ft), g, None, None,
+                                     None) == V.E_MODEL
+    rbox = W.box_array([16])
+    assert V.lib.vpet_abc_bank_build(16, P(rbox), 10, 1, P(cp), P(ft), g, None, None, None) == V.E_ARG  # NULL outs
+    for slot, bad in ((5, (0.0, 70.0)), (5, (25.0, 70.0)), (6, (0.0, 4.0)), (2, (0.0, 0.2))):
+        b2 = rbox.copy()
+        b2[0, slot] = bad
+        assert V.lib.vpet_abc_bank_build(16, P(b2), 10, 1, P(cp), P(ft), g, None, None, None) == V.E_ARG, slot
+    assert V.lib.vpet_abc_infer(None, 0, P(ft), P(cp), g, 8, P(W.box_array([8])), 10, 0.5, 1, None, None, None,
+                                None) == V.E_MODEL                # the per-voxel path does not run them
     assert ib(V_=3) == V.E_ARG                            # NULL device pointers

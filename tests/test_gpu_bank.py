@@ -165,9 +165,9 @@ def test_infer_bank_limits():
         V.infer_bank(torch.from_numpy(y).to(DEV), ft, H, cp.size, [W.M_2TCM_IRR], 1000, 0.01, th, x,
                      distance="l1", bank_scan="bf16")
     assert e.value.status == V.E_ARG
-    ft40 = W.frame_times([1.0] * 40)
+    ft50 = W.frame_times([1.0] * 50)
     with pytest.raises(V.VpetError) as e:
-        V.bank_build([W.M_2TCM_IRR], W.box_array([W.M_2TCM_IRR]), 10, 1, W.grid(H, 40.0)[1], ft40, H)
+        V.bank_build([W.M_2TCM_IRR], W.box_array([W.M_2TCM_IRR]), 10, 1, W.grid(H, 50.0)[1], ft50, H)
     assert e.value.status == V.E_LIMIT
 
 
