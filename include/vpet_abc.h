@@ -58,7 +58,8 @@ typedef enum {
     VPET_E_GRID = 3,   /* frame bound off the grid, outside it, or not increasing */
     VPET_E_HIP = 4,    /* HIP runtime or launch failure                          */
     VPET_E_NOMEM = 5,  /* device or pinned-host allocation failed                */
-    VPET_E_LIMIT = 6   /* valid request beyond a documented capacity             */
+    VPET_E_LIMIT = 6,  /* valid request beyond a documented capacity             */
+    VPET_E_IO = 7      /* a file could not be opened, read or written            */
 } vpet_status;
 
 #define VPET_M_1TCM (1u << 0)     /* one-tissue model: K1 exp(-k2 t)                 */
@@ -279,6 +280,39 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
                         uint32_t model_id, int64_t n_draws, double accept_frac, const float* bank_theta,
                         const double* bank_x, float* out_moments, float* out_model_prob,
                         const vpet_abc_opts* opts, void* hip_stream);
+
+/*
+ * Streamed shared-bank inference of a volume stored in a file (total-body
+ * scale; the whole-volume study of Sec. III-B2).  The observed TACs are read
+ * chunk by chunk from tacs_path (raw little-endian fp32, [n_voxels][F]
+ * row-major, F = grid.n_frames); while chunk c is screened on the GPU, chunk
+ * c+1 is read and copied in and the outputs of chunk c-1 are written to
+ *   <out_prefix>.moments   [n_voxels][M][VPET_PSTRIDE][2] fp32
+ *   <out_prefix>.prob      [n_voxels][M] fp32
+ * at their voxel offsets.  After the outputs of a chunk are on disk,
+ * <out_prefix>.progress (one text line: the run's shape and the number of
+ * completed chunks, replaced atomically) is updated, so a run that stops --
+ * killed, or by max_chunks -- continues with resume != 0 from the first
+ * incomplete chunk; resume == 0 starts over.
+ *   model_id, n_draws, accept_frac, bank_theta, bank_x: as vpet_abc_infer_bank
+ *   chunk_voxels  voxels per chunk, >= 1 (pinned host and device buffers hold
+ *                 two chunks of input and output)
+ *   max_chunks    process at most this many chunks in this call (0 = all)
+ *   out_done      host, optional: completed chunks after the call
+ *   opts          as vpet_abc_infer_bank, except that caller weights, the
+ *                 debug outputs and the timing/fallback reports are refused
+ *                 (VPET_E_ARG); NULL = defaults
+ * The call returns when the processed chunks are on disk (synchronous); it
+ * uses hip_stream for the kernels and one internal stream for the copies in.
+ * Each voxel's outputs are those of vpet_abc_infer_bank on the same data.
+ * Errors: those of vpet_abc_infer_bank; VPET_E_IO for files (missing or short
+ * input, unwritable outputs); VPET_E_ARG for a progress file of another run's
+ * shape when resuming.
+ */
+int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* frame_times, vpet_grid grid,
+                         uint32_t model_id, int64_t n_draws, double accept_frac, const float* bank_theta,
+                         const double* bank_x, int64_t chunk_voxels, const char* out_prefix, int32_t resume,
+                         int64_t max_chunks, const vpet_abc_opts* opts, int64_t* out_done, void* hip_stream);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* vpet_abc_last_error(void);

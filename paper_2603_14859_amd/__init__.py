@@ -6,4 +6,5 @@ same entry points (``simulate``, ``infer``, ``draws``, ``accept_count``).
 """
 from ._binding import (E_ARG, E_GRID, E_HIP, E_LIMIT, E_MODEL, E_NOMEM, EXPORTED, LIB_PATH, M_1TCM,  # noqa: F401
                        M_2TCM_IRR, M_2TCM_REV, M_LPNTPET, M_MRTM, MAX_ACCEPT, OK, PSTRIDE, VpetError, accept_count, draws, infer,
-                       lib, model_mask, simulate, version, bank_build, infer_bank, BANK_MAX_ACCEPT, BANK_MAX_FRAMES)
+                       lib, model_mask, simulate, version, bank_build, infer_bank, BANK_MAX_ACCEPT, BANK_MAX_FRAMES,
+                       stream_bank, load_stream_outputs, E_IO)

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvpetabc.so")
 
-OK, E_ARG, E_MODEL, E_GRID, E_HIP, E_NOMEM, E_LIMIT = range(7)
+OK, E_ARG, E_MODEL, E_GRID, E_HIP, E_NOMEM, E_LIMIT, E_IO = range(8)
 M_1TCM, M_2TCM_IRR, M_2TCM_REV = 1, 2, 4
 M_MRTM, M_LPNTPET = 8, 16  # reference-tissue models (input = reference TAC)
 _ALL_MODELS = (M_1TCM, M_2TCM_IRR, M_2TCM_REV, M_MRTM, M_LPNTPET)
@@ -24,7 +24,7 @@ PSTRIDE = 8
 MAX_ACCEPT = 3968
 
 EXPORTED = ("vpet_abc_accept_count", "vpet_abc_simulate", "vpet_abc_infer", "vpet_abc_draws",
-            "vpet_abc_bank_ld", "vpet_abc_bank_build", "vpet_abc_infer_bank",
+            "vpet_abc_bank_ld", "vpet_abc_bank_build", "vpet_abc_infer_bank", "vpet_abc_stream_bank",
             "vpet_abc_last_error", "vpet_abc_version")
 BANK_MAX_ACCEPT = 512
 BANK_MAX_FRAMES = 48
@@ -63,6 +63,8 @@ def _load():
     L.vpet_abc_bank_ld.restype = ctypes.c_int
     L.vpet_abc_bank_build.argtypes = [u32, P, i64, u64, P, P, Grid, P, P, P]
     L.vpet_abc_infer_bank.argtypes = [P, i64, P, Grid, u32, i64, f64, P, P, P, P, ctypes.POINTER(Opts), P]
+    L.vpet_abc_stream_bank.argtypes = [ctypes.c_char_p, i64, P, Grid, u32, i64, f64, P, P, i64, ctypes.c_char_p,
+                                       ctypes.c_int32, i64, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_int64), P]
     L.vpet_abc_last_error.restype = ctypes.c_char_p
     L.vpet_abc_version.restype = ctypes.c_int
     for name in EXPORTED[:4] + EXPORTED[5:7]:
@@ -276,6 +278,41 @@ def infer_bank(tacs, frame_times, dt: float, n_nodes: int, models, n_draws: int,
     if debug:
         res["fallback_voxels"] = int(n_fallback.value)
     return res
+
+
+def stream_bank(tacs_path: str, n_voxels: int, frame_times, dt: float, n_nodes: int, models, n_draws: int,
+                accept_frac: float, bank_theta, bank_x, out_prefix: str, *, chunk_voxels: int = 1 << 20,
+                resume: bool = True, max_chunks: int = 0, weight_floor=0.0, decay_lambda=0.0, distance="l2",
+                bank_pilot=0, bank_scan="auto", stream=None) -> int:
+    """Shared-bank inference of a volume stored as raw fp32 [n_voxels][F] in
+    tacs_path, streamed in chunks; outputs go to <out_prefix>.moments/.prob
+    (see load_stream_outputs).  Returns the number of completed chunks."""
+    import torch
+    if not (bank_x.dtype == torch.float64 and bank_theta.dtype == torch.float32):
+        raise TypeError("bank_x must be float64 and bank_theta float32 (from bank_build)")
+    ft = _host(frame_times, np.float32)
+    o = Opts()
+    o.decay_lambda = float(decay_lambda)
+    o.weight_floor_frac = float(weight_floor)
+    o.distance = {"l2": 0, "l1": 1}[distance]
+    o.bank_pilot = int(bank_pilot)
+    o.bank_scan = {"auto": 0, "f64": 1, "bf16": 2}[bank_scan]
+    done = ctypes.c_int64(0)
+    _check(lib.vpet_abc_stream_bank(str(tacs_path).encode(), int(n_voxels), ft.ctypes.data_as(ctypes.c_void_p),
+                                    Grid(float(dt), int(n_nodes), ft.size - 1), model_mask(models), int(n_draws),
+                                    float(accept_frac), _ptr(bank_theta), _ptr(bank_x), int(chunk_voxels),
+                                    str(out_prefix).encode(), int(bool(resume)), int(max_chunks), ctypes.byref(o),
+                                    ctypes.byref(done), _stream(stream)))
+    return int(done.value)
+
+
+def load_stream_outputs(out_prefix: str, n_voxels: int, n_models: int):
+    """Read-only memory maps of a streamed run's moments [V][M][8][2] and
+    model probabilities [V][M] (fp32)."""
+    mom = np.memmap(str(out_prefix) + ".moments", dtype=np.float32, mode="r",
+                    shape=(int(n_voxels), int(n_models), PSTRIDE, 2))
+    prob = np.memmap(str(out_prefix) + ".prob", dtype=np.float32, mode="r", shape=(int(n_voxels), int(n_models)))
+    return mom, prob
 
 
 def version() -> int:

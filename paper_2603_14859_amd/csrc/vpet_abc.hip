@@ -40,6 +40,10 @@
 #include <string>
 #include <vector>
 
+#include <fcntl.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include "vpet_abc.h"
 
 #define VPET_VERSION_NUMBER 10000
@@ -2307,7 +2311,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         Q.out_dist = o.out_accept_dist ? o.out_accept_dist + (size_t)base * n_acc : nullptr;
         Q.out_thr = o.out_threshold ? o.out_threshold + base : nullptr;
         const dim3 lanes((unsigned)((Q.V + 255) / 256)), b256(256), per_voxel((unsigned)Q.V), b64(64);
-        const dim3 mblocks((unsigned)((Q.V + kMfmaVox - 1) / kMfmaVox)), b512(512);
+        const dim3 mblocks((unsigned)((Q.V + kMfmaVox - 1) / kMfmaVox));
         const dim3 fb_grid((unsigned)std::min<long long>(Q.V, 2048)), fb_block(64 * fb_waves), one(1);
 #define VPET_BANK_LAUNCH(LDV, L1V)                                                                        \
     do {                                                                                                  \
@@ -2368,6 +2372,217 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     e = hipEventRecord(ctx->ev[slot], st);
     if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipEventRecord");
     return rc;
+}
+
+
+// ===========================================================================
+// Streaming driver: a volume in a file, two chunks in flight.
+// ===========================================================================
+}  // extern "C"
+
+namespace {
+
+bool pread_all(int fd, void* buf, size_t bytes, off_t off) {
+    char* p = static_cast<char*>(buf);
+    while (bytes > 0) {
+        const ssize_t r = ::pread(fd, p, bytes, off);
+        if (r <= 0) return false;
+        p += r;
+        bytes -= (size_t)r;
+        off += r;
+    }
+    return true;
+}
+
+bool pwrite_all(int fd, const void* buf, size_t bytes, off_t off) {
+    const char* p = static_cast<const char*>(buf);
+    while (bytes > 0) {
+        const ssize_t r = ::pwrite(fd, p, bytes, off);
+        if (r <= 0) return false;
+        p += r;
+        bytes -= (size_t)r;
+        off += r;
+    }
+    return true;
+}
+
+// The progress line names the run's shape so that a resume cannot continue
+// a different run.
+std::string progress_line(int64_t V, int F, int M, int64_t chunk, int64_t done) {
+    char buf[192];
+    snprintf(buf, sizeof buf, "vpet_abc_stream v1 voxels=%lld frames=%d models=%d chunk=%lld done=%lld\n",
+             (long long)V, F, M, (long long)chunk, (long long)done);
+    return buf;
+}
+
+int write_progress(const std::string& path, const std::string& line) {
+    const std::string tmp = path + ".tmp";
+    const int fd = ::open(tmp.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0644);
+    if (fd < 0) return fail(VPET_E_IO, "cannot write %s", tmp.c_str());
+    const bool ok = pwrite_all(fd, line.data(), line.size(), 0) && ::fsync(fd) == 0;
+    ::close(fd);
+    if (!ok || ::rename(tmp.c_str(), path.c_str()) != 0) return fail(VPET_E_IO, "cannot update %s", path.c_str());
+    return VPET_OK;
+}
+
+// Host and device buffers of the pipeline; released by the destructor.
+struct StreamBuffers {
+    float* h_in[2] = {nullptr, nullptr};
+    float* h_mom[2] = {nullptr, nullptr};
+    float* h_prob[2] = {nullptr, nullptr};
+    float* d_in[2] = {nullptr, nullptr};
+    float* d_mom[2] = {nullptr, nullptr};
+    float* d_prob[2] = {nullptr, nullptr};
+    hipEvent_t ev_in[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
+    hipStream_t copy = nullptr;
+    int fds[3] = {-1, -1, -1};
+    ~StreamBuffers() {
+        if (copy) (void)hipStreamSynchronize(copy);
+        for (int b = 0; b < 2; ++b) {
+            if (ev_done[b]) (void)hipEventSynchronize(ev_done[b]);
+            if (h_in[b]) (void)hipHostFree(h_in[b]);
+            if (h_mom[b]) (void)hipHostFree(h_mom[b]);
+            if (h_prob[b]) (void)hipHostFree(h_prob[b]);
+            if (d_in[b]) (void)hipFree(d_in[b]);
+            if (d_mom[b]) (void)hipFree(d_mom[b]);
+            if (d_prob[b]) (void)hipFree(d_prob[b]);
+            if (ev_in[b]) (void)hipEventDestroy(ev_in[b]);
+            if (ev_done[b]) (void)hipEventDestroy(ev_done[b]);
+        }
+        if (copy) (void)hipStreamDestroy(copy);
+        for (int fd : fds)
+            if (fd >= 0) ::close(fd);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* frame_times, vpet_grid grid,
+                         uint32_t model_id, int64_t n_draws, double accept_frac, const float* bank_theta,
+                         const double* bank_x, int64_t chunk_voxels, const char* out_prefix, int32_t resume,
+                         int64_t max_chunks, const vpet_abc_opts* opts, int64_t* out_done, void* hip_stream) {
+    if (out_done) *out_done = 0;
+    vpet_abc_opts o{};
+    if (opts) o = *opts;
+    if (o.weights || o.out_accept_idx || o.out_accept_dist || o.out_threshold || o.out_scan_ms ||
+        o.out_fallback_voxels)
+        return fail(VPET_E_ARG, "streaming takes no caller weights, debug outputs or reports");
+    // everything vpet_abc_infer_bank checks, without work (0 voxels)
+    int rc = vpet_abc_infer_bank(nullptr, 0, frame_times, grid, model_id, n_draws, accept_frac, bank_theta, bank_x,
+                                 nullptr, nullptr, &o, hip_stream);
+    if (rc != VPET_OK) return rc;
+    if (!tacs_path || !out_prefix) return fail(VPET_E_ARG, "tacs_path and out_prefix must not be NULL");
+    if (n_voxels < 0 || chunk_voxels < 1 || max_chunks < 0)
+        return fail(VPET_E_ARG, "need n_voxels >= 0, chunk_voxels >= 1, max_chunks >= 0");
+    if (!bank_theta || !bank_x) return fail(VPET_E_ARG, "bank pointers must not be NULL");
+    const int F = grid.n_frames;
+    const int M = __builtin_popcount(model_id);
+    const int64_t chunk = std::min<int64_t>(chunk_voxels, std::max<int64_t>(n_voxels, 1));
+    const int64_t nchunks = (n_voxels + chunk - 1) / chunk;
+    const size_t in_row = sizeof(float) * (size_t)F, mom_row = sizeof(float) * (size_t)M * VPET_PSTRIDE * 2,
+                 prob_row = sizeof(float) * (size_t)M;
+
+    StreamBuffers B;
+    B.fds[0] = ::open(tacs_path, O_RDONLY);
+    if (B.fds[0] < 0) return fail(VPET_E_IO, "cannot open %s", tacs_path);
+    struct stat st_in;
+    if (::fstat(B.fds[0], &st_in) != 0 || (uint64_t)st_in.st_size < (uint64_t)n_voxels * in_row)
+        return fail(VPET_E_IO, "%s holds fewer than %lld x %d fp32 values", tacs_path, (long long)n_voxels, F);
+    const std::string pre(out_prefix), mom_path = pre + ".moments", prob_path = pre + ".prob",
+                                         prog_path = pre + ".progress";
+    int64_t done = 0;
+    if (resume) {
+        const int fd = ::open(prog_path.c_str(), O_RDONLY);
+        if (fd >= 0) {
+            char buf[256] = {0};
+            const ssize_t r = ::pread(fd, buf, sizeof buf - 1, 0);
+            ::close(fd);
+            long long v = -1, c = -1, d = -1;
+            int f = -1, m = -1;
+            if (r <= 0 || sscanf(buf, "vpet_abc_stream v1 voxels=%lld frames=%d models=%d chunk=%lld done=%lld", &v, &f,
+                                 &m, &c, &d) != 5)
+                return fail(VPET_E_IO, "unreadable progress file %s", prog_path.c_str());
+            if (v != n_voxels || f != F || m != M || c != chunk || d < 0 || d > nchunks)
+                return fail(VPET_E_ARG, "progress file %s belongs to a run of another shape", prog_path.c_str());
+            done = d;
+        }
+    }
+    const int oflags = O_RDWR | O_CREAT | (resume ? 0 : O_TRUNC);
+    B.fds[1] = ::open(mom_path.c_str(), oflags, 0644);
+    B.fds[2] = ::open(prob_path.c_str(), oflags, 0644);
+    if (B.fds[1] < 0 || B.fds[2] < 0) return fail(VPET_E_IO, "cannot open %s.*", out_prefix);
+    if (::ftruncate(B.fds[1], (off_t)(mom_row * (size_t)n_voxels)) != 0 ||
+        ::ftruncate(B.fds[2], (off_t)(prob_row * (size_t)n_voxels)) != 0)
+        return fail(VPET_E_IO, "cannot size the output files %s.*", out_prefix);
+    if (!resume || done == 0)
+        if ((rc = write_progress(prog_path, progress_line(n_voxels, F, M, chunk, 0))) != VPET_OK) return rc;
+    const int64_t last = max_chunks > 0 ? std::min<int64_t>(nchunks, done + max_chunks) : nchunks;
+    if (done >= last) {
+        if (out_done) *out_done = done;
+        return VPET_OK;
+    }
+
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = hipStreamCreateWithFlags(&B.copy, hipStreamNonBlocking);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = hipHostMalloc((void**)&B.h_in[b], in_row * chunk, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&B.h_mom[b], mom_row * chunk, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&B.h_prob[b], prob_row * chunk, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc((void**)&B.d_in[b], in_row * chunk);
+        if (e == hipSuccess) e = hipMalloc((void**)&B.d_mom[b], mom_row * chunk);
+        if (e == hipSuccess) e = hipMalloc((void**)&B.d_prob[b], prob_row * chunk);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B.ev_in[b], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B.ev_done[b], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "stream buffers: %s", hipGetErrorString(e));
+
+    auto rows = [&](int64_t c) { return std::min<int64_t>(chunk, n_voxels - c * chunk); };
+    // read chunk c into host buffer b and queue its copy to the device
+    auto load = [&](int64_t c, int b) -> int {
+        hipError_t he = hipEventSynchronize(B.ev_in[b]);  // the previous copy out of h_in[b]
+        if (he != hipSuccess) return hip_fail(he, "hipEventSynchronize");
+        if (!pread_all(B.fds[0], B.h_in[b], in_row * (size_t)rows(c), (off_t)(in_row * (size_t)(c * chunk))))
+            return fail(VPET_E_IO, "read of %s failed at chunk %lld", tacs_path, (long long)c);
+        he = hipStreamWaitEvent(B.copy, B.ev_done[b], 0);  // d_in[b] free: its last chunk was screened
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(B.d_in[b], B.h_in[b], in_row * (size_t)rows(c), hipMemcpyHostToDevice, B.copy);
+        if (he == hipSuccess) he = hipEventRecord(B.ev_in[b], B.copy);
+        return he == hipSuccess ? VPET_OK : hip_fail(he, "chunk copy in");
+    };
+    // wait for chunk c's outputs and write them at their offsets
+    auto store = [&](int64_t c, int b) -> int {
+        hipError_t he = hipEventSynchronize(B.ev_done[b]);
+        if (he != hipSuccess) return hip_fail(he, "chunk outputs");
+        const size_t n = (size_t)rows(c), v0 = (size_t)(c * chunk);
+        if (!pwrite_all(B.fds[1], B.h_mom[b], mom_row * n, (off_t)(mom_row * v0)) ||
+            !pwrite_all(B.fds[2], B.h_prob[b], prob_row * n, (off_t)(prob_row * v0)) || ::fsync(B.fds[1]) != 0 ||
+            ::fsync(B.fds[2]) != 0)
+            return fail(VPET_E_IO, "write of %s.* failed at chunk %lld", out_prefix, (long long)c);
+        return write_progress(prog_path, progress_line(n_voxels, F, M, chunk, c + 1));
+    };
+
+    if ((rc = load(done, 0)) != VPET_OK) return rc;
+    for (int64_t c = done; c < last; ++c) {
+        const int b = (int)((c - done) & 1);
+        e = hipStreamWaitEvent(st, B.ev_in[b], 0);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+        rc = vpet_abc_infer_bank(B.d_in[b], rows(c), frame_times, grid, model_id, n_draws, accept_frac, bank_theta,
+                                 bank_x, B.d_mom[b], B.d_prob[b], &o, hip_stream);
+        if (rc != VPET_OK) return rc;
+        e = hipMemcpyAsync(B.h_mom[b], B.d_mom[b], mom_row * (size_t)rows(c), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(B.h_prob[b], B.d_prob[b], prob_row * (size_t)rows(c), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(B.ev_done[b], st);
+        if (e != hipSuccess) return hip_fail(e, "chunk copy out");
+        if (c + 1 < last && (rc = load(c + 1, b ^ 1)) != VPET_OK) return rc;   // overlaps chunk c
+        if (c > done && (rc = store(c - 1, b ^ 1)) != VPET_OK) return rc;      // overlaps chunk c
+        if (out_done) *out_done = c;
+    }
+    if ((rc = store(last - 1, (int)((last - 1 - done) & 1))) != VPET_OK) return rc;
+    if (out_done) *out_done = last;
+    return VPET_OK;
 }
 
 }  // extern "C"

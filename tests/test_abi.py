@@ -162,3 +162,28 @@ def test_bank_validation_without_gpu(V):
     assert V.lib.vpet_abc_infer(None, 0, P(ft), P(cp), g, 8, P(W.box_array([8])), 10, 0.5, 1, None, None, None,
                                 None) == V.E_MODEL                # the per-voxel path does not run them
     assert ib(V_=3) == V.E_ARG                            # NULL device pointers
+
+
+def test_stream_validation_without_gpu(V, tmp_path):
+    ft = W.frame_times(W.SCHED_22x60)
+    cp = W.grid(0.2, 60.0)[1]
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    g = V._binding.Grid(0.2, cp.size, ft.size - 1)
+    fake = ctypes.c_void_p(256)  # bank pointers are only checked for NULL before the files
+    path = tmp_path / "tacs.f32"
+    np.ones((10, 22), dtype=np.float32).tofile(path)
+    prefix = str(tmp_path / "out").encode()
+
+    def sb(p=str(path).encode(), nv=10, resume=0, opts=None, chunk=4):
+        return V.lib.vpet_abc_stream_bank(p, nv, P(ft), g, 2, 1000, 0.01, fake, fake, chunk, prefix, resume, 0,
+                                          ctypes.byref(opts) if opts is not None else None, None, None)
+    assert sb(p=str(tmp_path / "missing.f32").encode()) == V.E_IO
+    assert sb(nv=11) == V.E_IO                            # file shorter than 11 x 22 values
+    assert sb(chunk=0) == V.E_ARG
+    o = V._binding.Opts()
+    o.weights = 1234
+    assert sb(opts=o) == V.E_ARG                          # no caller weights in streaming
+    (tmp_path / "out.progress").write_text("vpet_abc_stream v1 voxels=99 frames=22 models=1 chunk=4 done=1\n")
+    assert sb(resume=1) == V.E_ARG                        # progress of a run of another shape
+    assert V.lib.vpet_abc_stream_bank(str(path).encode(), 10, P(ft), g, 0, 1000, 0.01, fake, fake, 4, prefix, 0, 0,
+                                      None, None, None) == V.E_MODEL

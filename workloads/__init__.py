@@ -189,6 +189,18 @@ class Workload:
         eps = rng.standard_normal((n, len(self.durations)))
         return th, eps
 
+    def truth_mixture(self, n: int | None = None):
+        """Irreversible / reversible mixture (total-body configuration): 2TCM
+        parameters [V][8] from the reversible box, with k4 = 0 for the
+        irreversible half; the reversible mask and noise draws [V][F]."""
+        n = self.n_voxels if n is None else n
+        rng = np.random.default_rng(self.data_seed)
+        th = true_params(rng, n, M_2TCM_REV, box_array([M_2TCM_REV])[0])
+        rev = rng.uniform(size=n) < 0.5
+        th[~rev, 3] = 0.0
+        eps = rng.standard_normal((n, len(self.durations)))
+        return th, rev, eps
+
     def truth_reference(self, n: int | None = None):
         """Reference-tissue configurations: lp-ntPET parameters [V][8] (gamma = 0
         and no activation timing for the null half), the activated mask and
@@ -217,6 +229,14 @@ CFG_LARGE = Workload("irr2tcm_1Mvox_30fr_100kdraws", 1 << 20, SCHED_30x50, n_dra
 CFG_LPNT = Workload("mrtm_lpnt_1.56Mvox_40fr_200kdraws", 128 * 128 * 95, SCHED_40x90,
                     models=(M_MRTM, M_LPNTPET), n_draws=200_000, accept_frac=0.001,
                     decay_lambda=LAMBDA_C11, reference=True)
+# Total-body scale: 150 x 150 x 486 voxels, 30 frames over 50 min, half
+# irreversible and half reversible 2TCM voxels, one shared bank of 1M draws
+# (500k per model), n = 100 accepted, streamed through the GPU in 1M-voxel chunks.
+CFG_TBPET = Workload("irrrev_tbpet_10.9Mvox_30fr_1Mbank", 150 * 150 * 486, SCHED_30x50,
+                     models=(M_2TCM_IRR, M_2TCM_REV), n_draws=500_000, accept_frac=1e-4)
+# Its small streaming case: 3000 voxels, 5000 draws per model, 1 % accepted.
+CFG_TBPET_SMALL = Workload("irrrev_3000vox_30fr_10kbank", 3000, SCHED_30x50, models=(M_2TCM_IRR, M_2TCM_REV),
+                           n_draws=5000, accept_frac=0.01)
 # Its small parity case: 256 voxels, 5000 draws per model, 0.4 % accepted.
 CFG_LPNT_SMALL = Workload("mrtm_lpnt_256vox_40fr_5kdraws", 256, SCHED_40x90, models=(M_MRTM, M_LPNTPET),
                           n_draws=5000, accept_frac=0.004, decay_lambda=LAMBDA_C11, reference=True)
