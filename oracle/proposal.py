@@ -1,0 +1,208 @@
+"""FP64 oracle of the learned proposal and importance-weighted ABC.
+
+TEST INFRASTRUCTURE ONLY (like the rest of ``oracle/``): plain numpy, FP64,
+written from the definitions below; it shares no code with the GPU library.
+
+This part is not in the paper.  It is an amortised importance sampler for the
+prior draws of Alg. 1 (lines 1-2): a multilayer perceptron maps a voxel's
+observed TAC to a mixture of Gaussians over the log of the free parameters,
+draws come from that mixture instead of the prior, and each accepted draw is
+weighted by prior / proposal (the usual importance weight, so the ABC target
+is unchanged).  Definitions:
+
+* features: x_f = log1p(max(y_f, 0)), zero-padded to NF = 32 inputs;
+* network: h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), o = h2 W3 + b3, widths
+  32 -> 256 -> 256 -> 72 (8 mixture logits, 8 x 4 means, 8 x 4 raw scales);
+* mixture over z = log(theta) of the D = 4 free parameters (K1, k2, k3, vB of
+  the irreversible 2TCM): weights softmax(logits); log sd = LS0 + (LS1 - LS0)
+  sigmoid(raw) (a smooth clamp to [LS0, LS1]);
+* training loss: mean negative log density of z = log(theta) of the training
+  draws (clamped at 1e-6 before the log), minimised with Adam;
+* draws (voxel v, draw i): Philox4x32-10 counter (i, v, 2, blk), key = seed,
+  words w0..w7; component c = first c with cumsum(pi)_c > u0, u0 = (w0>>8) 2^-24;
+  two Box-Muller pairs n_{2p}, n_{2p+1} = r cos / sin(2 pi u_b), r =
+  sqrt(-2 ln u_a), u_a = ((w_{1+2p}>>8) + 1) 2^-24, u_b = (w_{2+2p}>>8) 2^-24;
+  z_j = mu_cj + sd_cj n_j; theta_j = fp32(exp(z_j)); a draw outside the prior
+  box has weight 0;
+* weight: log w = sum_j z_j - log q(z) (prior uniform on the box; the
+  Jacobian of theta = exp(z) gives sum_j z_j), normalised over the accepted
+  draws with a max shift in FP64;
+* summaries: weighted mean sum w t / sum w, weighted variance
+  sum w (t - mean)^2 / sum w, effective sample size (sum w)^2 / sum w^2.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+NF, H, NOUT, C, D = 32, 256, 72, 8, 4
+LS0, LS1 = -6.0, 2.0
+FREE_SLOTS = (0, 1, 2, 4)  # K1, k2, k3, vB of the irreversible 2TCM
+
+
+def init_params(rng: np.random.Generator) -> dict:
+    """He-normal weights, zero biases (FP64)."""
+    return {"W1": rng.standard_normal((NF, H)) * math.sqrt(2.0 / NF), "b1": np.zeros(H),
+            "W2": rng.standard_normal((H, H)) * math.sqrt(2.0 / H), "b2": np.zeros(H),
+            "W3": rng.standard_normal((H, NOUT)) * math.sqrt(1.0 / H), "b3": np.zeros(NOUT)}
+
+
+def features(y: np.ndarray) -> np.ndarray:
+    y = np.asarray(y, dtype=np.float64)
+    x = np.zeros((y.shape[0], NF))
+    x[:, :y.shape[1]] = np.log1p(np.maximum(y, 0.0))
+    return x
+
+
+def forward(p: dict, x: np.ndarray):
+    a1 = x @ p["W1"] + p["b1"]
+    h1 = np.maximum(a1, 0.0)
+    a2 = h1 @ p["W2"] + p["b2"]
+    h2 = np.maximum(a2, 0.0)
+    o = h2 @ p["W3"] + p["b3"]
+    return o, (x, a1, h1, a2, h2)
+
+
+def mixture(o: np.ndarray):
+    """(log pi [B][C], mu [B][C][D], log sd [B][C][D]) of network outputs."""
+    logits = o[:, :C]
+    m = logits.max(axis=1, keepdims=True)
+    logpi = logits - m - np.log(np.exp(logits - m).sum(axis=1, keepdims=True))
+    mu = o[:, C:C + C * D].reshape(-1, C, D)
+    raw = o[:, C + C * D:C + 2 * C * D].reshape(-1, C, D)
+    logsd = LS0 + (LS1 - LS0) / (1.0 + np.exp(-raw))
+    return logpi, mu, logsd
+
+
+def log_density(o: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """log q(z) per row (the mixture density of z)."""
+    logpi, mu, logsd = mixture(o)
+    t = (z[:, None, :] - mu) * np.exp(-logsd)
+    comp = logpi + (-0.5 * t * t - logsd - 0.5 * math.log(2.0 * math.pi)).sum(axis=2)
+    mx = comp.max(axis=1, keepdims=True)
+    return (mx + np.log(np.exp(comp - mx).sum(axis=1, keepdims=True)))[:, 0]
+
+
+def targets(theta: np.ndarray) -> np.ndarray:
+    """z = log(theta) of the free parameters (theta clamped at 1e-6)."""
+    t = np.asarray(theta, dtype=np.float64)[:, FREE_SLOTS]
+    return np.log(np.maximum(t, 1e-6))
+
+
+def loss_and_grad(p: dict, x: np.ndarray, z: np.ndarray):
+    """Mean negative log density and its gradient with respect to every parameter."""
+    B = x.shape[0]
+    o, (x, a1, h1, a2, h2) = forward(p, x)
+    logpi, mu, logsd = mixture(o)
+    sd_inv = np.exp(-logsd)
+    t = (z[:, None, :] - mu) * sd_inv
+    comp = logpi + (-0.5 * t * t - logsd - 0.5 * math.log(2.0 * math.pi)).sum(axis=2)
+    mx = comp.max(axis=1, keepdims=True)
+    lse = mx + np.log(np.exp(comp - mx).sum(axis=1, keepdims=True))
+    loss = -lse.mean()
+    r = np.exp(comp - lse)                     # responsibilities [B][C]
+    do = np.zeros_like(o)
+    do[:, :C] = (np.exp(logpi) - r) / B        # d(-log q)/d logits
+    do[:, C:C + C * D] = (-(r[:, :, None] * t * sd_inv) / B).reshape(B, -1)
+    s = (logsd - LS0) / (LS1 - LS0)            # sigmoid(raw)
+    dlogsd = r[:, :, None] * (1.0 - t * t) / B
+    do[:, C + C * D:] = (dlogsd * (LS1 - LS0) * s * (1.0 - s)).reshape(B, -1)
+    g = {"W3": h2.T @ do, "b3": do.sum(axis=0)}
+    dh2 = (do @ p["W3"].T) * (a2 > 0.0)
+    g["W2"], g["b2"] = h1.T @ dh2, dh2.sum(axis=0)
+    dh1 = (dh2 @ p["W2"].T) * (a1 > 0.0)
+    g["W1"], g["b1"] = x.T @ dh1, dh1.sum(axis=0)
+    return loss, g
+
+
+def adam(p: dict, g: dict, state: dict, lr: float, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma and Ba) in place; state holds m, v and t."""
+    state["t"] = state.get("t", 0) + 1
+    t = state["t"]
+    for k in p:
+        m = state.setdefault("m_" + k, np.zeros_like(p[k]))
+        v = state.setdefault("v_" + k, np.zeros_like(p[k]))
+        m[...] = b1 * m + (1.0 - b1) * g[k]
+        v[...] = b2 * v + (1.0 - b2) * g[k] * g[k]
+        mh = m / (1.0 - b1 ** t)
+        vh = v / (1.0 - b2 ** t)
+        p[k] -= lr * mh / (np.sqrt(vh) + eps)
+
+
+def draws(o_v: np.ndarray, words: np.ndarray):
+    """Proposal draws of one voxel: z [n][D] (FP64), theta [n][D] (fp32) from the
+    voxel's network output o_v [72] and Philox words [n][8]."""
+    logpi, mu, logsd = mixture(o_v[None, :])
+    cum = np.cumsum(np.exp(logpi[0]))
+    u0 = (words[:, 0] >> 8).astype(np.float64) * 2.0 ** -24
+    c = np.minimum(np.searchsorted(cum, u0, side="right"), C - 1)
+    nrm = np.empty((words.shape[0], D))
+    for q in range(2):
+        ua = ((words[:, 1 + 2 * q] >> 8).astype(np.float64) + 1.0) * 2.0 ** -24
+        ub = (words[:, 2 + 2 * q] >> 8).astype(np.float64) * 2.0 ** -24
+        r = np.sqrt(-2.0 * np.log(ua))
+        nrm[:, 2 * q] = r * np.cos(2.0 * math.pi * ub)
+        nrm[:, 2 * q + 1] = r * np.sin(2.0 * math.pi * ub)
+    z = mu[0][c] + np.exp(logsd[0][c]) * nrm
+    return z, np.exp(z).astype(np.float32)
+
+
+def log_weight(o_v: np.ndarray, z: np.ndarray) -> np.ndarray:
+    return z.sum(axis=1) - log_density(np.repeat(o_v[None, :], z.shape[0], axis=0), z)
+
+
+def weighted_summary(theta: np.ndarray, logw: np.ndarray):
+    """Weighted mean, variance (both per column) and ESS, FP64 with a max shift."""
+    w = np.exp(logw - logw.max())
+    sw = w.sum()
+    mean = (w[:, None] * theta).sum(axis=0) / sw
+    var = (w[:, None] * (theta - mean) ** 2).sum(axis=0) / sw
+    return mean, var, sw * sw / (w * w).sum()
+
+
+def philox_words(v: int, n: int, seed: int) -> np.ndarray:
+    """Words [n][8] of the proposal draws i = 0..n-1 of voxel v (stream 2)."""
+    import oracle as ora
+    i = np.arange(n, dtype=np.uint32)
+    out = np.empty((n, 8), dtype=np.uint32)
+    for blk in range(2):
+        ctr = np.stack([i, np.full(n, v, np.uint32), np.full(n, 2, np.uint32), np.full(n, blk, np.uint32)], axis=1)
+        out[:, 4 * blk:4 * blk + 4] = ora.philox(ctr, seed)
+    return out
+
+
+def infer_is(y_v, frame_times, input_fn, dt, box, o_v, n_draws, accept_frac, seed, v_global, lam=None):
+    """Importance-weighted fixed-budget ABC of one voxel (irreversible 2TCM):
+    n_draws proposal draws, the n closest valid ones accepted (ties to the lower
+    draw index), weighted summaries.  Returns (accepted indices, moments [8][2]
+    with Ki in slot 5 and NaN in unused slots, ESS, distances of every draw)."""
+    import oracle as ora
+    lam = ora.DEFAULT_LAMBDA if lam is None else lam
+    words = philox_words(v_global, n_draws, seed)
+    z, th4 = draws(np.asarray(o_v, dtype=np.float64), words)
+    lo = np.array([np.float32(box[s][0]) for s in FREE_SLOTS])
+    hi = np.array([np.float32(box[s][1]) for s in FREE_SLOTS])
+    valid = np.all((th4 >= lo) & (th4 <= hi), axis=1)
+    theta = np.full((n_draws, 8), np.nan, dtype=np.float32)
+    theta[:, FREE_SLOTS] = th4
+    cp = np.asarray(input_fn, dtype=np.float32)
+    y = np.asarray(y_v, dtype=np.float32)
+    w = ora.weights(y, frame_times, dt, cp.size, lam=lam)
+    d = np.full(n_draws, np.inf)
+    if valid.any():
+        x = ora.simulate(ora.M_2TCM_IRR, theta[valid], cp, dt, frame_times)
+        d[valid] = (w * (y.astype(np.float64) - x) ** 2).sum(axis=1)
+    n = ora.accept_count(n_draws, accept_frac)
+    order = np.lexsort((np.arange(n_draws), d))[:n]
+    keep = order[np.isfinite(d[order])]
+    t = theta[keep].astype(np.float64)
+    t[:, 5] = t[:, 0] * t[:, 2] / (t[:, 1] + t[:, 2])
+    mom = np.full((8, 2), np.nan)
+    ess = np.nan
+    if keep.size:
+        cols = [0, 1, 2, 4, 5]
+        mean, var, ess = weighted_summary(t[:, cols], log_weight(np.asarray(o_v, dtype=np.float64), z[keep]))
+        mom[cols, 0] = mean
+        mom[cols, 1] = var
+    return order, mom, ess, d
