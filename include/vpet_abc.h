@@ -103,6 +103,11 @@ typedef enum {
 #define VPET_MAX_FRAMES 1024
 #define VPET_BANK_MAX_FRAMES 48
 #define VPET_BANK_MAX_ACCEPT 512
+/* FP32 parameter blob of the learned proposal network (see
+ * vpet_proposal_init): W1 [32][256], b1 [256], W2 [256][256], b2 [256],
+ * W3 [256][96], b3 [96] (outputs 72..95 unused). */
+#define VPET_PROPOSAL_NPARAM 98912
+#define VPET_PROPOSAL_NOUT 96
 
 typedef struct {
     float dt;         /* grid step (min), > 0                         */
@@ -159,6 +164,24 @@ typedef struct {
      * that were redone by the exact pass over the whole bank.  Makes the call
      * synchronous. */
     int64_t* out_fallback_voxels;
+    /* vpet_abc_infer only: device [n_voxels][VPET_PROPOSAL_NOUT] outputs of the
+     * learned proposal network (vpet_proposal_forward) for each voxel.  When
+     * set, the n_draws draws of each voxel come from its mixture (Philox
+     * stream 2) instead of the prior, draws outside the prior box are
+     * discarded, and the moments are weighted by prior / proposal
+     * (importance-weighted ABC: the target is unchanged).  The irreversible
+     * 2TCM alone (VPET_E_MODEL otherwise); model probability 1. */
+    const float* proposal;
+    /* device [n_voxels]: effective sample size (sum w)^2 / sum w^2 of each
+     * voxel's accepted weights; needs proposal. */
+    float* out_ess;
+    /* With proposal: defensive prior share a in [0, 1].  The draws come from
+     * a p + (1 - a) q (prior p, network mixture q): u0 < a draws uniformly
+     * from the prior box, and every weight is p / (a p + (1 - a) q) <= 1 / a.
+     * 0 = the network mixture alone. */
+    double proposal_prior_share;
+    /* With proposal: factor (> 0) on every component's sd; 0 -> 1. */
+    double proposal_sd_scale;
 } vpet_abc_opts;
 
 /*
@@ -313,6 +336,62 @@ int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* f
                          uint32_t model_id, int64_t n_draws, double accept_frac, const float* bank_theta,
                          const double* bank_x, int64_t chunk_voxels, const char* out_prefix, int32_t resume,
                          int64_t max_chunks, const vpet_abc_opts* opts, int64_t* out_done, void* hip_stream);
+
+/*
+ * Learned proposal for importance-weighted ABC (not in the paper: an
+ * amortised proposal for the prior draws of Alg. 1, lines 1-2; the ABC
+ * target is unchanged because accepted draws carry the weight prior /
+ * proposal).  The network maps features x_f = log1p(max(y_f, 0)) of a TAC
+ * (zero-padded to 32 inputs; F <= 32, VPET_E_LIMIT otherwise) through
+ * relu(x W1 + b1), relu(h1 W2 + b2), h2 W3 + b3 to 72 outputs: 8 mixture
+ * logits, 8 x 4 means and 8 x 4 raw scales of a Gaussian mixture over
+ * z = log(K1, k2, k3, vB) of the irreversible 2TCM, with log sd = -6 +
+ * 8 sigmoid(raw).  The products run on BF16 matrix cores: each fp32 operand
+ * is split into bf16 hi + lo and three products are accumulated in FP32
+ * (about 3 * 2^-16 relative error per term; FP32 master weights); params is
+ * the VPET_PROPOSAL_NPARAM-float blob laid out as documented at that
+ * constant.  All pointers are device pointers
+ * unless stated; every call is asynchronous on hip_stream unless stated.
+ */
+
+/* He-normal weights (sd sqrt(2 / fan_in), the output layer sqrt(1 / fan_in))
+ * and zero biases into params, normals from Philox stream 5 keyed by seed.
+ * Errors: VPET_E_ARG (NULL params), VPET_E_HIP. */
+int vpet_proposal_init(float* params, uint64_t seed, void* hip_stream);
+
+/* out [n][VPET_PROPOSAL_NOUT] = network outputs of the TACs tacs [n][n_frames]
+ * (fp32 row-major); columns 72..95 are padding.  Scratch for at most 2^17
+ * rows at a time is allocated and freed in stream order.
+ * Errors: VPET_E_ARG, VPET_E_LIMIT (n_frames outside 1..32), VPET_E_NOMEM,
+ * VPET_E_HIP. */
+int vpet_proposal_forward(const float* params, const float* tacs, int64_t n, int32_t n_frames, float* out,
+                          void* hip_stream);
+
+/* Training loss and its gradient for one batch: loss[0] = mean over the n
+ * rows of -log q(z | tacs), z = log(max(theta, 1e-6)) of slots K1, k2, k3, vB
+ * of theta [n][VPET_PSTRIDE] (fp32, the bank layout); grad
+ * [VPET_PROPOSAL_NPARAM] is overwritten with d loss / d params.  1 <= n <=
+ * 2^20.  Errors: VPET_E_ARG, VPET_E_LIMIT, VPET_E_NOMEM, VPET_E_HIP. */
+int vpet_proposal_loss_grad(const float* params, const float* tacs, const float* theta, int64_t n,
+                            int32_t n_frames, float* grad, float* loss, void* hip_stream);
+
+/* `steps` Adam steps (beta 0.9, 0.999, eps 1e-8; the step size follows a
+ * cosine decay from learning_rate at the first step towards 0) on params,
+ * trained on the shared bank of vpet_abc_bank_build (bank_theta, bank_x with
+ * n_bank rows of one irreversible 2TCM bank): step t takes `batch`
+ * consecutive rows of a seeded affine permutation of the bank (a new one per
+ * pass) and adds fresh Gaussian noise of variance
+ * noise_level e^{decay_lambda tmid_f} max(x_f, 0) / dt_f to each frame
+ * (Sec. III-A1 noise; Philox stream 4 keyed by seed); frame_times is host
+ * [n_frames + 1].  out_loss (host, optional, [steps]) receives each step's
+ * batch loss, which makes the call synchronous.  Scratch (Adam moments and
+ * one batch of activations) is allocated and freed in stream order.
+ * Errors: VPET_E_ARG, VPET_E_GRID (frame bounds), VPET_E_LIMIT, VPET_E_NOMEM,
+ * VPET_E_HIP. */
+int vpet_proposal_train(float* params, const float* bank_theta, const double* bank_x, int64_t n_bank,
+                        const float* frame_times, int32_t n_frames, double noise_level, double decay_lambda,
+                        int64_t steps, int32_t batch, float learning_rate, uint64_t seed, float* out_loss,
+                        void* hip_stream);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* vpet_abc_last_error(void);

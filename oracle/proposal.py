@@ -18,15 +18,22 @@ is unchanged).  Definitions:
   sigmoid(raw) (a smooth clamp to [LS0, LS1]);
 * training loss: mean negative log density of z = log(theta) of the training
   draws (clamped at 1e-6 before the log), minimised with Adam;
+* inference-time options: an sd scale s (every component's log sd + log s,
+  a wider proposal) and a defensive prior share a in [0, 1]: the proposal is
+  a p(theta) + (1 - a) q(theta), a mixture with the prior (Hesterberg's
+  defensive importance sampling), which bounds every weight by 1 / a;
 * draws (voxel v, draw i): Philox4x32-10 counter (i, v, 2, blk), key = seed,
-  words w0..w7; component c = first c with cumsum(pi)_c > u0, u0 = (w0>>8) 2^-24;
-  two Box-Muller pairs n_{2p}, n_{2p+1} = r cos / sin(2 pi u_b), r =
-  sqrt(-2 ln u_a), u_a = ((w_{1+2p}>>8) + 1) 2^-24, u_b = (w_{2+2p}>>8) 2^-24;
-  z_j = mu_cj + sd_cj n_j; theta_j = fp32(exp(z_j)); a draw outside the prior
-  box has weight 0;
-* weight: log w = sum_j z_j - log q(z) (prior uniform on the box; the
-  Jacobian of theta = exp(z) gives sum_j z_j), normalised over the accepted
-  draws with a max shift in FP64;
+  words w0..w7, u0 = (w0>>8) 2^-24.  If u0 < a the draw is from the prior:
+  theta_j = fp32(lo_j + u_j (hi_j - lo_j)) with u_j = (w_{1+j}>>8) 2^-24 and
+  z_j = log theta_j.  Otherwise the component is the first c with
+  a + (1 - a) cumsum(pi)_c > u0; two Box-Muller pairs n_{2p}, n_{2p+1} =
+  r cos / sin(2 pi u_b), r = sqrt(-2 ln u_a), u_a = ((w_{1+2p}>>8) + 1) 2^-24,
+  u_b = (w_{2+2p}>>8) 2^-24; z_j = mu_cj + sd_cj n_j; theta_j = fp32(exp(z_j));
+  a draw outside the prior box (fp32 bounds) has weight 0;
+* weight: with L = log q(z) - sum_j z_j + sum_j log(hi_j - lo_j) (the log
+  ratio proposal / prior in theta space; sum_j z_j is the Jacobian of
+  theta = exp(z)), log w = -log(a + (1 - a) e^L); L = -inf when some
+  theta_j = 0.  Normalised over the accepted draws with a max shift in FP64;
 * summaries: weighted mean sum w t / sum w, weighted variance
   sum w (t - mean)^2 / sum w, effective sample size (sum w)^2 / sum w^2.
 """
@@ -64,7 +71,7 @@ def forward(p: dict, x: np.ndarray):
     return o, (x, a1, h1, a2, h2)
 
 
-def mixture(o: np.ndarray):
+def mixture(o: np.ndarray, sd_scale: float = 1.0):
     """(log pi [B][C], mu [B][C][D], log sd [B][C][D]) of network outputs."""
     logits = o[:, :C]
     m = logits.max(axis=1, keepdims=True)
@@ -72,12 +79,14 @@ def mixture(o: np.ndarray):
     mu = o[:, C:C + C * D].reshape(-1, C, D)
     raw = o[:, C + C * D:C + 2 * C * D].reshape(-1, C, D)
     logsd = LS0 + (LS1 - LS0) / (1.0 + np.exp(-raw))
+    if sd_scale != 1.0:
+        logsd = logsd + math.log(sd_scale)
     return logpi, mu, logsd
 
 
-def log_density(o: np.ndarray, z: np.ndarray) -> np.ndarray:
+def log_density(o: np.ndarray, z: np.ndarray, sd_scale: float = 1.0) -> np.ndarray:
     """log q(z) per row (the mixture density of z)."""
-    logpi, mu, logsd = mixture(o)
+    logpi, mu, logsd = mixture(o, sd_scale)
     t = (z[:, None, :] - mu) * np.exp(-logsd)
     comp = logpi + (-0.5 * t * t - logsd - 0.5 * math.log(2.0 * math.pi)).sum(axis=2)
     mx = comp.max(axis=1, keepdims=True)
@@ -130,11 +139,13 @@ def adam(p: dict, g: dict, state: dict, lr: float, b1=0.9, b2=0.999, eps=1e-8):
         p[k] -= lr * mh / (np.sqrt(vh) + eps)
 
 
-def draws(o_v: np.ndarray, words: np.ndarray):
+def draws(o_v: np.ndarray, words: np.ndarray, lo=None, hi=None, prior_share: float = 0.0, sd_scale: float = 1.0):
     """Proposal draws of one voxel: z [n][D] (FP64), theta [n][D] (fp32) from the
-    voxel's network output o_v [72] and Philox words [n][8]."""
-    logpi, mu, logsd = mixture(o_v[None, :])
-    cum = np.cumsum(np.exp(logpi[0]))
+    voxel's network output o_v [72], Philox words [n][8] and, for the
+    defensive share, the fp32 prior box lo, hi [D]."""
+    logpi, mu, logsd = mixture(o_v[None, :], sd_scale)
+    a = float(prior_share)
+    cum = a + (1.0 - a) * np.cumsum(np.exp(logpi[0]))
     u0 = (words[:, 0] >> 8).astype(np.float64) * 2.0 ** -24
     c = np.minimum(np.searchsorted(cum, u0, side="right"), C - 1)
     nrm = np.empty((words.shape[0], D))
@@ -145,11 +156,31 @@ def draws(o_v: np.ndarray, words: np.ndarray):
         nrm[:, 2 * q] = r * np.cos(2.0 * math.pi * ub)
         nrm[:, 2 * q + 1] = r * np.sin(2.0 * math.pi * ub)
     z = mu[0][c] + np.exp(logsd[0][c]) * nrm
-    return z, np.exp(z).astype(np.float32)
+    th = np.exp(z).astype(np.float32)
+    from_prior = u0 < a
+    if from_prior.any():
+        u = (words[from_prior, 1:1 + D] >> 8).astype(np.float64) * 2.0 ** -24
+        lo64, hi64 = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+        th[from_prior] = (lo64 + u * (hi64 - lo64)).astype(np.float32)
+        with np.errstate(divide="ignore"):
+            z[from_prior] = np.log(th[from_prior].astype(np.float64))
+    return z, th
 
 
-def log_weight(o_v: np.ndarray, z: np.ndarray) -> np.ndarray:
-    return z.sum(axis=1) - log_density(np.repeat(o_v[None, :], z.shape[0], axis=0), z)
+def log_weight(o_v: np.ndarray, z: np.ndarray, lo=None, hi=None, prior_share: float = 0.0,
+               sd_scale: float = 1.0) -> np.ndarray:
+    """log w = -log(a + (1 - a) q(theta) / p(theta)) of draws z [n][D]."""
+    a = float(prior_share)
+    logvol = 0.0 if lo is None else float(np.sum(np.log(np.asarray(hi, np.float64) - np.asarray(lo, np.float64))))
+    L = np.full(z.shape[0], -np.inf)
+    fin = np.all(np.isfinite(z), axis=1)
+    if fin.any():
+        L[fin] = (log_density(np.repeat(o_v[None, :], int(fin.sum()), axis=0), z[fin], sd_scale)
+                  - z[fin].sum(axis=1) + logvol)
+    if a == 0.0:
+        return -L
+    with np.errstate(divide="ignore"):
+        return -np.logaddexp(math.log(a), np.log1p(-a) + L)
 
 
 def weighted_summary(theta: np.ndarray, logw: np.ndarray):
@@ -172,18 +203,20 @@ def philox_words(v: int, n: int, seed: int) -> np.ndarray:
     return out
 
 
-def infer_is(y_v, frame_times, input_fn, dt, box, o_v, n_draws, accept_frac, seed, v_global, lam=None):
+def infer_is(y_v, frame_times, input_fn, dt, box, o_v, n_draws, accept_frac, seed, v_global, lam=None,
+             prior_share=0.0, sd_scale=1.0):
     """Importance-weighted fixed-budget ABC of one voxel (irreversible 2TCM):
     n_draws proposal draws, the n closest valid ones accepted (ties to the lower
     draw index), weighted summaries.  Returns (accepted indices, moments [8][2]
     with Ki in slot 5 and NaN in unused slots, ESS, distances of every draw)."""
     import oracle as ora
     lam = ora.DEFAULT_LAMBDA if lam is None else lam
+    lo = np.array([np.float32(box[s][0]) for s in FREE_SLOTS], dtype=np.float64)
+    hi = np.array([np.float32(box[s][1]) for s in FREE_SLOTS], dtype=np.float64)
+    o_v = np.asarray(o_v, dtype=np.float64)
     words = philox_words(v_global, n_draws, seed)
-    z, th4 = draws(np.asarray(o_v, dtype=np.float64), words)
-    lo = np.array([np.float32(box[s][0]) for s in FREE_SLOTS])
-    hi = np.array([np.float32(box[s][1]) for s in FREE_SLOTS])
-    valid = np.all((th4 >= lo) & (th4 <= hi), axis=1)
+    z, th4 = draws(o_v, words, lo, hi, prior_share, sd_scale)
+    valid = np.all((th4 >= lo.astype(np.float32)) & (th4 <= hi.astype(np.float32)), axis=1)
     theta = np.full((n_draws, 8), np.nan, dtype=np.float32)
     theta[:, FREE_SLOTS] = th4
     cp = np.asarray(input_fn, dtype=np.float32)
@@ -202,7 +235,7 @@ def infer_is(y_v, frame_times, input_fn, dt, box, o_v, n_draws, accept_frac, see
     ess = np.nan
     if keep.size:
         cols = [0, 1, 2, 4, 5]
-        mean, var, ess = weighted_summary(t[:, cols], log_weight(np.asarray(o_v, dtype=np.float64), z[keep]))
+        mean, var, ess = weighted_summary(t[:, cols], log_weight(o_v, z[keep], lo, hi, prior_share, sd_scale))
         mom[cols, 0] = mean
         mom[cols, 1] = var
     return order, mom, ess, d

@@ -25,9 +25,13 @@ MAX_ACCEPT = 3968
 
 EXPORTED = ("vpet_abc_accept_count", "vpet_abc_simulate", "vpet_abc_infer", "vpet_abc_draws",
             "vpet_abc_bank_ld", "vpet_abc_bank_build", "vpet_abc_infer_bank", "vpet_abc_stream_bank",
-            "vpet_abc_last_error", "vpet_abc_version")
+            "vpet_abc_last_error", "vpet_abc_version", "vpet_proposal_init", "vpet_proposal_forward",
+            "vpet_proposal_loss_grad", "vpet_proposal_train")
 BANK_MAX_ACCEPT = 512
 BANK_MAX_FRAMES = 48
+PROPOSAL_NPARAM = 98912
+PROPOSAL_NOUT = 96
+PROPOSAL_MAX_FRAMES = 32
 
 
 class VpetError(RuntimeError):
@@ -47,7 +51,9 @@ class Opts(ctypes.Structure):
                 ("out_threshold", ctypes.c_void_p), ("voxel_offset", ctypes.c_int64),
                 ("waves_per_voxel", ctypes.c_int32), ("bank_pilot", ctypes.c_int64),
                 ("bank_scan", ctypes.c_int32), ("out_scan_ms", ctypes.POINTER(ctypes.c_float)),
-                ("out_fallback_voxels", ctypes.POINTER(ctypes.c_int64))]
+                ("out_fallback_voxels", ctypes.POINTER(ctypes.c_int64)),
+                ("proposal", ctypes.c_void_p), ("out_ess", ctypes.c_void_p),
+                ("proposal_prior_share", ctypes.c_double), ("proposal_sd_scale", ctypes.c_double)]
 
 
 def _load():
@@ -65,9 +71,14 @@ def _load():
     L.vpet_abc_infer_bank.argtypes = [P, i64, P, Grid, u32, i64, f64, P, P, P, P, ctypes.POINTER(Opts), P]
     L.vpet_abc_stream_bank.argtypes = [ctypes.c_char_p, i64, P, Grid, u32, i64, f64, P, P, i64, ctypes.c_char_p,
                                        ctypes.c_int32, i64, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_int64), P]
+    L.vpet_proposal_init.argtypes = [P, u64, P]
+    L.vpet_proposal_forward.argtypes = [P, P, i64, ctypes.c_int32, P, P]
+    L.vpet_proposal_loss_grad.argtypes = [P, P, P, i64, ctypes.c_int32, P, P, P]
+    L.vpet_proposal_train.argtypes = [P, P, P, i64, P, ctypes.c_int32, f64, f64, i64, ctypes.c_int32,
+                                      ctypes.c_float, u64, P, P]
     L.vpet_abc_last_error.restype = ctypes.c_char_p
     L.vpet_abc_version.restype = ctypes.c_int
-    for name in EXPORTED[:4] + EXPORTED[5:7]:
+    for name in EXPORTED[:4] + EXPORTED[5:8] + EXPORTED[10:]:
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -138,11 +149,16 @@ def simulate(model: int, theta, input_fn, frame_times, dt: float, out=None, stre
 
 def infer(tacs, frame_times, input_fn, dt: float, models, prior_box, n_draws: int, accept_frac: float,
           seed: int, *, weights=None, weight_floor=0.0, decay_lambda=0.0, distance="l2", debug=False,
-          voxel_offset=0, waves_per_voxel=0, out=None, stream=None) -> dict:
+          voxel_offset=0, waves_per_voxel=0, proposal=None, prior_share=0.0, sd_scale=1.0, out=None,
+          stream=None) -> dict:
     """Voxelwise rejection ABC on observed TACs [V][F] (fp32, device).
 
     Returns a dict of device tensors: moments [V][M][8][2], model_prob [V][M]
     and, with debug=True, accept_idx [V][n], accept_dist [V][n], threshold [V].
+    proposal: network outputs [V][96] (proposal_forward); the draws then come
+    from each voxel's mixture (with a defensive prior share prior_share and
+    every sd times sd_scale), the moments are importance-weighted and "ess"
+    [V] is returned as well.
     """
     import torch
     tacs = _dev_f32(tacs, "tacs")
@@ -178,6 +194,16 @@ def infer(tacs, frame_times, input_fn, dt: float, models, prior_box, n_draws: in
         o.out_threshold = res["threshold"].data_ptr()
     o.voxel_offset = int(voxel_offset)
     o.waves_per_voxel = int(waves_per_voxel)
+    if proposal is not None:
+        proposal = _dev_f32(proposal, "proposal")
+        if tuple(proposal.shape) != (V, PROPOSAL_NOUT):
+            raise ValueError(f"proposal must be [V][{PROPOSAL_NOUT}]")
+        o.proposal = proposal.data_ptr()
+        o.proposal_prior_share = float(prior_share)
+        o.proposal_sd_scale = float(sd_scale)
+        if "ess" not in res:
+            res["ess"] = torch.empty((V,), dtype=torch.float32, device=dev)
+        o.out_ess = res["ess"].data_ptr()
     grid = Grid(float(dt), cp.size, F)
     _check(lib.vpet_abc_infer(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p), cp.ctypes.data_as(ctypes.c_void_p),
                               grid, mask, box.ctypes.data_as(ctypes.c_void_p), int(n_draws), float(accept_frac),
@@ -313,6 +339,65 @@ def load_stream_outputs(out_prefix: str, n_voxels: int, n_models: int):
                     shape=(int(n_voxels), int(n_models), PSTRIDE, 2))
     prob = np.memmap(str(out_prefix) + ".prob", dtype=np.float32, mode="r", shape=(int(n_voxels), int(n_models)))
     return mom, prob
+
+
+def proposal_init(seed: int, device="cuda", stream=None):
+    """A freshly initialised parameter blob [PROPOSAL_NPARAM] (fp32, device)."""
+    import torch
+    p = torch.empty((PROPOSAL_NPARAM,), dtype=torch.float32, device=device)
+    _check(lib.vpet_proposal_init(_ptr(p), int(seed) & ((1 << 64) - 1), _stream(stream)))
+    return p
+
+
+def _params(p):
+    p = _dev_f32(p, "params")
+    if p.numel() != PROPOSAL_NPARAM:
+        raise ValueError(f"params must hold {PROPOSAL_NPARAM} floats")
+    return p
+
+
+def proposal_forward(params, tacs, out=None, stream=None):
+    """Network outputs [V][96] (fp32, device) of TACs [V][F]."""
+    import torch
+    params, tacs = _params(params), _dev_f32(tacs, "tacs")
+    V, F = tacs.shape
+    if out is None:
+        out = torch.empty((V, PROPOSAL_NOUT), dtype=torch.float32, device=tacs.device)
+    _check(lib.vpet_proposal_forward(_ptr(params), _ptr(tacs), V, F, _ptr(out), _stream(stream)))
+    return out
+
+
+def proposal_loss_grad(params, tacs, theta, stream=None):
+    """(loss [1], grad [PROPOSAL_NPARAM]) device tensors of one batch:
+    TACs [n][F] and parameter rows theta [n][8]."""
+    import torch
+    params, tacs, theta = _params(params), _dev_f32(tacs, "tacs"), _dev_f32(theta, "theta")
+    n, F = tacs.shape
+    if tuple(theta.shape) != (n, PSTRIDE):
+        raise ValueError("theta must be [n][8]")
+    g = torch.empty((PROPOSAL_NPARAM,), dtype=torch.float32, device=tacs.device)
+    loss = torch.empty((1,), dtype=torch.float32, device=tacs.device)
+    _check(lib.vpet_proposal_loss_grad(_ptr(params), _ptr(tacs), _ptr(theta), n, F, _ptr(g), _ptr(loss),
+                                       _stream(stream)))
+    return loss, g
+
+
+def proposal_train(params, bank_theta, bank_x, frame_times, *, steps: int, batch: int = 4096, lr: float = 1e-3,
+                   noise_level: float = 0.1, decay_lambda: float = 0.0, seed: int = 0, stream=None):
+    """Adam steps on params (in place) over a shared irreversible-2TCM bank;
+    returns the per-step batch losses (numpy, waits for the stream)."""
+    import torch
+    params = _params(params)
+    if not (bank_x.dtype == torch.float64 and bank_theta.dtype == torch.float32):
+        raise TypeError("bank_x must be float64 and bank_theta float32 (from bank_build)")
+    ft = _host(frame_times, np.float32)
+    losses = np.zeros(int(steps), dtype=np.float32)
+    _check(lib.vpet_proposal_train(_ptr(params), _ptr(bank_theta), _ptr(bank_x), int(bank_theta.shape[0]),
+                                   ft.ctypes.data_as(ctypes.c_void_p), ft.size - 1, float(noise_level),
+                                   float(decay_lambda), int(steps), int(batch), float(lr),
+                                   int(seed) & ((1 << 64) - 1),
+                                   losses.ctypes.data_as(ctypes.c_void_p) if steps > 0 else None, _stream(stream)))
+    return losses
 
 
 def version() -> int:

@@ -110,6 +110,13 @@ struct InferArgs {
     int* out_idx;
     float* out_dist;
     float* out_thr;
+    // importance-weighted ABC with a learned proposal (irreversible 2TCM only)
+    const float* prop;  // [V][96] network outputs, or nullptr for prior draws
+    float* out_ess;     // [V] effective sample size of the accepted weights
+    float plo[4], phi[4];  // prior box of K1, k2, k3, vB (fp32)
+    double prop_share;     // defensive prior share a of the proposal a p + (1 - a) q
+    double prop_logscale;  // log of the sd scale of every mixture component
+    double prop_logvol;    // sum_j log(phi_j - plo_j): minus the log prior density
 };
 
 // ---------------------------------------------------------------------------
@@ -1625,6 +1632,576 @@ void launch_mfma(dim3 grid, hipStream_t st, const BankArgs& Q) {
 }
 
 // ===========================================================================
+// Learned proposal (not in the paper): an amortised importance sampler for the
+// prior draws of Alg. 1.  A multilayer perceptron maps a voxel's observed TAC
+// (features x_f = log1p(max(y_f, 0)), zero-padded to 32) through two ReLU
+// layers of 256 to 72 outputs: 8 mixture logits, 8 x 4 means and 8 x 4 raw
+// scales of a diagonal Gaussian mixture over z = log(theta) of the free
+// parameters (K1, k2, k3, vB); log sd = LS0 + (LS1 - LS0) sigmoid(raw).  It is
+// trained on simulated (theta, noisy TAC) pairs by minimising the mean
+// negative log density of z, with bf16 matrix-core GEMMs (FP32 accumulation)
+// and FP32 master weights updated by Adam.  Draws from the mixture are
+// weighted by prior / proposal, so the ABC target is unchanged.
+// ===========================================================================
+constexpr int kMixC = 8, kMixD = 4;
+constexpr int kNetIn = 32, kNetH = 256, kNetOut = 96, kNetOutUsed = 72;
+constexpr double kLS0 = -6.0, kLS1 = 2.0;
+constexpr size_t kOffW1 = 0, kOffB1 = kOffW1 + (size_t)kNetIn * kNetH, kOffW2 = kOffB1 + kNetH,
+                 kOffB2 = kOffW2 + (size_t)kNetH * kNetH, kOffW3 = kOffB2 + kNetH,
+                 kOffB3 = kOffW3 + (size_t)kNetH * kNetOut, kNetParams = kOffB3 + kNetOut;
+static_assert(kNetParams == VPET_PROPOSAL_NPARAM, "parameter blob layout");
+
+// C = epilogue(op(A) op(B)): a(m, k) = A[m sam + k sak], b(k, n) = B[k sbk +
+// n sbn], FP32 in memory, bf16 on the matrix cores, FP32 accumulation.
+// Epilogue: + bias[n]; then ReLU (relu), or multiplication by (mask[m][n] > 0)
+// (the ReLU derivative of the forward activation); accumulate adds to C.
+struct GemmArgs {
+    const float* A;
+    long long sam, sak;
+    const float* B;
+    long long sbk, sbn;
+    float* C;
+    long long ldc;
+    const float* bias;
+    const float* mask;
+    long long ldm;
+    int M, N, K, relu, accumulate;
+};
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    return (uint32_t)bf16_rn(a) | ((uint32_t)bf16_rn(b) << 16);
+}
+
+// Split of 8 fp32 values into bf16 hi = rn(x) and lo = rn(x - hi), packed.
+__device__ __forceinline__ void split_bf16x8(const float (&x)[8], uint4& hi, uint4& lo) {
+    uint32_t h[8], l[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        h[e] = bf16_rn(x[e]);
+        l[e] = bf16_rn(x[e] - __uint_as_float(h[e] << 16));
+    }
+    hi = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+    lo = make_uint4(l[0] | (l[1] << 16), l[2] | (l[3] << 16), l[4] | (l[5] << 16), l[6] | (l[7] << 16));
+}
+
+// C = act(A B + bias) (or masked) with fp32 operands on BF16 matrix cores:
+// each operand is split into bf16 hi + lo and the product is hi*hi + hi*lo +
+// lo*hi (three MFMAs, FP32 accumulation), relative error about 3 * 2^-16 per
+// term instead of 2^-7 for a plain bf16 product.
+// Block = 4 wavefronts = a 64 x 64 tile of C (a 32 x 32 tile per wavefront).
+__global__ __launch_bounds__(256) void vpet_gemm_bf16x3_kernel(GemmArgs G) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.y * 64 + (wave >> 1) * 32, n0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int am = m0 + (lane & 31), bn = n0 + (lane & 31), kk = 8 * (lane >> 5);
+    f32x16_t acc = {};
+    for (int k0 = 0; k0 < G.K; k0 += 16) {
+        float a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + kk + e;
+            a[e] = (am < G.M && k < G.K) ? G.A[am * G.sam + k * G.sak] : 0.0f;
+            b[e] = (bn < G.N && k < G.K) ? G.B[k * G.sbk + bn * G.sbn] : 0.0f;
+        }
+        uint4 ah, al, bh, bl;
+        split_bf16x8(a, ah, al);
+        split_bf16x8(b, bh, bl);
+        const bf16x8_t Ah = __builtin_bit_cast(bf16x8_t, ah), Al = __builtin_bit_cast(bf16x8_t, al);
+        const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, bh), Bl = __builtin_bit_cast(bf16x8_t, bl);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int m = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), n = n0 + (lane & 31);
+        if (m >= G.M || n >= G.N) continue;
+        float v = acc[r];
+        if (G.bias) v += G.bias[n];
+        if (G.relu) v = fmaxf(v, 0.0f);
+        if (G.mask && !(G.mask[(long long)m * G.ldm + n] > 0.0f)) v = 0.0f;
+        float* c = G.C + (long long)m * G.ldc + n;
+        *c = G.accumulate ? *c + v : v;
+    }
+}
+
+// db[n] = sum_m dY[m][n] (one block per column).
+__global__ __launch_bounds__(256) void vpet_colsum_kernel(const float* dY, long long ld, int M, float* out) {
+    const int n = blockIdx.x;
+    double s = 0.0;
+    for (int m = threadIdx.x; m < M; m += blockDim.x) s += (double)dY[(long long)m * ld + n];
+    __shared__ double part[4];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[n] = (float)(part[0] + part[1] + part[2] + part[3]);
+}
+
+// Mean negative log density of z[b][4] under the mixture of O[b][96] and its
+// gradient dO (already divided by the batch size); loss_acc += mean.
+__global__ __launch_bounds__(256) void vpet_mix_loss_kernel(const float* O, const float* Z, int Bn, float* dO,
+                                                            float* loss_acc) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    double nll = 0.0;
+    if (b < Bn) {
+        const float* o = O + (size_t)b * kNetOut;
+        float* d = dO + (size_t)b * kNetOut;
+        double lg[kMixC], comp[kMixC], mx = -1e300;
+#pragma unroll
+        for (int c = 0; c < kMixC; ++c) mx = fmax(mx, (double)o[c]);
+        double se = 0.0;
+#pragma unroll
+        for (int c = 0; c < kMixC; ++c) se += exp((double)o[c] - mx);
+        const double lse_l = mx + log(se);
+        double cmx = -1e300;
+#pragma unroll
+        for (int c = 0; c < kMixC; ++c) {
+            lg[c] = (double)o[c] - lse_l;  // log pi_c
+            double q = lg[c];
+#pragma unroll
+            for (int j = 0; j < kMixD; ++j) {
+                const double sg = 1.0 / (1.0 + exp(-(double)o[kMixC + kMixC * kMixD + c * kMixD + j]));
+                const double lsd = kLS0 + (kLS1 - kLS0) * sg;
+                const double t = ((double)Z[b * kMixD + j] - (double)o[kMixC + c * kMixD + j]) * exp(-lsd);
+                q += -0.5 * t * t - lsd - 0.9189385332046727;  // 0.5 log(2 pi)
+            }
+            comp[c] = q;
+            cmx = fmax(cmx, q);
+        }
+        double sc = 0.0;
+#pragma unroll
+        for (int c = 0; c < kMixC; ++c) sc += exp(comp[c] - cmx);
+        const double lse = cmx + log(sc);
+        nll = -lse;
+        const double rB = 1.0 / (double)Bn;
+#pragma unroll
+        for (int c = 0; c < kMixC; ++c) {
+            const double r = exp(comp[c] - lse);
+            d[c] = (float)((exp(lg[c]) - r) * rB);
+#pragma unroll
+            for (int j = 0; j < kMixD; ++j) {
+                const double sg = 1.0 / (1.0 + exp(-(double)o[kMixC + kMixC * kMixD + c * kMixD + j]));
+                const double lsd = kLS0 + (kLS1 - kLS0) * sg;
+                const double isd = exp(-lsd);
+                const double t = ((double)Z[b * kMixD + j] - (double)o[kMixC + c * kMixD + j]) * isd;
+                d[kMixC + c * kMixD + j] = (float)(-r * t * isd * rB);
+                d[kMixC + kMixC * kMixD + c * kMixD + j] = (float)(r * (1.0 - t * t) * (kLS1 - kLS0) * sg * (1.0 - sg) * rB);
+            }
+        }
+        for (int q = kNetOutUsed; q < kNetOut; ++q) d[q] = 0.0f;
+    }
+    __shared__ double part[4];
+    double s = wave_sum(nll);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss_acc, (float)((part[0] + part[1] + part[2] + part[3]) / (double)Bn));
+}
+
+// Adam (Kingma and Ba) on the FP32 master weights; c1, c2 are the bias
+// corrections 1 / (1 - beta^t).
+__global__ __launch_bounds__(256) void vpet_adam_kernel(float* p, const float* g, float* m, float* v, long long n,
+                                                        float lr, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi, vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+}
+
+// He-normal weights (sd sqrt(2 / fan_in); the output layer sqrt(1 / fan_in)),
+// zero biases; normals from Philox stream 5 by Box-Muller.
+__global__ __launch_bounds__(256) void vpet_net_init_kernel(float* p, uint32_t key0, uint32_t key1) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)kNetParams) return;
+    double sd = 0.0;
+    if (i < (long long)kOffB1) sd = sqrt(2.0 / kNetIn);
+    else if (i >= (long long)kOffW2 && i < (long long)kOffB2) sd = sqrt(2.0 / kNetH);
+    else if (i >= (long long)kOffW3 && i < (long long)kOffB3) sd = sqrt(1.0 / kNetH);
+    uint32_t w[4];
+    philox10((uint32_t)i, 0u, 5u, 0u, key0, key1, w);
+    const double ua = ((double)(w[0] >> 8) + 1.0) * 0x1p-24, ub = (double)(w[1] >> 8) * 0x1p-24;
+    p[i] = (float)(sd * sqrt(-2.0 * log(ua)) * cos(2.0 * M_PI * ub));
+}
+
+// Network inputs X[b][32] = log1p(max(y, 0)) (zero padding) of observed TACs.
+__global__ __launch_bounds__(256) void vpet_net_features_kernel(const float* tacs, long long n, int F, float* X) {
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    for (int f = 0; f < kNetIn; ++f)
+        X[b * kNetIn + f] = f < F ? (float)log1p(fmax((double)tacs[b * F + f], 0.0)) : 0.0f;
+}
+
+// Training batch: bank row of sample j of epoch e is (j * mul + add) mod n_bank
+// (mul coprime with n_bank); the TAC gets fresh Gaussian noise
+// sd_f = sqrt(fac_f max(x_f, 0)) (fac_f = level e^{lambda tmid_f} / dt_f,
+// normals from Philox stream 4, counter (row, e, 4, f/4)); inputs as above and
+// targets z = log(max(theta, 1e-6)) of K1, k2, k3, vB.
+__global__ __launch_bounds__(256) void vpet_net_batch_kernel(const float* bank_theta, const double* bank_x, int ld,
+                                                             long long n_bank, int F, const double* fac,
+                                                             unsigned long long j0, unsigned long long mul,
+                                                             unsigned long long add, uint32_t epoch, int Bn,
+                                                             uint32_t key0, uint32_t key1, float* X, float* Z) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Bn) return;
+    const unsigned long long row = ((j0 + (unsigned long long)b) % (unsigned long long)n_bank * mul + add) %
+                                   (unsigned long long)n_bank;
+    const float* t = bank_theta + row * VPET_PSTRIDE;
+    const int sl[kMixD] = {0, 1, 2, 4};
+#pragma unroll
+    for (int j = 0; j < kMixD; ++j) Z[b * kMixD + j] = (float)log(fmax((double)t[sl[j]], 1e-6));
+    const double* x = bank_x + row * (size_t)ld;
+    for (int f0 = 0; f0 < kNetIn; f0 += 4) {
+        uint32_t w[4];
+        philox10((uint32_t)row, epoch, 4u, (uint32_t)(f0 >> 2), key0, key1, w);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const double ua = ((double)(w[2 * q] >> 8) + 1.0) * 0x1p-24, ub = (double)(w[2 * q + 1] >> 8) * 0x1p-24;
+            const double r = sqrt(-2.0 * log(ua));
+            double sn, cs;
+            sincos(2.0 * M_PI * ub, &sn, &cs);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int f = f0 + 2 * q + e;
+                float v = 0.0f;
+                if (f < F) {
+                    const double xf = x[f];
+                    const double y = xf + sqrt(fac[f] * fmax(xf, 0.0)) * (e ? sn : cs) * r;
+                    v = (float)log1p(fmax(y, 0.0));
+                }
+                X[(size_t)b * kNetIn + f] = v;
+            }
+        }
+    }
+}
+
+// Per-voxel mixture in FP64 (the proposal of voxel row), kept in LDS.
+struct MixTab {
+    double cum[kMixC], logpi[kMixC];
+    double mu[kMixC * kMixD], sd[kMixC * kMixD], logsd[kMixC * kMixD];
+    double share, log_share, log_rest, logvol;
+};
+
+// Mixture of one voxel's outputs o[72]: weights softmax(logits), log sd =
+// LS0 + (LS1 - LS0) sigmoid(raw) + logscale; cum[c] = a + (1 - a) (pi_0 + ...
+// + pi_c), the component thresholds of u0 above the defensive share a.
+__device__ void mix_table(const float* o, MixTab& t, double share, double logscale, double logvol) {
+    double mx = -1e300;
+    for (int c = 0; c < kMixC; ++c) mx = fmax(mx, (double)o[c]);
+    double se = 0.0;
+    for (int c = 0; c < kMixC; ++c) se += exp((double)o[c] - mx);
+    const double lse = mx + log(se);
+    double run = 0.0;
+    for (int c = 0; c < kMixC; ++c) {
+        t.logpi[c] = (double)o[c] - lse;
+        run += exp(t.logpi[c]);
+        t.cum[c] = share + (1.0 - share) * run;
+        for (int j = 0; j < kMixD; ++j) {
+            const int q = c * kMixD + j;
+            t.mu[q] = (double)o[kMixC + q];
+            t.logsd[q] = kLS0 + (kLS1 - kLS0) / (1.0 + exp(-(double)o[kMixC + kMixC * kMixD + q]));
+            if (logscale != 0.0) t.logsd[q] += logscale;
+            t.sd[q] = exp(t.logsd[q]);
+        }
+    }
+    t.share = share;
+    t.log_share = log(share);
+    t.log_rest = log1p(-share);
+    t.logvol = logvol;
+}
+
+// Proposal draw i of voxel v: Philox stream 2.  u0 below the defensive share
+// draws theta uniformly from the box (z = log theta); otherwise a component
+// by inverse CDF and Box-Muller normals give z, theta = fp32(exp(z)).  Draw
+// order of the irreversible 2TCM (K1, k2, k3, vB).  False outside the box.
+__device__ __forceinline__ bool proposal_draw(const MixTab& t, uint32_t key0, uint32_t key1, uint32_t v, uint32_t i,
+                                              const float* lo, const float* hi, float th[kMaxParams],
+                                              double z[kMixD]) {
+    uint32_t w[8];
+    philox10(i, v, 2u, 0u, key0, key1, w);
+    philox10(i, v, 2u, 1u, key0, key1, w + 4);
+    const double u0 = (double)(w[0] >> 8) * 0x1p-24;
+    if (u0 < t.share) {
+#pragma unroll
+        for (int j = 0; j < kMixD; ++j) {
+            const double u = (double)(w[1 + j] >> 8) * 0x1p-24;
+            th[j] = (float)((double)lo[j] + u * ((double)hi[j] - (double)lo[j]));
+            z[j] = log((double)th[j]);
+        }
+#pragma unroll
+        for (int j = kMixD; j < kMaxParams; ++j) th[j] = 0.0f;
+        return true;
+    }
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < kMixC - 1; ++q) c += (t.cum[q] <= u0) ? 1 : 0;
+    double nrm[kMixD];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const double ua = ((double)(w[1 + 2 * q] >> 8) + 1.0) * 0x1p-24;
+        const double ub = (double)(w[2 + 2 * q] >> 8) * 0x1p-24;
+        const double r = sqrt(-2.0 * log(ua));
+        double sn, cs;
+        sincos(2.0 * M_PI * ub, &sn, &cs);
+        nrm[2 * q] = r * cs;
+        nrm[2 * q + 1] = r * sn;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < kMixD; ++j) {
+        z[j] = t.mu[c * kMixD + j] + t.sd[c * kMixD + j] * nrm[j];
+        th[j] = (float)exp(z[j]);
+        ok = ok && th[j] >= lo[j] && th[j] <= hi[j];
+    }
+#pragma unroll
+    for (int j = kMixD; j < kMaxParams; ++j) th[j] = 0.0f;
+    return ok;
+}
+
+// log w = -log(a + (1 - a) e^L), L = log q(z) - sum_j z_j + logvol the log
+// ratio proposal / prior in theta space (sum_j z_j: the Jacobian of exp);
+// L = -inf where some theta_j = 0.  With a = 0 simply -L.
+__device__ __forceinline__ double proposal_log_weight(const MixTab& t, const double z[kMixD]) {
+    bool fin = true;
+#pragma unroll
+    for (int j = 0; j < kMixD; ++j) fin = fin && isfinite(z[j]);
+    if (!fin) return -t.log_share;
+    double comp[kMixC], mx = -1e300;
+#pragma unroll
+    for (int c = 0; c < kMixC; ++c) {
+        double q = t.logpi[c];
+#pragma unroll
+        for (int j = 0; j < kMixD; ++j) {
+            const double u = (z[j] - t.mu[c * kMixD + j]) / t.sd[c * kMixD + j];
+            q += -0.5 * u * u - t.logsd[c * kMixD + j] - 0.9189385332046727;
+        }
+        comp[c] = q;
+        mx = fmax(mx, q);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMixC; ++c) s += exp(comp[c] - mx);
+    double zs = 0.0;
+#pragma unroll
+    for (int j = 0; j < kMixD; ++j) zs += z[j];
+    const double L = (mx + log(s)) - zs + t.logvol;
+    if (t.share == 0.0) return -L;
+    const double x = t.log_share, y = t.log_rest + L;  // -logaddexp(x, y)
+    const double m = fmax(x, y);
+    return -(m + log1p(exp(-fabs(x - y))));
+}
+
+// Keys of one tile of proposal draws (invalid draws never enter the top n).
+template <int U, bool L1>
+__device__ __forceinline__ void tile_keys_is(const InferArgs& P, const MixTab& mix, uint32_t v, uint32_t i0,
+                                             const double2* yw, uint64_t (&key)[U]) {
+    DrawState<1, U> s;
+    uint32_t idx[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t i = i0 + (uint32_t)(u * kWave + lane_id());
+        idx[u] = i < P.n_draws ? i : P.n_draws - 1;
+        float th[kMaxParams];
+        double z[kMixD];
+        ok[u] = proposal_draw(mix, P.key0, P.key1, v, idx[u], P.plo, P.phi, th, z) && i < P.n_draws;
+        if (!ok[u]) {  // a harmless in-box stand-in keeps the lane's recursion finite
+            th[0] = P.plo[0] + 0.5f * (P.phi[0] - P.plo[0]);
+            th[1] = P.plo[1] + 0.5f * (P.phi[1] - P.plo[1]);
+            th[2] = P.plo[2] + 0.5f * (P.phi[2] - P.plo[2]);
+            th[3] = P.plo[3];
+        }
+        setup<KIND_IRR, 1, U>(th, P.h, P.C0, s, u);
+    }
+    DistSink<U, L1> sink;
+    sink.yw = yw;
+#pragma unroll
+    for (int u = 0; u < U; ++u) sink.d[u] = 0.0;
+    simulate_draws<KIND_IRR, U>(P.tab, P.F, P.k0, s, sink);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        float fd = (float)sink.d[u];
+        if (!(fd == fd)) fd = __builtin_inff();
+        key[u] = ok[u] ? (((uint64_t)__float_as_uint(fd) << 32) | idx[u]) : kNoKey;
+    }
+}
+
+__device__ double block_max(double v, double* red, int nw) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    if (lane_id() == 0) red[(threadIdx.x >> 6) * kRedStride] = v;
+    __syncthreads();
+    double m = -__builtin_inf();
+    for (int w = 0; w < nw; ++w) m = fmax(m, red[w * kRedStride]);
+    __syncthreads();
+    return m;
+}
+
+// Importance-weighted ABC of one voxel per block (irreversible 2TCM): n_draws
+// proposal draws from the voxel's mixture, the n closest valid ones accepted,
+// moments weighted by prior / proposal (FP64, max-shifted), and the effective
+// sample size (sum w)^2 / sum w^2.
+template <bool L1>
+__global__ __launch_bounds__(256) void vpet_infer_is_kernel(InferArgs P) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long row = blockIdx.x;
+    if (row >= P.V) return;
+    const int F = P.F;
+    const uint32_t vg = (uint32_t)(P.vbase + (unsigned long long)row);
+    double2* yw = reinterpret_cast<double2*>(lds);
+    const int yw_bytes = (16 * F + 15) & ~15;
+    uint64_t* keys_all = reinterpret_cast<uint64_t*>(lds + yw_bytes);
+    double* red = reinterpret_cast<double*>(keys_all + (size_t)P.wpv * P.cap);
+    int* flag = reinterpret_cast<int*>(red + kRedStride * kMaxWpv);
+    MixTab* mix = reinterpret_cast<MixTab*>(reinterpret_cast<unsigned char*>(flag) + 16);
+    const int n = (int)P.n_acc;
+    if (wave == 0) {
+        const float* y = P.tacs + (size_t)row * F;
+        const cdp FR = (cdp)P.tab.fr;
+        const cip NF = (cip)P.tab.nf;
+        float ymax = -__builtin_inff();
+        int bad = 0;
+        for (int f = lane; f < F; f += kWave) {
+            const float yy = y[f];
+            bad |= !isfinite(yy);
+            ymax = fmaxf(ymax, yy);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            ymax = fmaxf(ymax, __shfl_xor(ymax, off, kWave));
+            bad |= __shfl_xor(bad, off, kWave);
+        }
+        const bool valid = !bad && ymax > 0.0f;
+        const double den_floor = P.floor_frac * (double)ymax;
+        for (int f = lane; f < F; f += kWave) {
+            const double nfd = (double)NF[f];
+            const double yy = (double)y[f];
+            double w;
+            if (P.weights) {
+                w = (double)P.weights[(size_t)row * F + f];
+            } else {
+                const double den = yy > den_floor ? yy : den_floor;
+                w = FR[4 * f + 3] / den;
+            }
+            const double W = P.l1 ? sqrt(w) / nfd : w / (nfd * nfd);
+            yw[f] = make_double2(nfd * yy, W);
+        }
+        if (lane == 0) {
+            *flag = valid ? 1 : 0;
+            mix_table(P.prop + (size_t)row * kNetOut, *mix, P.prop_share, P.prop_logscale, P.prop_logvol);
+        }
+    }
+    __syncthreads();
+    if (*flag == 0) {
+        if (wave == 0) {
+            const float qnan = __builtin_nanf("");
+            for (int j = lane; j < 16; j += kWave) P.out_mom[(size_t)row * 16 + j] = qnan;
+            if (lane == 0) {
+                P.out_prob[row] = qnan;
+                if (P.out_ess) P.out_ess[row] = qnan;
+                if (P.out_thr) P.out_thr[row] = qnan;
+            }
+            if (P.out_idx)
+                for (int j = lane; j < n; j += kWave) P.out_idx[(size_t)row * n + j] = -1;
+            if (P.out_dist)
+                for (int j = lane; j < n; j += kWave) P.out_dist[(size_t)row * n + j] = qnan;
+        }
+        return;
+    }
+    TopN top;
+    top.keys = keys_all + (size_t)wave * P.cap;
+    top.n = n;
+    top.cap = P.cap;
+    top.nbuf = 0;
+    top.tau = kNoKey;
+    for (int j = lane; j < P.cap; j += kWave) top.keys[j] = kNoKey;
+    wave_lds_sync();
+    constexpr int kU = kUmax;
+    constexpr int kTile = kWave * kU;
+    const uint32_t ntiles = (P.n_draws + kTile - 1) / kTile;
+    for (uint32_t t = (uint32_t)wave; t < ntiles; t += (uint32_t)P.wpv) {
+        uint64_t key[kU];
+        tile_keys_is<kU, L1>(P, *mix, vg, t * kTile, yw, key);
+        top.insert(key);
+    }
+    top.merge();
+    __syncthreads();
+    if (P.wpv > 1) block_bitonic_sort(keys_all, P.wpv * P.cap);
+    const uint64_t* acc = keys_all;
+    if (P.out_idx)
+        for (int j = tid; j < n; j += blockDim.x)
+            P.out_idx[(size_t)row * n + j] = acc[j] == kNoKey ? -1 : (int)(uint32_t)acc[j];
+    if (P.out_dist)
+        for (int j = tid; j < n; j += blockDim.x) P.out_dist[(size_t)row * n + j] = __uint_as_float((uint32_t)(acc[j] >> 32));
+    if (P.out_thr && tid == 0) P.out_thr[row] = __uint_as_float((uint32_t)(acc[n - 1] >> 32));
+
+    // weights of the accepted draws: max, then sums, then the spread
+    const int nw = blockDim.x >> 6;
+    auto accepted = [&](int j, float th[kMaxParams], double& lw) {
+        if (acc[j] == kNoKey) return false;
+        double z[kMixD];
+        proposal_draw(*mix, P.key0, P.key1, vg, (uint32_t)acc[j], P.plo, P.phi, th, z);
+        lw = proposal_log_weight(*mix, z);
+        return true;
+    };
+    double lmax = -__builtin_inf();
+    for (int j = tid; j < n; j += blockDim.x) {
+        float th[kMaxParams];
+        double lw;
+        if (accepted(j, th, lw)) lmax = fmax(lmax, lw);
+    }
+    lmax = block_max(lmax, red, nw);
+    double s1[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s1[q] = 0.0;  // sum w val[0..5], sum w, sum w^2
+    for (int j = tid; j < n; j += blockDim.x) {
+        float th[kMaxParams];
+        double lw;
+        if (!accepted(j, th, lw)) continue;
+        const double w = exp(lw - lmax);
+        double val[6];
+        slot_values(KIND_IRR, th, val);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s1[q] = fma(w, val[q], s1[q]);
+        s1[6] += w;
+        s1[7] = fma(w, w, s1[7]);
+    }
+    block_sum<8>(s1, red, nw);
+    const double sw = s1[6];
+    double mean[6], s2[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        mean[q] = s1[q] / sw;
+        s2[q] = 0.0;
+    }
+    for (int j = tid; j < n; j += blockDim.x) {
+        float th[kMaxParams];
+        double lw;
+        if (!accepted(j, th, lw)) continue;
+        const double w = exp(lw - lmax);
+        double val[6];
+        slot_values(KIND_IRR, th, val);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double dv = val[q] - mean[q];
+            s2[q] = fma(w * dv, dv, s2[q]);
+        }
+    }
+    block_sum<6>(s2, red, nw);
+    if (tid < 16) {
+        const int q = tid >> 1;
+        float outv = __builtin_nanf("");
+        if (q < 6 && slot_used(KIND_IRR, q) && sw > 0.0) outv = (tid & 1) == 0 ? (float)mean[q] : (float)(s2[q] / sw);
+        P.out_mom[(size_t)row * 16 + tid] = outv;
+    }
+    if (tid == 0) {
+        P.out_prob[row] = sw > 0.0 ? 1.0f : __builtin_nanf("");
+        if (P.out_ess) P.out_ess[row] = sw > 0.0 ? (float)(sw * sw / s1[7]) : __builtin_nanf("");
+    }
+}
+
+// ===========================================================================
 // Host side.
 // ===========================================================================
 thread_local std::string g_err;
@@ -1970,6 +2547,26 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
     InferArgs P{};
     for (int m = 0; m < M; ++m)
         if ((rc = fill_model(kinds[m], prior_box + (size_t)m * VPET_PSTRIDE * 2, P.md[m])) != VPET_OK) return rc;
+    if (o.proposal) {
+        if (M != 1 || kinds[0] != KIND_IRR)
+            return fail(VPET_E_MODEL, "the learned proposal drives the irreversible 2TCM alone");
+        const int sl[4] = {VPET_SLOT_K1, VPET_SLOT_K2, VPET_SLOT_K3, VPET_SLOT_VB};
+        const double share = o.proposal_prior_share, scale = o.proposal_sd_scale == 0.0 ? 1.0 : o.proposal_sd_scale;
+        if (!(share >= 0.0 && share <= 1.0)) return fail(VPET_E_ARG, "opts.proposal_prior_share must lie in [0, 1]");
+        if (!(std::isfinite(scale) && scale > 0.0)) return fail(VPET_E_ARG, "opts.proposal_sd_scale must be > 0");
+        P.prop_logvol = 0.0;
+        for (int j = 0; j < 4; ++j) {
+            P.plo[j] = (float)prior_box[2 * sl[j]];
+            P.phi[j] = (float)prior_box[2 * sl[j] + 1];
+            P.prop_logvol += std::log((double)P.phi[j] - (double)P.plo[j]);
+        }
+        P.prop_share = share;
+        P.prop_logscale = std::log(scale);
+        P.prop = o.proposal;
+        P.out_ess = o.out_ess;
+    } else if (o.out_ess) {
+        return fail(VPET_E_ARG, "opts.out_ess needs opts.proposal");
+    }
     const double lambda = o.decay_lambda > 0.0 ? o.decay_lambda : std::log(2.0) / 109.8;
     HostTab T;
     if ((rc = make_tables(input_fn, frame_times, grid, lambda, T)) != VPET_OK) return rc;
@@ -1984,7 +2581,8 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
         while (wpv < kMaxWpv && (double)n_voxels * wpv < 8192.0) wpv <<= 1;
     }
     auto lds_for = [&](int w) {
-        return (size_t)((16 * T.F + 15) & ~15) + sizeof(uint64_t) * (size_t)w * cap + sizeof(double) * kRedStride * kMaxWpv + 16;
+        return (size_t)((16 * T.F + 15) & ~15) + sizeof(uint64_t) * (size_t)w * cap + sizeof(double) * kRedStride * kMaxWpv + 16 +
+               (o.proposal ? sizeof(MixTab) : 0);
     };
     while (wpv > 1 && lds_for(wpv) > (size_t)kLdsLimit) wpv >>= 1;
     if (lds_for(wpv) > (size_t)kLdsLimit) return fail(VPET_E_LIMIT, "selection buffer exceeds LDS");
@@ -2028,9 +2626,13 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
         Q.out_idx = o.out_accept_idx ? o.out_accept_idx + (size_t)base * n_acc : nullptr;
         Q.out_dist = o.out_accept_dist ? o.out_accept_dist + (size_t)base * n_acc : nullptr;
         Q.out_thr = o.out_threshold ? o.out_threshold + base : nullptr;
+        Q.prop = o.proposal ? o.proposal + (size_t)base * VPET_PROPOSAL_NOUT : nullptr;
+        Q.out_ess = o.out_ess ? o.out_ess + base : nullptr;
         const dim3 grid((unsigned)Q.V), block(kWave * wpv);
-        const int sel = (M == 1 ? kinds[0] : 0) * 2 + (o.distance == 1 ? 1 : 0);
+        const int sel = o.proposal ? -1 - o.distance : (M == 1 ? kinds[0] : 0) * 2 + (o.distance == 1 ? 1 : 0);
         switch (sel) {
+            case -1: hipLaunchKernelGGL((vpet_infer_is_kernel<false>), grid, block, lds, st, Q); break;
+            case -2: hipLaunchKernelGGL((vpet_infer_is_kernel<true>), grid, block, lds, st, Q); break;
             case 2 * KIND_IRR: hipLaunchKernelGGL((vpet_infer_kernel<KIND_IRR, false>), grid, block, lds, st, Q); break;
             case 2 * KIND_IRR + 1: hipLaunchKernelGGL((vpet_infer_kernel<KIND_IRR, true>), grid, block, lds, st, Q); break;
             case 2 * KIND_REV: hipLaunchKernelGGL((vpet_infer_kernel<KIND_REV, false>), grid, block, lds, st, Q); break;
@@ -2158,7 +2760,6 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
                     VPET_BANK_MAX_ACCEPT);
     // frame bounds and weights' decay factors (the input function is not needed)
     if (!frame_times) return fail(VPET_E_ARG, "frame_times must not be NULL");
-    if (!(std::isfinite(grid.dt) && grid.dt > 0.0f)) return fail(VPET_E_GRID, "grid.dt must be finite and > 0");
     if (grid.n_nodes < 2 || grid.n_frames < 1) return fail(VPET_E_GRID, "grid needs n_nodes >= 2, n_frames >= 1");
     if (grid.n_frames > VPET_BANK_MAX_FRAMES)
         return fail(VPET_E_LIMIT, "the bank form supports up to %d frames", VPET_BANK_MAX_FRAMES);
@@ -2583,6 +3184,253 @@ int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* f
     if ((rc = store(last - 1, (int)((last - 1 - done) & 1))) != VPET_OK) return rc;
     if (out_done) *out_done = last;
     return VPET_OK;
+}
+
+
+// ===========================================================================
+// Learned proposal: network evaluation and training.
+// ===========================================================================
+}  // extern "C"
+
+namespace {
+
+__global__ __launch_bounds__(256) void vpet_fill_kernel(float* p, long long n, float v) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void vpet_net_targets_kernel(const float* theta, long long n, float* Z) {
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    const int sl[kMixD] = {0, 1, 2, 4};
+    for (int j = 0; j < kMixD; ++j) Z[b * kMixD + j] = (float)log(fmax((double)theta[b * VPET_PSTRIDE + sl[j]], 1e-6));
+}
+
+// Activations of one batch of up to `rows` samples.
+struct NetWork {
+    float *X, *H1, *H2, *O, *dO, *dH1, *dH2, *Z;
+    long long rows;
+};
+
+size_t net_work_bytes(long long rows) {
+    return sizeof(float) * (size_t)rows * (kNetIn + 4 * kNetH + 2 * kNetOut + kMixD) + 8 * 256;
+}
+
+void net_work_carve(char* base, long long rows, NetWork& w) {
+    auto take = [&](size_t nfl) {
+        float* p = reinterpret_cast<float*>(base);
+        base += align256(sizeof(float) * nfl);
+        return p;
+    };
+    w.rows = rows;
+    w.X = take((size_t)rows * kNetIn);
+    w.H1 = take((size_t)rows * kNetH);
+    w.H2 = take((size_t)rows * kNetH);
+    w.dH1 = take((size_t)rows * kNetH);
+    w.dH2 = take((size_t)rows * kNetH);
+    w.O = take((size_t)rows * kNetOut);
+    w.dO = take((size_t)rows * kNetOut);
+    w.Z = take((size_t)rows * kMixD);
+}
+
+void gemm(hipStream_t st, const float* A, long long sam, long long sak, const float* B, long long sbk, long long sbn,
+          float* C, long long ldc, int M, int N, int K, const float* bias, int relu, const float* mask, long long ldm) {
+    GemmArgs G{A, sam, sak, B, sbk, sbn, C, ldc, bias, mask, ldm, M, N, K, relu, 0};
+    hipLaunchKernelGGL(vpet_gemm_bf16x3_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64)), dim3(256),
+                       0, st, G);
+}
+
+// H1 = relu(X W1 + b1), H2 = relu(H1 W2 + b2), O = H2 W3 + b3 for n rows of X.
+void net_forward(hipStream_t st, const float* p, const NetWork& w, int n) {
+    gemm(st, w.X, kNetIn, 1, p + kOffW1, kNetH, 1, w.H1, kNetH, n, kNetH, kNetIn, p + kOffB1, 1, nullptr, 0);
+    gemm(st, w.H1, kNetH, 1, p + kOffW2, kNetH, 1, w.H2, kNetH, n, kNetH, kNetH, p + kOffB2, 1, nullptr, 0);
+    gemm(st, w.H2, kNetH, 1, p + kOffW3, kNetOut, 1, w.O, kNetOut, n, kNetOut, kNetH, p + kOffB3, 0, nullptr, 0);
+}
+
+// Gradients of the mean negative log density into g (overwritten), given dO.
+void net_backward(hipStream_t st, const float* p, const NetWork& w, int n, float* g) {
+    gemm(st, w.H2, 1, kNetH, w.dO, kNetOut, 1, g + kOffW3, kNetOut, kNetH, kNetOut, n, nullptr, 0, nullptr, 0);
+    hipLaunchKernelGGL(vpet_colsum_kernel, dim3(kNetOut), dim3(256), 0, st, w.dO, (long long)kNetOut, n, g + kOffB3);
+    gemm(st, w.dO, kNetOut, 1, p + kOffW3, 1, kNetOut, w.dH2, kNetH, n, kNetH, kNetOut, nullptr, 0, w.H2, kNetH);
+    gemm(st, w.H1, 1, kNetH, w.dH2, kNetH, 1, g + kOffW2, kNetH, kNetH, kNetH, n, nullptr, 0, nullptr, 0);
+    hipLaunchKernelGGL(vpet_colsum_kernel, dim3(kNetH), dim3(256), 0, st, w.dH2, (long long)kNetH, n, g + kOffB2);
+    gemm(st, w.dH2, kNetH, 1, p + kOffW2, 1, kNetH, w.dH1, kNetH, n, kNetH, kNetH, nullptr, 0, w.H1, kNetH);
+    gemm(st, w.X, 1, kNetIn, w.dH1, kNetH, 1, g + kOffW1, kNetH, kNetIn, kNetH, n, nullptr, 0, nullptr, 0);
+    hipLaunchKernelGGL(vpet_colsum_kernel, dim3(kNetH), dim3(256), 0, st, w.dH1, (long long)kNetH, n, g + kOffB1);
+}
+
+int check_frames(int32_t n_frames) {
+    if (n_frames < 1 || n_frames > kNetIn) return fail(VPET_E_LIMIT, "the proposal network takes 1..%d frames", kNetIn);
+    return VPET_OK;
+}
+
+unsigned long long gcd_u64(unsigned long long a, unsigned long long b) {
+    while (b) {
+        const unsigned long long t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vpet_proposal_init(float* params, uint64_t seed, void* hip_stream) {
+    if (!params) return fail(VPET_E_ARG, "params must not be NULL");
+    hipLaunchKernelGGL(vpet_net_init_kernel, dim3((unsigned)((kNetParams + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)hip_stream, params, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? VPET_OK : hip_fail(e, "proposal init");
+}
+
+int vpet_proposal_forward(const float* params, const float* tacs, int64_t n, int32_t n_frames, float* out,
+                          void* hip_stream) {
+    int rc = check_frames(n_frames);
+    if (rc != VPET_OK) return rc;
+    if (n < 0) return fail(VPET_E_ARG, "n must be >= 0");
+    if (n == 0) return VPET_OK;
+    if (!params || !tacs || !out) return fail(VPET_E_ARG, "params, tacs and out must not be NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const long long rows = std::min<long long>(n, 1LL << 17);
+    char* scratch = nullptr;
+    hipError_t e = hipMallocAsync((void**)&scratch, net_work_bytes(rows), st);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "proposal scratch: %s", hipGetErrorString(e));
+    NetWork w;
+    net_work_carve(scratch, rows, w);
+    for (long long b0 = 0; b0 < n; b0 += rows) {
+        const int cnt = (int)std::min<long long>(rows, n - b0);
+        hipLaunchKernelGGL(vpet_net_features_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
+                           tacs + (size_t)b0 * n_frames, (long long)cnt, n_frames, w.X);
+        NetWork wo = w;
+        wo.O = out + (size_t)b0 * kNetOut;  // the last layer writes the caller's buffer
+        net_forward(st, params, wo, cnt);
+    }
+    e = hipGetLastError();
+    const hipError_t e2 = hipFreeAsync(scratch, st);
+    if (e != hipSuccess) return hip_fail(e, "proposal forward");
+    return e2 == hipSuccess ? VPET_OK : hip_fail(e2, "hipFreeAsync");
+}
+
+int vpet_proposal_loss_grad(const float* params, const float* tacs, const float* theta, int64_t n, int32_t n_frames,
+                            float* grad, float* loss, void* hip_stream) {
+    int rc = check_frames(n_frames);
+    if (rc != VPET_OK) return rc;
+    if (n < 1 || n > (1LL << 20)) return fail(VPET_E_ARG, "n must lie in [1, 2^20]");
+    if (!params || !tacs || !theta || !grad || !loss) return fail(VPET_E_ARG, "pointers must not be NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    char* scratch = nullptr;
+    hipError_t e = hipMallocAsync((void**)&scratch, net_work_bytes(n), st);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "proposal scratch: %s", hipGetErrorString(e));
+    NetWork w;
+    net_work_carve(scratch, n, w);
+    const unsigned blk = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(vpet_net_features_kernel, dim3(blk), dim3(256), 0, st, tacs, (long long)n, n_frames, w.X);
+    hipLaunchKernelGGL(vpet_net_targets_kernel, dim3(blk), dim3(256), 0, st, theta, (long long)n, w.Z);
+    hipLaunchKernelGGL(vpet_fill_kernel, dim3(1), dim3(256), 0, st, loss, 1LL, 0.0f);
+    net_forward(st, params, w, (int)n);
+    hipLaunchKernelGGL(vpet_mix_loss_kernel, dim3(blk), dim3(256), 0, st, w.O, w.Z, (int)n, w.dO, loss);
+    net_backward(st, params, w, (int)n, grad);
+    e = hipGetLastError();
+    const hipError_t e2 = hipFreeAsync(scratch, st);
+    if (e != hipSuccess) return hip_fail(e, "proposal loss/gradient");
+    return e2 == hipSuccess ? VPET_OK : hip_fail(e2, "hipFreeAsync");
+}
+
+int vpet_proposal_train(float* params, const float* bank_theta, const double* bank_x, int64_t n_bank,
+                        const float* frame_times, int32_t n_frames, double noise_level, double decay_lambda,
+                        int64_t steps, int32_t batch, float learning_rate, uint64_t seed, float* out_loss,
+                        void* hip_stream) {
+    const int F = n_frames;
+    int rc = check_frames(F);
+    if (rc != VPET_OK) return rc;
+    if (!params || !bank_theta || !bank_x || !frame_times) return fail(VPET_E_ARG, "pointers must not be NULL");
+    if (n_bank < 1 || n_bank > 4294967295LL || steps < 0 || batch < 1 || batch > (1 << 20))
+        return fail(VPET_E_ARG, "need 1 <= n_bank < 2^32, steps >= 0, 1 <= batch <= 2^20");
+    if (!(learning_rate > 0.0f) || !(noise_level >= 0.0) || !(decay_lambda >= 0.0))
+        return fail(VPET_E_ARG, "learning_rate > 0, noise_level >= 0 and decay_lambda >= 0 are required");
+    std::vector<double> fac(kNetIn, 0.0);
+    for (int f = 0; f < F; ++f) {
+        const double a = frame_times[f], b = frame_times[f + 1];
+        if (!(std::isfinite(a) && std::isfinite(b) && b > a)) return fail(VPET_E_GRID, "frame bounds must increase");
+        fac[f] = noise_level * std::exp(decay_lambda * 0.5 * (a + b)) / (b - a);
+    }
+    if (steps == 0) return VPET_OK;
+    const int ld = vpet_abc_bank_ld(F);
+    DevCtx* ctx;
+    if ((rc = current_ctx(&ctx)) != VPET_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int slot;
+    const void* dfac;
+    if ((rc = upload_blob(*ctx, fac.data(), sizeof(double) * kNetIn, st, &dfac, slot)) != VPET_OK) return rc;
+    const size_t pbytes = align256(sizeof(float) * kNetParams);
+    char* scratch = nullptr;
+    hipError_t e = hipMallocAsync((void**)&scratch, 3 * pbytes + align256(sizeof(float) * (size_t)steps) +
+                                                        net_work_bytes(batch), st);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "training scratch: %s", hipGetErrorString(e));
+    float* g = reinterpret_cast<float*>(scratch);
+    float* m = reinterpret_cast<float*>(scratch + pbytes);
+    float* v = reinterpret_cast<float*>(scratch + 2 * pbytes);
+    float* losses = reinterpret_cast<float*>(scratch + 3 * pbytes);
+    NetWork w;
+    net_work_carve(scratch + 3 * pbytes + align256(sizeof(float) * (size_t)steps), batch, w);
+    const unsigned pblk = (unsigned)((kNetParams + 255) / 256);
+    hipLaunchKernelGGL(vpet_fill_kernel, dim3(pblk), dim3(256), 0, st, m, (long long)kNetParams, 0.0f);
+    hipLaunchKernelGGL(vpet_fill_kernel, dim3(pblk), dim3(256), 0, st, v, (long long)kNetParams, 0.0f);
+    hipLaunchKernelGGL(vpet_fill_kernel, dim3((unsigned)((steps + 255) / 256)), dim3(256), 0, st, losses,
+                       (long long)steps, 0.0f);
+    const unsigned long long N = (unsigned long long)n_bank;
+    unsigned long long mul = 1, add = 0;
+    long long epoch = -1;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    double b1t = 1.0, b2t = 1.0;
+    for (long long t = 0; t < steps; ++t) {
+        const unsigned long long j = (unsigned long long)t * (unsigned long long)batch;
+        if ((long long)(j / N) != epoch) {  // a new pass over the bank: a new affine permutation of its rows
+            epoch = (long long)(j / N);
+            uint32_t hw[4];
+            uint32_t c0 = (uint32_t)epoch, key0 = k0, key1 = k1, c1 = 0u, c2 = 6u, c3 = 0u;
+            for (int r = 0; r < 10; ++r) {  // the same Philox4x32-10 on the host
+                const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+                const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ key0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ key1;
+                c1 = (uint32_t)p1;
+                c3 = (uint32_t)p0;
+                c0 = n0;
+                c2 = n2;
+                key0 += 0x9E3779B9u;
+                key1 += 0xBB67AE85u;
+            }
+            hw[0] = c0;
+            hw[1] = c1;
+            mul = N > 1 ? (((unsigned long long)hw[0] << 32 | hw[1]) % (N - 1)) + 1 : 1;
+            while (gcd_u64(mul, N) != 1) mul = mul % N + 1;
+            add = N > 1 ? (unsigned long long)c2 % N : 0;
+        }
+        const unsigned blk = (unsigned)((batch + 255) / 256);
+        hipLaunchKernelGGL(vpet_net_batch_kernel, dim3(blk), dim3(256), 0, st, bank_theta, bank_x, ld, (long long)n_bank,
+                           F, static_cast<const double*>(dfac), j % N, mul, add, (uint32_t)epoch, (int)batch, k0, k1,
+                           w.X, w.Z);
+        net_forward(st, params, w, batch);
+        hipLaunchKernelGGL(vpet_mix_loss_kernel, dim3(blk), dim3(256), 0, st, w.O, w.Z, (int)batch, w.dO, losses + t);
+        net_backward(st, params, w, batch, g);
+        b1t *= 0.9;
+        b2t *= 0.999;
+        const double lr_t = learning_rate * 0.5 * (1.0 + std::cos(M_PI * (double)t / (double)steps));
+        hipLaunchKernelGGL(vpet_adam_kernel, dim3(pblk), dim3(256), 0, st, params, g, m, v, (long long)kNetParams,
+                           (float)lr_t, (float)(1.0 / (1.0 - b1t)), (float)(1.0 / (1.0 - b2t)));
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess && out_loss)
+        e = hipMemcpyAsync(out_loss, losses, sizeof(float) * (size_t)steps, hipMemcpyDeviceToHost, st);
+    const hipError_t e2 = hipFreeAsync(scratch, st);
+    const hipError_t e3 = hipEventRecord(ctx->ev[slot], st);
+    if (e == hipSuccess && out_loss) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "proposal training");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+    return e3 == hipSuccess ? VPET_OK : hip_fail(e3, "hipEventRecord");
 }
 
 }  // extern "C"

@@ -20,7 +20,7 @@ def V():
 
 def test_exports_every_declared_symbol(V):
     hdr = open(os.path.join(ROOT, "include", "vpet_abc.h")).read()
-    declared = set(re.findall(r"\b(vpet_abc_\w+)\s*\(", hdr))
+    declared = set(re.findall(r"\b(vpet_(?:abc|proposal)_\w+)\s*\(", hdr))
     assert declared == set(V.EXPORTED)
     for name in declared:
         assert hasattr(V.lib, name)
@@ -187,3 +187,52 @@ def test_stream_validation_without_gpu(V, tmp_path):
     assert sb(resume=1) == V.E_ARG                        # progress of a run of another shape
     assert V.lib.vpet_abc_stream_bank(str(path).encode(), 10, P(ft), g, 0, 1000, 0.01, fake, fake, 4, prefix, 0, 0,
                                       None, None, None) == V.E_MODEL
+
+
+def test_proposal_validation_without_gpu(V):
+    """The learned-proposal entry points and the proposal option of
+    vpet_abc_infer refuse bad requests before any device work."""
+    L = V.lib
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    assert L.vpet_proposal_init(None, 1, None) == V.E_ARG
+    assert L.vpet_proposal_forward(fake, fake, 10, 33, fake, None) == V.E_LIMIT
+    assert L.vpet_proposal_forward(fake, fake, 10, 0, fake, None) == V.E_LIMIT
+    assert L.vpet_proposal_forward(fake, fake, -1, 30, fake, None) == V.E_ARG
+    assert L.vpet_proposal_forward(fake, fake, 0, 30, fake, None) == V.OK  # nothing to do
+    assert L.vpet_proposal_forward(None, fake, 4, 30, fake, None) == V.E_ARG
+    assert L.vpet_proposal_loss_grad(fake, fake, fake, 0, 30, fake, fake, None) == V.E_ARG
+    assert L.vpet_proposal_loss_grad(fake, fake, fake, (1 << 20) + 1, 30, fake, fake, None) == V.E_ARG
+    assert L.vpet_proposal_loss_grad(fake, fake, None, 8, 30, fake, fake, None) == V.E_ARG
+    assert L.vpet_proposal_loss_grad(fake, fake, fake, 8, 40, fake, fake, None) == V.E_LIMIT
+    ft = W.frame_times(W.SCHED_30x50)
+    ftp = ft.ctypes.data_as(ctypes.c_void_p)
+
+    def train(n_bank=1000, ft_=ftp, F=30, noise=0.1, lam=0.0, steps=5, batch=64, lr=1e-3):
+        return L.vpet_proposal_train(fake, fake, fake, n_bank, ft_, F, noise, lam, steps, batch, lr, 1, None, None)
+    assert train(n_bank=0) == V.E_ARG
+    assert train(steps=-1) == V.E_ARG
+    assert train(batch=0) == V.E_ARG
+    assert train(lr=0.0) == V.E_ARG
+    assert train(lr=float("nan")) == V.E_ARG
+    assert train(noise=-1.0) == V.E_ARG
+    assert train(F=33) == V.E_LIMIT
+    bad = ft.copy()
+    bad[3] = bad[2]
+    assert train(ft_=bad.ctypes.data_as(ctypes.c_void_p)) == V.E_GRID
+    assert train(steps=0) == V.OK  # validated, nothing to do
+    o = V._binding.Opts()
+    o.proposal = 0x1000
+    assert _call_infer(V, model=1, V_=1, box=W.box_array([1]), opts=o)[0] == V.E_MODEL
+    assert _call_infer(V, model=6, V_=1, box=W.box_array([2, 4]), opts=o)[0] == V.E_MODEL
+    o.proposal_prior_share = 1.5
+    assert _call_infer(V, V_=1, opts=o)[0] == V.E_ARG
+    o.proposal_prior_share = float("nan")
+    assert _call_infer(V, V_=1, opts=o)[0] == V.E_ARG
+    o.proposal_prior_share = 0.1
+    o.proposal_sd_scale = -1.0
+    assert _call_infer(V, V_=1, opts=o)[0] == V.E_ARG
+    o.proposal_sd_scale = float("inf")
+    assert _call_infer(V, V_=1, opts=o)[0] == V.E_ARG
+    o2 = V._binding.Opts()
+    o2.out_ess = 0x1000
+    assert _call_infer(V, V_=1, opts=o2)[0] == V.E_ARG

@@ -117,3 +117,62 @@ def test_adam_first_step_and_training_lowers_loss():
         prop.adam(q, g, st, lr=1e-3)
     l1, _ = prop.loss_and_grad(q, x, z)
     assert l1 < l0 - 1.0, (l0, l1)
+
+
+def _box():
+    box = W.box_array([W.M_2TCM_IRR])[0]
+    lo = np.array([np.float32(box[s][0]) for s in prop.FREE_SLOTS], dtype=np.float64)
+    hi = np.array([np.float32(box[s][1]) for s in prop.FREE_SLOTS], dtype=np.float64)
+    return lo, hi
+
+
+def test_defensive_share_draws_the_prior_and_keeps_the_target(ora):
+    """Defensive mixture a p + (1 - a) q: a share 1 gives uniform draws on the
+    box with equal weights; a share 0.3 draws that fraction from the prior and,
+    with every draw accepted, the weighted means are still the prior means."""
+    lo, hi = _box()
+    rng = np.random.default_rng(5)
+    o = rng.standard_normal(prop.NOUT)
+    words = prop.philox_words(11, 100_000, 4)
+    z, th = prop.draws(o, words, lo, hi, prior_share=1.0)
+    assert np.all((th >= lo.astype(np.float32)) & (th <= hi.astype(np.float32)))
+    assert np.allclose(th.mean(axis=0), 0.5 * (lo + hi), atol=4.5 * np.sqrt((hi - lo) ** 2 / 12 / 1e5))
+    lw = prop.log_weight(o, z, lo, hi, prior_share=1.0)
+    assert np.all(lw == 0.0)
+    # a share of 0.3 around a broad proposal
+    o = np.zeros(prop.NOUT)
+    o[prop.C:prop.C + prop.C * prop.D] = np.tile(np.log(np.sqrt(np.maximum(lo, 1e-3) * hi)), prop.C)
+    o[prop.C + prop.C * prop.D:] = 1.0
+    words = prop.philox_words(3, 400_000, 22)
+    z, th = prop.draws(o, words, lo, hi, prior_share=0.3)
+    u0 = (words[:, 0] >> 8) * 2.0 ** -24
+    frac = np.mean(u0 < 0.3)
+    assert abs(frac - 0.3) < 4.5 * math.sqrt(0.3 * 0.7 / words.shape[0])
+    valid = np.all((th >= lo.astype(np.float32)) & (th <= hi.astype(np.float32)), axis=1)
+    lw = prop.log_weight(o, z[valid], lo, hi, prior_share=0.3)
+    assert np.all(lw <= -math.log(0.3) + 1e-12)  # every weight below 1 / a
+    w = np.exp(lw - lw.max())
+    est = (w[:, None] * th[valid].astype(np.float64)).sum(axis=0) / w.sum()
+    ess = w.sum() ** 2 / (w * w).sum()
+    se = np.sqrt((hi - lo) ** 2 / 12.0 / ess)
+    assert np.all(np.abs(est - 0.5 * (lo + hi)) < 4.5 * se), (est, se)
+    # the same draws weighted as if the share were 0 miss (the share term matters)
+    lw0 = prop.log_weight(o, z[valid], lo, hi, prior_share=0.0)
+    w0 = np.exp(lw0 - lw0.max())
+    est0 = (w0[:, None] * th[valid].astype(np.float64)).sum(axis=0) / w0.sum()
+    assert np.any(np.abs(est0 - 0.5 * (lo + hi)) > 10 * se)
+
+
+def test_sd_scale_widens_every_component():
+    rng = np.random.default_rng(6)
+    o = rng.standard_normal(prop.NOUT)
+    o[:prop.C] = -50.0
+    o[0] = 50.0  # one component
+    words = prop.philox_words(2, 200_000, 8)
+    z1, _ = prop.draws(o, words)
+    z2, _ = prop.draws(o, words, sd_scale=2.5)
+    logpi, mu, logsd = prop.mixture(o[None, :])
+    assert np.allclose(z2 - mu[0, 0], 2.5 * (z1 - mu[0, 0]), rtol=1e-12, atol=1e-12)
+    sd = np.exp(logsd[0, 0]) * 2.5
+    lq = prop.log_density(o[None, :], z2[:1], sd_scale=2.5)[0]
+    assert lq == pytest.approx(np.sum(stats.norm.logpdf(z2[0], loc=mu[0, 0], scale=sd)), rel=1e-9, abs=1e-9)
