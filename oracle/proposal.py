@@ -22,14 +22,15 @@ is unchanged).  Definitions:
   a wider proposal) and a defensive prior share a in [0, 1]: the proposal is
   a p(theta) + (1 - a) q(theta), a mixture with the prior (Hesterberg's
   defensive importance sampling), which bounds every weight by 1 / a;
-* draws (voxel v, draw i): Philox4x32-10 counter (i, v, 2, blk), key = seed,
-  words w0..w7, u0 = (w0>>8) 2^-24.  If u0 < a the draw is from the prior:
-  theta_j = fp32(lo_j + u_j (hi_j - lo_j)) with u_j = (w_{1+j}>>8) 2^-24 and
-  z_j = log theta_j.  Otherwise the component is the first c with
-  a + (1 - a) cumsum(pi)_c > u0; two Box-Muller pairs n_{2p}, n_{2p+1} =
-  r cos / sin(2 pi u_b), r = sqrt(-2 ln u_a), u_a = ((w_{1+2p}>>8) + 1) 2^-24,
-  u_b = (w_{2+2p}>>8) 2^-24; z_j = mu_cj + sd_cj n_j; theta_j = fp32(exp(z_j));
-  a draw outside the prior box (fp32 bounds) has weight 0;
+* draws (voxel v, draw i): one Philox4x32-10 block, counter (i, v, 2, 0),
+  key = seed, words w0..w3; u0 = ((w0 & 255) | (w1 & 255) << 8 | (w2 & 255)
+  << 16) 2^-24 from the low bytes, u_j = (w_j >> 8) 2^-24 from the high 24
+  bits.  If u0 < a the draw is from the prior: theta_j = fp32(lo_j + u_j
+  (hi_j - lo_j)) and z_j = log theta_j.  Otherwise the component is the first
+  c with a + (1 - a) cumsum(pi)_c > u0; two Box-Muller pairs n_{2p}, n_{2p+1}
+  = r cos / sin(2 pi u_{2p+1}), r = sqrt(-2 ln(u_{2p} + 2^-24)); z_j = mu_cj
+  + sd_cj n_j; theta_j = fp32(exp(z_j)); a draw outside the prior box (fp32
+  bounds) has weight 0;
 * weight: with L = log q(z) - sum_j z_j + sum_j log(hi_j - lo_j) (the log
   ratio proposal / prior in theta space; sum_j z_j is the Jacobian of
   theta = exp(z)), log w = -log(a + (1 - a) e^L); L = -inf when some
@@ -141,27 +142,26 @@ def adam(p: dict, g: dict, state: dict, lr: float, b1=0.9, b2=0.999, eps=1e-8):
 
 def draws(o_v: np.ndarray, words: np.ndarray, lo=None, hi=None, prior_share: float = 0.0, sd_scale: float = 1.0):
     """Proposal draws of one voxel: z [n][D] (FP64), theta [n][D] (fp32) from the
-    voxel's network output o_v [72], Philox words [n][8] and, for the
+    voxel's network output o_v [72], Philox words [n][4] and, for the
     defensive share, the fp32 prior box lo, hi [D]."""
     logpi, mu, logsd = mixture(o_v[None, :], sd_scale)
     a = float(prior_share)
     cum = a + (1.0 - a) * np.cumsum(np.exp(logpi[0]))
-    u0 = (words[:, 0] >> 8).astype(np.float64) * 2.0 ** -24
+    w = words.astype(np.uint64)
+    u0 = ((w[:, 0] & 255) | (w[:, 1] & 255) << 8 | (w[:, 2] & 255) << 16).astype(np.float64) * 2.0 ** -24
+    u = (w >> 8).astype(np.float64) * 2.0 ** -24
     c = np.minimum(np.searchsorted(cum, u0, side="right"), C - 1)
     nrm = np.empty((words.shape[0], D))
     for q in range(2):
-        ua = ((words[:, 1 + 2 * q] >> 8).astype(np.float64) + 1.0) * 2.0 ** -24
-        ub = (words[:, 2 + 2 * q] >> 8).astype(np.float64) * 2.0 ** -24
-        r = np.sqrt(-2.0 * np.log(ua))
-        nrm[:, 2 * q] = r * np.cos(2.0 * math.pi * ub)
-        nrm[:, 2 * q + 1] = r * np.sin(2.0 * math.pi * ub)
+        r = np.sqrt(-2.0 * np.log(u[:, 2 * q] + 2.0 ** -24))
+        nrm[:, 2 * q] = r * np.cos(2.0 * math.pi * u[:, 2 * q + 1])
+        nrm[:, 2 * q + 1] = r * np.sin(2.0 * math.pi * u[:, 2 * q + 1])
     z = mu[0][c] + np.exp(logsd[0][c]) * nrm
     th = np.exp(z).astype(np.float32)
     from_prior = u0 < a
     if from_prior.any():
-        u = (words[from_prior, 1:1 + D] >> 8).astype(np.float64) * 2.0 ** -24
         lo64, hi64 = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
-        th[from_prior] = (lo64 + u * (hi64 - lo64)).astype(np.float32)
+        th[from_prior] = (lo64 + u[from_prior] * (hi64 - lo64)).astype(np.float32)
         with np.errstate(divide="ignore"):
             z[from_prior] = np.log(th[from_prior].astype(np.float64))
     return z, th
@@ -193,14 +193,11 @@ def weighted_summary(theta: np.ndarray, logw: np.ndarray):
 
 
 def philox_words(v: int, n: int, seed: int) -> np.ndarray:
-    """Words [n][8] of the proposal draws i = 0..n-1 of voxel v (stream 2)."""
+    """Words [n][4] of the proposal draws i = 0..n-1 of voxel v (stream 2)."""
     import oracle as ora
     i = np.arange(n, dtype=np.uint32)
-    out = np.empty((n, 8), dtype=np.uint32)
-    for blk in range(2):
-        ctr = np.stack([i, np.full(n, v, np.uint32), np.full(n, 2, np.uint32), np.full(n, blk, np.uint32)], axis=1)
-        out[:, 4 * blk:4 * blk + 4] = ora.philox(ctr, seed)
-    return out
+    ctr = np.stack([i, np.full(n, v, np.uint32), np.full(n, 2, np.uint32), np.zeros(n, np.uint32)], axis=1)
+    return ora.philox(ctr, seed)
 
 
 def infer_is(y_v, frame_times, input_fn, dt, box, o_v, n_draws, accept_frac, seed, v_global, lam=None,

@@ -1668,10 +1668,6 @@ struct GemmArgs {
     int M, N, K, relu, accumulate;
 };
 
-__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
-    return (uint32_t)bf16_rn(a) | ((uint32_t)bf16_rn(b) << 16);
-}
-
 // Split of 8 fp32 values into bf16 hi = rn(x) and lo = rn(x - hi), packed.
 __device__ __forceinline__ void split_bf16x8(const float (&x)[8], uint4& hi, uint4& lo) {
     uint32_t h[8], l[8];
@@ -1880,12 +1876,14 @@ struct MixTab {
     double cum[kMixC], logpi[kMixC];
     double mu[kMixC * kMixD], sd[kMixC * kMixD], logsd[kMixC * kMixD];
     double share, log_share, log_rest, logvol;
+    float lo[kMixD], hi[kMixD];  // fp32 prior box of the drawn parameters
 };
 
 // Mixture of one voxel's outputs o[72]: weights softmax(logits), log sd =
 // LS0 + (LS1 - LS0) sigmoid(raw) + logscale; cum[c] = a + (1 - a) (pi_0 + ...
 // + pi_c), the component thresholds of u0 above the defensive share a.
-__device__ void mix_table(const float* o, MixTab& t, double share, double logscale, double logvol) {
+__device__ void mix_table(const float* o, MixTab& t, double share, double logscale, double logvol, const float* lo,
+                          const float* hi) {
     double mx = -1e300;
     for (int c = 0; c < kMixC; ++c) mx = fmax(mx, (double)o[c]);
     double se = 0.0;
@@ -1904,32 +1902,42 @@ __device__ void mix_table(const float* o, MixTab& t, double share, double logsca
             t.sd[q] = exp(t.logsd[q]);
         }
     }
+    for (int j = 0; j < kMixD; ++j) {
+        t.lo[j] = lo[j];
+        t.hi[j] = hi[j];
+    }
     t.share = share;
     t.log_share = log(share);
     t.log_rest = log1p(-share);
     t.logvol = logvol;
 }
 
-// Proposal draw i of voxel v: Philox stream 2.  u0 below the defensive share
+// Proposal draw i of voxel v: one Philox block (stream 2), u0 from the low
+// bytes of words 0-2, u_j = (w_j >> 8) 2^-24.  u0 below the defensive share
 // draws theta uniformly from the box (z = log theta); otherwise a component
 // by inverse CDF and Box-Muller normals give z, theta = fp32(exp(z)).  Draw
 // order of the irreversible 2TCM (K1, k2, k3, vB).  False outside the box.
+// With WANT_Z false, z is not formed for prior draws (the screening pass
+// needs theta only).
+template <bool WANT_Z>
 __device__ __forceinline__ bool proposal_draw(const MixTab& t, uint32_t key0, uint32_t key1, uint32_t v, uint32_t i,
-                                              const float* lo, const float* hi, float th[kMaxParams],
-                                              double z[kMixD]) {
-    uint32_t w[8];
+                                              float th[kMaxParams], double z[kMixD]) {
+    const float* lo = t.lo;
+    const float* hi = t.hi;
+    uint32_t w[4];
     philox10(i, v, 2u, 0u, key0, key1, w);
-    philox10(i, v, 2u, 1u, key0, key1, w + 4);
-    const double u0 = (double)(w[0] >> 8) * 0x1p-24;
+    const double u0 = (double)((w[0] & 255u) | (w[1] & 255u) << 8 | (w[2] & 255u) << 16) * 0x1p-24;
+    double u[kMixD];
+#pragma unroll
+    for (int j = 0; j < kMixD; ++j) u[j] = (double)(w[j] >> 8) * 0x1p-24;
+#pragma unroll
+    for (int j = kMixD; j < kMaxParams; ++j) th[j] = 0.0f;
     if (u0 < t.share) {
 #pragma unroll
         for (int j = 0; j < kMixD; ++j) {
-            const double u = (double)(w[1 + j] >> 8) * 0x1p-24;
-            th[j] = (float)((double)lo[j] + u * ((double)hi[j] - (double)lo[j]));
-            z[j] = log((double)th[j]);
+            th[j] = (float)((double)lo[j] + u[j] * ((double)hi[j] - (double)lo[j]));
+            if (WANT_Z) z[j] = log((double)th[j]);
         }
-#pragma unroll
-        for (int j = kMixD; j < kMaxParams; ++j) th[j] = 0.0f;
         return true;
     }
     int c = 0;
@@ -1938,24 +1946,40 @@ __device__ __forceinline__ bool proposal_draw(const MixTab& t, uint32_t key0, ui
     double nrm[kMixD];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const double ua = ((double)(w[1 + 2 * q] >> 8) + 1.0) * 0x1p-24;
-        const double ub = (double)(w[2 + 2 * q] >> 8) * 0x1p-24;
-        const double r = sqrt(-2.0 * log(ua));
+        const double r = sqrt(-2.0 * log(u[2 * q] + 0x1p-24));
         double sn, cs;
-        sincos(2.0 * M_PI * ub, &sn, &cs);
+        sincos(2.0 * M_PI * u[2 * q + 1], &sn, &cs);
         nrm[2 * q] = r * cs;
         nrm[2 * q + 1] = r * sn;
     }
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < kMixD; ++j) {
-        z[j] = t.mu[c * kMixD + j] + t.sd[c * kMixD + j] * nrm[j];
-        th[j] = (float)exp(z[j]);
+        const double zj = t.mu[c * kMixD + j] + t.sd[c * kMixD + j] * nrm[j];
+        if (WANT_Z) z[j] = zj;
+        th[j] = (float)exp(zj);
         ok = ok && th[j] >= lo[j] && th[j] <= hi[j];
     }
-#pragma unroll
-    for (int j = kMixD; j < kMaxParams; ++j) th[j] = 0.0f;
     return ok;
+}
+
+// The screening pass's draw as an out-of-line call: its transcendental
+// functions' FP64 constants are then formed inside the call instead of being
+// hoisted (and kept live, or spilled) across the whole simulation loop.
+struct ThetaDraw {
+    float th[kMixD];
+    int ok;
+};
+
+__device__ __attribute__((noinline)) ThetaDraw proposal_theta(const MixTab* t, uint32_t key0, uint32_t key1,
+                                                              uint32_t v, uint32_t i) {
+    ThetaDraw r;
+    float th[kMaxParams];
+    double z[kMixD];
+    r.ok = proposal_draw<false>(*t, key0, key1, v, i, th, z) ? 1 : 0;
+#pragma unroll
+    for (int j = 0; j < kMixD; ++j) r.th[j] = th[j];
+    return r;
 }
 
 // log w = -log(a + (1 - a) e^L), L = log q(z) - sum_j z_j + logvol the log
@@ -2003,13 +2027,17 @@ __device__ __forceinline__ void tile_keys_is(const InferArgs& P, const MixTab& m
         const uint32_t i = i0 + (uint32_t)(u * kWave + lane_id());
         idx[u] = i < P.n_draws ? i : P.n_draws - 1;
         float th[kMaxParams];
-        double z[kMixD];
-        ok[u] = proposal_draw(mix, P.key0, P.key1, v, idx[u], P.plo, P.phi, th, z) && i < P.n_draws;
+        const ThetaDraw d = proposal_theta(&mix, P.key0, P.key1, v, idx[u]);
+#pragma unroll
+        for (int j = 0; j < kMixD; ++j) th[j] = d.th[j];
+#pragma unroll
+        for (int j = kMixD; j < kMaxParams; ++j) th[j] = 0.0f;
+        ok[u] = d.ok && i < P.n_draws;
         if (!ok[u]) {  // a harmless in-box stand-in keeps the lane's recursion finite
-            th[0] = P.plo[0] + 0.5f * (P.phi[0] - P.plo[0]);
-            th[1] = P.plo[1] + 0.5f * (P.phi[1] - P.plo[1]);
-            th[2] = P.plo[2] + 0.5f * (P.phi[2] - P.plo[2]);
-            th[3] = P.plo[3];
+            th[0] = mix.hi[0];
+            th[1] = mix.hi[1];
+            th[2] = mix.lo[2];
+            th[3] = mix.lo[3];
         }
         setup<KIND_IRR, 1, U>(th, P.h, P.C0, s, u);
     }
@@ -2041,8 +2069,10 @@ __device__ double block_max(double v, double* red, int nw) {
 // proposal draws from the voxel's mixture, the n closest valid ones accepted,
 // moments weighted by prior / proposal (FP64, max-shifted), and the effective
 // sample size (sum w)^2 / sum w^2.
+// (At most 128 VGPRs for four waves per SIMD: the few spills this costs sit
+// in the accepted-draw epilogue, not in the screening loop.)
 template <bool L1>
-__global__ __launch_bounds__(256) void vpet_infer_is_kernel(InferArgs P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void vpet_infer_is_kernel(InferArgs P) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long row = blockIdx.x;
@@ -2089,7 +2119,8 @@ __global__ __launch_bounds__(256) void vpet_infer_is_kernel(InferArgs P) {
         }
         if (lane == 0) {
             *flag = valid ? 1 : 0;
-            mix_table(P.prop + (size_t)row * kNetOut, *mix, P.prop_share, P.prop_logscale, P.prop_logvol);
+            mix_table(P.prop + (size_t)row * kNetOut, *mix, P.prop_share, P.prop_logscale, P.prop_logvol, P.plo,
+                      P.phi);
         }
     }
     __syncthreads();
@@ -2141,7 +2172,7 @@ __global__ __launch_bounds__(256) void vpet_infer_is_kernel(InferArgs P) {
     auto accepted = [&](int j, float th[kMaxParams], double& lw) {
         if (acc[j] == kNoKey) return false;
         double z[kMixD];
-        proposal_draw(*mix, P.key0, P.key1, vg, (uint32_t)acc[j], P.plo, P.phi, th, z);
+        proposal_draw<true>(*mix, P.key0, P.key1, vg, (uint32_t)acc[j], th, z);
         lw = proposal_log_weight(*mix, z);
         return true;
     };

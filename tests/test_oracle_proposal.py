@@ -145,7 +145,8 @@ def test_defensive_share_draws_the_prior_and_keeps_the_target(ora):
     o[prop.C + prop.C * prop.D:] = 1.0
     words = prop.philox_words(3, 400_000, 22)
     z, th = prop.draws(o, words, lo, hi, prior_share=0.3)
-    u0 = (words[:, 0] >> 8) * 2.0 ** -24
+    w = words.astype(np.uint64)
+    u0 = ((w[:, 0] & 255) | (w[:, 1] & 255) << 8 | (w[:, 2] & 255) << 16) * 2.0 ** -24
     frac = np.mean(u0 < 0.3)
     assert abs(frac - 0.3) < 4.5 * math.sqrt(0.3 * 0.7 / words.shape[0])
     valid = np.all((th >= lo.astype(np.float32)) & (th <= hi.astype(np.float32)), axis=1)
