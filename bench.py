@@ -7,7 +7,10 @@ timed region.  Prints one JSON line.
 
 Default workload: 1,048,576 voxels (128 x 128 x 64), 30 frames over 50 min on a
 0.2-min grid, irreversible 2TCM prior box, 100,000 prior draws per voxel drawn
-independently for every voxel, 0.1 % accepted (n = 100).
+independently for every voxel, 0.1 % accepted (n = 100).  The same line carries
+the shared-bank form ("bank_form": one 100k-row bank for all voxels) and the
+learned proposal ("learned_proposal": 20k importance-weighted draws per voxel
+from a network trained on the GPU, with the error comparison against plain ABC).
 """
 from __future__ import annotations
 
@@ -239,6 +242,7 @@ def main():
     ap.add_argument("--scratch-dir", default="/tmp", help="tbpet: where the volume file and outputs are written")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bank", action="store_true", help="skip the shared-bank form")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal form")
     ap.add_argument("--bank-scan", choices=["bf16", "f64"], default="bf16",
                     help="pair screening of the shared-bank form: BF16 matrix cores or FP64 vector ALUs")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
@@ -334,27 +338,33 @@ def main():
     if not args.no_bank and F <= V.BANK_MAX_FRAMES:
         out["bank_form"] = bank_form(cfg, ft, cp, y_host, y, args.steps, args.warmup, not args.no_cpu_baseline,
                                      args.cpu_budget / 3, args.bank_scan)
+    if not args.no_learned and cfg.name == W.CFG_LARGE.name:
+        m_plain = res["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
+        del res
+        lf = learned_form(cfg, ft, cp, y_host, y, args.steps, args.warmup, not args.no_cpu_baseline,
+                          args.cpu_budget / 3, m_plain=m_plain)
+        lf["comparison"]["plain_100k_voxels_per_s"] = out["value"]
+        out["learned_proposal"] = lf
     print(json.dumps(out), flush=True)
 
 
-def main_learned(args, dev):
-    """Importance-weighted ABC with a learned proposal on the 1M-voxel volume:
-    the network is trained once on 10.24M noisy simulations (5000 Adam steps of
+def learned_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, cpu: bool, budget_s: float, m_plain=None):
+    """Importance-weighted ABC with a learned proposal on the same volume: the
+    network is trained once on 10.24M noisy simulations (5000 Adam steps of
     2048 rows of a 1M-draw bank, fresh noise per pass; outside the timed
     region), then one step = network forward pass + 20k proposal draws per
     voxel (defensive prior share 0.1, sd x 1.5), n = 100 accepted.  Plain ABC
-    at 100k prior draws (the whole volume) and at 1M prior draws (a 64k-voxel
-    subset) gives the error / throughput comparison."""
+    at 100k prior draws (the whole volume; m_plain if the caller has it) and at
+    1M prior draws (a 64k-voxel subset) gives the error / throughput
+    comparison.  Returns a dict for the JSON line."""
     import math
 
     import torch
 
     import paper_2603_14859_amd as V
     import workloads as W
-    cfg = W.CFG_LARGE
     IRR = W.M_2TCM_IRR
-    ft, cp, y_host = make_inputs(cfg, dev)
-    y = torch.from_numpy(y_host).to(dev)
+    dev = y.device
     th, _ = cfg.truth()
     ki = th[:, 0].astype(np.float64) * th[:, 2] / (th[:, 1] + th[:, 2])
     box = cfg.box_array()
@@ -387,54 +397,46 @@ def main_learned(args, dev):
         if ev is not None:
             ev[1].record(stream)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
+    for s in range(steps):
         step(ev[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    ms_per_step = wall * 1e3 / args.steps
+    ms_per_step = wall * 1e3 / steps
     m_is = res["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
     ess = res["ess"].cpu().numpy().astype(np.float64)
+    del res, prop_out
 
     # plain ABC: 100k prior draws over the whole volume, 1M on a subset
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r100 = V.infer(y, ft, cp, cfg.dt, [IRR], box, 100_000, n_acc / 100_000, cfg.infer_seed)
-    torch.cuda.synchronize()
-    t100 = time.perf_counter() - t0
-    m100 = r100["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
-    del r100
+    if m_plain is None:
+        r100 = V.infer(y, ft, cp, cfg.dt, [IRR], box, 100_000, n_acc / 100_000, cfg.infer_seed)
+        m_plain = r100["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
+        del r100
     sub = 65536
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     r1m = V.infer(y[:sub].contiguous(), ft, cp, cfg.dt, [IRR], box, 1_000_000, n_acc / 1_000_000, cfg.infer_seed)
     torch.cuda.synchronize()
     t1m = time.perf_counter() - t0
     m1m = r1m["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
 
-    def rmse(m, sl=slice(None)):
-        return float(math.sqrt(np.nanmean((m[sl, 0] - ki[sl]) ** 2)))
+    def rmse(m, n=nv):
+        return float(math.sqrt(np.nanmean((m[:n, 0] - ki[:n]) ** 2)))
+
     def agree(m, e):  # Ki means within 3 MC SE of plain ABC at 1M draws
         se = np.sqrt(m[:sub, 1] / e + m1m[:, 1] / n_acc)
         return float(np.nanmean(np.abs(m[:sub, 0] - m1m[:, 0]) <= 3.0 * se))
-    within = agree(m_is, ess[:sub])
-    within_pl = agree(m100, float(n_acc))
     fl = flops_per_draw(n_steps, F) * nv * n_is
     achieved = fl / (kernel_ms * 1e-3) / 1e12
-    out = {"metric": METRIC, "value": nv / (ms_per_step * 1e-3), "unit": "voxels/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64 simulation, bf16 network (fp32 accumulation)",
-           "data": "synthetic (seeded Feng input, uniform prior truths, Gaussian frame noise); network trained on "
-                   "simulations of the same forward model",
-           "config": {"workload": cfg.name + "-learned-proposal", "voxels": nv, "frames": F, "minutes": float(ft[-1]),
-                      "grid_dt_min": cfg.dt, "proposal_draws_per_voxel": n_is, "n_accept": n_acc,
-                      "prior_share": share, "sd_scale": scale, "models": ["2TCM-irreversible"],
-                      "parallelism": "single GPU"},
+    out = {"value": nv / (ms_per_step * 1e-3), "unit": "voxels/s", "ms_per_step": round(ms_per_step, 3),
+           "dtype": "f64 simulation, bf16x3 network (fp32 accumulation)",
+           "config": {"voxels": nv, "proposal_draws_per_voxel": n_is, "n_accept": n_acc, "prior_share": share,
+                      "sd_scale": scale, "models": ["2TCM-irreversible"]},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_F64_VECTOR_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_VECTOR_TFLOPS, 4), "traffic": None,
                         "kernel": "vpet_infer_is_kernel", "kernel_ms": round(kernel_ms, 3),
@@ -442,18 +444,18 @@ def main_learned(args, dev):
            "training": {**train, "samples": train["steps"] * train["batch"], "seconds": round(train_s, 2),
                         "loss_first_100": float(losses[:100].mean()), "loss_last_100": float(losses[-100:].mean())},
            "comparison": {
-               "ki_rmse_learned_20k": rmse(m_is), "ki_rmse_plain_100k": rmse(m100),
-               "plain_100k_voxels_per_s": nv / t100,
-               "subset_voxels": sub, "ki_rmse_learned_20k_subset": rmse(m_is, slice(0, sub)),
-               "ki_rmse_plain_1M_subset": rmse(m1m, slice(0, sub)), "plain_1M_voxels_per_s": sub / t1m,
+               "ki_rmse_learned_20k": rmse(m_is), "ki_rmse_plain_100k": rmse(m_plain),
+               "subset_voxels": sub, "ki_rmse_learned_20k_subset": rmse(m_is, sub),
+               "ki_rmse_plain_1M_subset": rmse(m1m, sub), "plain_1M_voxels_per_s": sub / t1m,
                "median_ess": float(np.nanmedian(ess)),
-               "frac_within_3_mc_se_of_plain_1M": within, "frac_within_3_mc_se_of_plain_1M_plain_100k": within_pl}}
-    if not args.no_cpu_baseline:
+               "frac_within_3_mc_se_of_plain_1M": agree(m_is, ess[:sub]),
+               "frac_within_3_mc_se_of_plain_1M_plain_100k": agree(m_plain, float(n_acc))}}
+    if cpu:
         import oracle.proposal as prop
         rng = np.random.default_rng(0)
         t0 = time.perf_counter()
         done = 0
-        while time.perf_counter() - t0 < args.cpu_budget or done == 0:
+        while time.perf_counter() - t0 < budget_s or done == 0:
             # a mixture centred near the voxel's truth (the oracle's cost does
             # not depend on the mixture: every draw is simulated)
             o = np.zeros(V.PROPOSAL_NOUT)
@@ -466,6 +468,39 @@ def main_learned(args, dev):
         out["cpu_baseline"] = {"value": done / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
                                "sample": f"first {done} voxels, {n_is} proposal draws each, FP64 numpy + C "
                                          f"(single thread, {dt:.1f} s)"}
+    return out
+
+
+def main_learned(args, dev):
+    """The learned-proposal form as the line's value (see learned_form); plain
+    ABC at 100k draws is timed once for the comparison."""
+    import torch
+
+    import paper_2603_14859_amd as V
+    import workloads as W
+    cfg = W.CFG_LARGE
+    ft, cp, y_host = make_inputs(cfg, dev)
+    y = torch.from_numpy(y_host).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r100 = V.infer(y, ft, cp, cfg.dt, [W.M_2TCM_IRR], cfg.box_array(), 100_000, 0.001, cfg.infer_seed)
+    torch.cuda.synchronize()
+    t100 = time.perf_counter() - t0
+    m100 = r100["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
+    del r100
+    lf = learned_form(cfg, ft, cp, y_host, y, args.steps, args.warmup, not args.no_cpu_baseline, args.cpu_budget,
+                      m_plain=m100)
+    lf["comparison"]["plain_100k_voxels_per_s"] = cfg.n_voxels / t100
+    out = {"metric": METRIC, "value": lf["value"], "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": lf["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": lf["dtype"],
+           "data": "synthetic (seeded Feng input, uniform prior truths, Gaussian frame noise); network trained on "
+                   "simulations of the same forward model",
+           "config": {"workload": cfg.name + "-learned-proposal", "frames": ft.size - 1, "minutes": float(ft[-1]),
+                      "grid_dt_min": cfg.dt, **lf["config"], "parallelism": "single GPU"},
+           "roofline": lf["roofline"], "training": lf["training"], "comparison": lf["comparison"]}
+    if "cpu_baseline" in lf:
+        out["cpu_baseline"] = lf["cpu_baseline"]
     print(json.dumps(out), flush=True)
 
 

@@ -201,11 +201,14 @@ def philox_words(v: int, n: int, seed: int) -> np.ndarray:
 
 
 def infer_is(y_v, frame_times, input_fn, dt, box, o_v, n_draws, accept_frac, seed, v_global, lam=None,
-             prior_share=0.0, sd_scale=1.0):
+             prior_share=0.0, sd_scale=1.0, l1=False, weights_v=None):
     """Importance-weighted fixed-budget ABC of one voxel (irreversible 2TCM):
     n_draws proposal draws, the n closest valid ones accepted (ties to the lower
-    draw index), weighted summaries.  Returns (accepted indices, moments [8][2]
-    with Ki in slot 5 and NaN in unused slots, ESS, distances of every draw)."""
+    draw index), weighted summaries.  Distances as in the plain method: the
+    noise-weighted L2 sum_f w_f (y_f - x_f)^2, or L1 sum_f sqrt(w_f) |y_f - x_f|,
+    with the default weights or the caller's weights_v.  Returns (accepted
+    indices, moments [8][2] with Ki in slot 5 and NaN in unused slots, ESS,
+    distances of every draw)."""
     import oracle as ora
     lam = ora.DEFAULT_LAMBDA if lam is None else lam
     lo = np.array([np.float32(box[s][0]) for s in FREE_SLOTS], dtype=np.float64)
@@ -218,11 +221,15 @@ def infer_is(y_v, frame_times, input_fn, dt, box, o_v, n_draws, accept_frac, see
     theta[:, FREE_SLOTS] = th4
     cp = np.asarray(input_fn, dtype=np.float32)
     y = np.asarray(y_v, dtype=np.float32)
-    w = ora.weights(y, frame_times, dt, cp.size, lam=lam)
+    if weights_v is None:
+        w = ora.weights(y, frame_times, dt, cp.size, lam=lam)
+    else:
+        w = np.asarray(weights_v, dtype=np.float32).astype(np.float64)
     d = np.full(n_draws, np.inf)
     if valid.any():
         x = ora.simulate(ora.M_2TCM_IRR, theta[valid], cp, dt, frame_times)
-        d[valid] = (w * (y.astype(np.float64) - x) ** 2).sum(axis=1)
+        r = y.astype(np.float64) - x
+        d[valid] = (np.sqrt(w) * np.abs(r)).sum(axis=1) if l1 else (w * r * r).sum(axis=1)
     n = ora.accept_count(n_draws, accept_frac)
     order = np.lexsort((np.arange(n_draws), d))[:n]
     keep = order[np.isfinite(d[order])]

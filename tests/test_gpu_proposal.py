@@ -198,10 +198,12 @@ def _synthetic_outputs(th, rng, spread=0.2, sd=0.3):
     return o
 
 
-def _check_is(y, ft, cp, o, n_draws, p, seed, v_off=0, share=0.0, scale=1.0):
+def _check_is(y, ft, cp, o, n_draws, p, seed, v_off=0, share=0.0, scale=1.0, l1=False, weights=None):
     box, lo, hi = _box_lohi()
     res = V.infer(torch.from_numpy(y).to(DEV), ft, cp, H, [IRR], box[None], n_draws, p, seed, debug=True,
-                  proposal=torch.from_numpy(o).to(DEV), voxel_offset=v_off, prior_share=share, sd_scale=scale)
+                  proposal=torch.from_numpy(o).to(DEV), voxel_offset=v_off, prior_share=share, sd_scale=scale,
+                  distance="l1" if l1 else "l2",
+                  weights=None if weights is None else torch.from_numpy(weights).to(DEV))
     torch.cuda.synchronize()
     g = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()}
     n = g["n"]
@@ -212,7 +214,8 @@ def _check_is(y, ft, cp, o, n_draws, p, seed, v_off=0, share=0.0, scale=1.0):
             continue
         ov = o[v].astype(np.float64)
         order, mom, ess, d = prop.infer_is(y[v], ft, cp, H, box, ov, n_draws, p, seed, v + v_off,
-                                           prior_share=share, sd_scale=scale)
+                                           prior_share=share, sd_scale=scale, l1=l1,
+                                           weights_v=None if weights is None else weights[v])
         assert order.size == n
         gi = g["accept_idx"][v]
         a_g = set(gi[gi >= 0].tolist())
@@ -266,6 +269,15 @@ def test_is_abc_parity_ragged_and_offset():
     o = _synthetic_outputs(th, rng, spread=0.5, sd=0.8)
     _check_is(y, ft, cp, o, 3001, 0.02, 5, v_off=1000, share=0.25)  # draws not a multiple of the tile
     _check_is(y[:3], ft, cp, o[:3], 7, 0.2, 5)            # tiny: n = 1
+
+
+def test_is_abc_parity_l1_and_caller_weights():
+    rng = np.random.default_rng(23)
+    ft, cp, th, y = _tacs(24, 10)
+    o = _synthetic_outputs(th, rng, spread=0.3, sd=0.4)
+    _check_is(y, ft, cp, o, 5000, 0.01, 77, share=0.1, l1=True)
+    w = rng.uniform(0.3, 2.0, y.shape).astype(np.float32)
+    _check_is(y, ft, cp, o, 5000, 0.01, 77, share=0.1, scale=1.3, weights=w)
 
 
 def test_is_abc_full_size_sampled():
