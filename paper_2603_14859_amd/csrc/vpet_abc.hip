@@ -176,15 +176,22 @@ __device__ __forceinline__ void draw_params(const ModelDev& md, uint32_t key0, u
 // ---------------------------------------------------------------------------
 struct Exp1 {
     double z, H0, c, rc, eT;  // eT = (1 - vB) A g (coefficient of the trapezoid sum of H)
+    double rbeta;             // 1 / beta
 };
 
-// One decaying exponential exp(-beta t), amplitude A (already times 1 - vB).
-// Returns the b coefficient (times A) through *bA for the PP term.
+// One decaying exponential exp(-beta t), amplitude A (already times 1 - vB),
+// or A = amp / beta with DIV.  Returns the b coefficient (times A) through *bA
+// for the PP term.  One division serves 1/x, 1/c and 1/beta: r = 1/(x c),
+// 1/x = c r, 1/c = x r, 1/beta = h/x (x = beta h > 0 here; x = 0 gives NaN
+// reciprocals, which the guards below and the accumulating frame path never
+// use).
+template <bool DIV = false>
 __device__ __forceinline__ Exp1 exp_setup(double beta, double amp, double h, double C0, double* bA) {
     const double x = beta * h;
     const double c = -expm1(-x);
-    const double rx = 1.0 / x;
-    const double rc = 1.0 / c;
+    const double r = 1.0 / (x * c);
+    const double rx = c * r;
+    const double rc = x * r;
     // b/h: (x - c)/x^2, or its Taylor series for x < 0.01 (cancellation)
     const double bs = 0.5 + x * (-1.0 / 6.0 + x * (1.0 / 24.0 + x * (-1.0 / 120.0 + x * (1.0 / 720.0))));
     const double bd = (x - c) * rx * rx;
@@ -192,6 +199,8 @@ __device__ __forceinline__ Exp1 exp_setup(double beta, double amp, double h, dou
     const double cx = (x > 0.0) ? c * rx : 1.0;  // c / x
     const double xc = (x > 0.0) ? x * rc : 1.0;  // x / c
     Exp1 e;
+    e.rbeta = h * rx;
+    if (DIV) amp *= e.rbeta;
     e.z = 1.0 - c;
     e.c = c;
     e.rc = rc;
@@ -255,11 +264,10 @@ __device__ __forceinline__ void setup(const float* th, double h, double C0, Draw
         const double k3 = th[2], vB = th[3];
         const double w = 1.0 - vB;
         const double beta = k2 + k3;
-        const double rb = 1.0 / beta;
         double bA;
-        Exp1 e = exp_setup(beta, w * K1 * k2 * rb, h, C0, &bA);
+        Exp1 e = exp_setup<true>(beta, w * K1 * k2, h, C0, &bA);
         s.z[0][u] = e.z; s.H[0][u] = e.H0; s.c[0][u] = e.c; s.rc[0][u] = e.rc; s.eT[0][u] = e.eT;
-        s.e0[u] = w * K1 * k3 * rb;  // (1 - vB) Ki on the running integral of the input
+        s.e0[u] = w * K1 * k3 * e.rbeta;  // (1 - vB) Ki on the running integral of the input
         s.eP[u] = vB + bA;
     } else {
         const double k3 = th[2], k4 = th[3], vB = th[4];
