@@ -119,10 +119,11 @@ typedef struct {
 typedef struct {
     /* Decay constant (1/min) in the default weights; 0 -> ln 2 / 109.8 (18F). */
     double decay_lambda;
-    /* device [V][F] caller weights w_vf > 0 (inverse-variance sense); NULL ->
-     * w_vf = dt_f exp(-lambda tmid_f) / max(y_vf, floor * max_f y_vf), the
-     * inverse of the Sec. III-A1 noise variance with the unknown true curve
-     * replaced by the observation. */
+    /* device [V][F] caller weights w_vf >= 0 (inverse-variance sense); a
+     * voxel with a negative or non-finite weight is invalid (NaN outputs,
+     * like a non-finite observation).  NULL -> w_vf = dt_f exp(-lambda
+     * tmid_f) / max(y_vf, floor * max_f y_vf), the inverse of the Sec. III-A1
+     * noise variance with the unknown true curve replaced by the observation. */
     const float* weights;
     /* floor in the default weights as a fraction of max_f y_vf; 0 -> 0.01. */
     float weight_floor_frac;

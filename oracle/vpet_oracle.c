@@ -386,11 +386,15 @@ void ora_weights(const float* y, const int32_t* kf, int F, double h, double lamb
     }
 }
 
-static int voxel_valid(const float* y, int F) {
+/* Reading R10: a voxel takes part only if every y_f is finite, some y_f > 0
+ * and, when the caller supplies weights (wv != NULL), every weight is finite
+ * and >= 0. */
+static int voxel_valid(const float* y, const float* wv, int F) {
     double ymax = -INFINITY;
     for (int f = 0; f < F; ++f) {
         if (!isfinite(y[f])) return 0;
         if ((double)y[f] > ymax) ymax = (double)y[f];
+        if (wv && !(isfinite(wv[f]) && wv[f] >= 0.0f)) return 0;
     }
     return ymax > 0.0;
 }
@@ -533,7 +537,7 @@ int64_t ora_infer(const float* y, int64_t V, int F, const float* cp_f32, int K, 
         const float* yv = y + (size_t)F * v;
         double* mom = moments + (size_t)v * M * 16;
         double* pr = probs + (size_t)v * M;
-        if (!voxel_valid(yv, F)) {
+        if (!voxel_valid(yv, weights_in ? weights_in + (size_t)F * v : NULL, F)) {
             for (int j = 0; j < M * 16; ++j) mom[j] = NAN;
             for (int m = 0; m < M; ++m) pr[m] = NAN;
             for (int64_t j = 0; j < n; ++j) {
@@ -670,7 +674,7 @@ int64_t ora_infer_bank(const float* y, int64_t V, int F, const float* cp_f32, in
         const float* yv = y + (size_t)F * v;
         double* mom = moments + (size_t)v * M * 16;
         double* pr = probs + (size_t)v * M;
-        if (!voxel_valid(yv, F)) {
+        if (!voxel_valid(yv, weights_in ? weights_in + (size_t)F * v : NULL, F)) {
             for (int j = 0; j < M * 16; ++j) mom[j] = NAN;
             for (int m = 0; m < M; ++m) pr[m] = NAN;
             for (int64_t j = 0; j < n; ++j) {

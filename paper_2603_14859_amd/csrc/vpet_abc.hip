@@ -597,16 +597,23 @@ __device__ void block_sum(double (&v)[NV], double* red, int wpv) {
 // ---------------------------------------------------------------------------
 // Sinks.
 // ---------------------------------------------------------------------------
+// X is the frame's node sum (n_f times its average).  L2: yw[f] = (s y_f,
+// s / n_f) with s = sqrt(w_f), so r = s (y - X / n_f) is one FMA and
+// d += r^2 another.  L1: yw[f] = (n_f y_f, sqrt(w_f) / n_f).
 template <int U, bool L1>
 struct DistSink {
-    const double2* yw;  // per frame: (n_f y_f, scaled weight)
+    const double2* yw;
     double d[U];
     __device__ __forceinline__ void operator()(int f, int, const double (&X)[U]) {
         const double2 q = yw[f];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const double r = q.x - X[u];
-            d[u] = L1 ? fma(q.y, fabs(r), d[u]) : fma(q.y * r, r, d[u]);
+            if (L1) {
+                d[u] = fma(q.y, fabs(q.x - X[u]), d[u]);
+            } else {
+                const double r = fma(-q.y, X[u], q.x);
+                d[u] = fma(r, r, d[u]);
+            }
         }
     }
 };
@@ -702,6 +709,10 @@ __global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
             const float yy = y[f];
             bad |= !isfinite(yy);
             ymax = fmaxf(ymax, yy);
+            if (P.weights) {  // caller weights must be finite and >= 0
+                const float wv = P.weights[(size_t)row * F + f];
+                bad |= !(wv >= 0.0f) || !isfinite(wv);
+            }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -720,8 +731,8 @@ __global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
                 const double den = yy > den_floor ? yy : den_floor;
                 w = FR[4 * f + 3] / den;
             }
-            const double W = P.l1 ? sqrt(w) / nfd : w / (nfd * nfd);
-            yw[f] = make_double2(nfd * yy, W);
+            const double sw = sqrt(w);
+            yw[f] = P.l1 ? make_double2(nfd * yy, sw / nfd) : make_double2(sw * yy, sw / nfd);
         }
         if (lane == 0) *flag = valid ? 1 : 0;
     }
@@ -976,10 +987,12 @@ __device__ __forceinline__ bool lane_curve(const BankArgs& P, long long row, dou
     for (int f = 0; f < LD; ++f) {
         double w = 0.0;
         if (f < P.F) {
-            if (P.weights)
+            if (P.weights) {  // caller weights must be finite and >= 0
                 w = (double)P.weights[(size_t)row * P.F + f];
-            else
+                bad = bad || !(w >= 0.0) || !isfinite(w);
+            } else {
                 w = OM[f] / (Y[f] > den_floor ? Y[f] : den_floor);
+            }
             if (L1) w = sqrt(w);
         }
         Wt[f] = w;
@@ -2104,6 +2117,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void v
             const float yy = y[f];
             bad |= !isfinite(yy);
             ymax = fmaxf(ymax, yy);
+            if (P.weights) {  // caller weights must be finite and >= 0
+                const float wv = P.weights[(size_t)row * F + f];
+                bad |= !(wv >= 0.0f) || !isfinite(wv);
+            }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -2122,8 +2139,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void v
                 const double den = yy > den_floor ? yy : den_floor;
                 w = FR[4 * f + 3] / den;
             }
-            const double W = P.l1 ? sqrt(w) / nfd : w / (nfd * nfd);
-            yw[f] = make_double2(nfd * yy, W);
+            const double sw = sqrt(w);
+            yw[f] = P.l1 ? make_double2(nfd * yy, sw / nfd) : make_double2(sw * yy, sw / nfd);
         }
         if (lane == 0) {
             *flag = valid ? 1 : 0;

@@ -133,7 +133,9 @@ def test_infer_bank_l1_weights_and_short_schedule():
     ft, cp, y = _inputs([1.0, 2.0, 3.0, 6.0], 70, seed=2)
     _check(y, ft, cp, [W.M_2TCM_IRR], 5000, 0.01, 4, l1=True)
     w = np.random.default_rng(3).uniform(0.3, 2.0, y.shape).astype(np.float32)
-    _check(y, ft, cp, [W.M_2TCM_IRR], 5000, 0.01, 4, weights=w)
+    w[5, 1], w[8, 3], w[11, 0] = -0.5, np.nan, 0.0  # invalid, invalid, allowed
+    g, _ = _check(y, ft, cp, [W.M_2TCM_IRR], 5000, 0.01, 4, weights=w)
+    assert np.isnan(g["moments"][[5, 8]]).all() and np.isfinite(g["moments"][11, 0, 5, 0])
 
 
 def test_infer_bank_forced_fallback_and_edges():

@@ -158,7 +158,9 @@ def test_infer_parity_l1_and_caller_weights():
     boxes = W.box_array(models)
     _check_infer(ora, y, ft, cp, models, boxes, 1000, 0.02, 5, l1=True)
     w = np.random.default_rng(2).uniform(0.2, 3.0, y.shape).astype(np.float32)
-    _check_infer(ora, y, ft, cp, models, boxes, 1000, 0.02, 5, weights=w)
+    w[3, 4], w[7, 0], w[9, 2] = -1.0, np.inf, 0.0  # invalid, invalid, allowed
+    g, _ = _check_infer(ora, y, ft, cp, models, boxes, 1000, 0.02, 5, weights=w)
+    assert np.isnan(g["moments"][[3, 7]]).all() and np.isfinite(g["moments"][9, 0, 5, 0])
 
 
 @pytest.mark.parametrize("n_draws,p", [(1, 1.0), (77, 0.05), (1000, 1.0), (1984, 1.0), (333, 0.003)])

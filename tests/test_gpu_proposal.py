@@ -209,7 +209,8 @@ def _check_is(y, ft, cp, o, n_draws, p, seed, v_off=0, share=0.0, scale=1.0, l1=
     n = g["n"]
     swaps = 0
     for v in range(y.shape[0]):
-        if not np.isfinite(y[v]).all() or not (np.max(y[v]) > 0):  # no valid observation
+        bad_w = weights is not None and not (np.isfinite(weights[v]).all() and (weights[v] >= 0).all())
+        if not np.isfinite(y[v]).all() or not (np.max(y[v]) > 0) or bad_w:  # no valid observation
             assert np.isnan(g["moments"][v]).all() and np.isnan(g["ess"][v]) and (g["accept_idx"][v] == -1).all()
             continue
         ov = o[v].astype(np.float64)
@@ -277,7 +278,9 @@ def test_is_abc_parity_l1_and_caller_weights():
     o = _synthetic_outputs(th, rng, spread=0.3, sd=0.4)
     _check_is(y, ft, cp, o, 5000, 0.01, 77, share=0.1, l1=True)
     w = rng.uniform(0.3, 2.0, y.shape).astype(np.float32)
-    _check_is(y, ft, cp, o, 5000, 0.01, 77, share=0.1, scale=1.3, weights=w)
+    w[2, 3], w[4, 0] = -1.0, 0.0  # invalid voxel; a zero weight is allowed
+    g = _check_is(y, ft, cp, o, 5000, 0.01, 77, share=0.1, scale=1.3, weights=w)
+    assert np.isnan(g["moments"][2]).all() and np.isfinite(g["moments"][4, 0, 5, 0])
 
 
 def test_is_abc_full_size_sampled():

@@ -321,3 +321,26 @@ def test_bank_linear_target_interval(ora):
         tol = 1e-6 * (hi - lo)   # the edges carry the cancellation of C - B^2/A
         assert acc.min() >= lo - tol and acc.max() <= hi + tol
         assert res["n"] - 2 <= np.sum((k1 > lo + tol) & (k1 < hi - tol)) <= res["n"]
+
+
+def test_bad_caller_weights_invalidate_the_voxel(ora):
+    """Reading R10: a negative or non-finite caller weight makes the voxel
+    invalid (NaN outputs, nothing accepted); a zero weight is allowed."""
+    ft, cp = _setup()
+    models = np.array([W.M_2TCM_IRR], dtype=np.uint32)
+    boxes = W.box_array(list(models))
+    y = _observed(ora, W.M_2TCM_IRR, W.CFG_SMALL.truth(7)[0][:5], ft, cp)
+    w = np.stack([ora.weights(yv, ft, H, cp.size) for yv in y]).astype(np.float32)
+    w[1, 3] = -0.5
+    w[2, 0] = np.inf
+    w[3, 5] = 0.0
+    res = ora.infer(y, ft, cp, H, models, boxes, 500, 0.02, 9, weights=w)
+    for v in (1, 2):
+        assert np.isnan(res["moments"][v]).all() and np.isnan(res["model_prob"][v]).all()
+        assert (res["accept_idx"][v] == -1).all()
+    for v in (0, 3, 4):
+        assert np.isfinite(res["moments"][v, 0, [0, 1, 2, 4, 5], 0]).all()
+    rb = ora.infer_bank(y, ft, cp, H, list(models), boxes, 500, 0.02, 9, weights=w)
+    for v in (1, 2):
+        assert np.isnan(rb["moments"][v]).all() and (rb["accept_idx"][v] == -1).all()
+    assert np.isfinite(rb["moments"][3, 0, 5, 0])
