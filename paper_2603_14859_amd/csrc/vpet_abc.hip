@@ -298,14 +298,17 @@ __device__ __forceinline__ void run_frames(const Tab& T, int F, int k0, DrawStat
     const cdp C = (cdp)T.C;
     const cdp FR = (cdp)T.fr;
     const cip NF = (cip)T.nf;
-    double H[NE][U], Ha[NE][U], acc[NE][U], eD[NE][U], eA[NE][U], eR[U];
+    // Two register sets for H: a frame's first step reads the set holding H at
+    // the frame start and writes the other, so the start value survives the
+    // frame without a copy; consecutive frames alternate the roles.
+    double HA[NE][U], HB[NE][U], acc[NE][U], eD[NE][U], eA[NE][U], eR[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         eR[u] = 0.0;
 #pragma unroll
         for (int j = 0; j < NE; ++j) {
             const bool accj = (j == 0) ? ACC0 : ACC1;
-            H[j][u] = s.H[j][u];
+            HA[j][u] = s.H[j][u];
             acc[j][u] = 0.0;
             if (accj) {  // T = acc - D/2
                 eA[j][u] = s.eT[j][u];
@@ -317,7 +320,7 @@ __device__ __forceinline__ void run_frames(const Tab& T, int F, int k0, DrawStat
             }
         }
     }
-#define VPET_STEP(cval)                                                  \
+#define VPET_STEP(H, cval)                                               \
     do {                                                                 \
         const double cc_ = (cval);                                       \
         _Pragma("unroll") for (int u = 0; u < U; ++u) {                  \
@@ -330,30 +333,40 @@ __device__ __forceinline__ void run_frames(const Tab& T, int F, int k0, DrawStat
     } while (0)
 
     int k = 0;
-    for (; k < k0; ++k) VPET_STEP(C[k]);
+    for (; k < k0; ++k) VPET_STEP(HA, C[k]);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int j = 0; j < NE; ++j) {
-            Ha[j][u] = H[j][u];
-            acc[j][u] = 0.0;  // the steps before the first frame are not part of any frame sum
-        }
+        for (int j = 0; j < NE; ++j) acc[j][u] = 0.0;  // the steps before the first frame are not part of any frame sum
 
-    for (int f = 0; f < F; ++f) {
+    // One frame: Hs holds H at the frame start and keeps it; Hd ends holding H
+    // at the frame end (every frame has at least one step).
+    auto frame = [&](int f, double (&Hs)[NE][U], double (&Hd)[NE][U]) {
         const int n = NF[f];
         const cdp Cp = C + k;
-        int q = 0;
+        {
+            const double c0 = Cp[0];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < NE; ++j) {
+                    const bool accj = (j == 0) ? ACC0 : ACC1;
+                    if (accj) acc[j][u] += Hs[j][u];
+                    Hd[j][u] = fma(s.z[j][u], Hs[j][u], c0);
+                }
+        }
+        int q = 1;
 #if VPET_STEP_UNROLL == 4
         for (; q + 4 <= n; q += 4) {
             const double c0 = Cp[q], c1 = Cp[q + 1], c2 = Cp[q + 2], c3 = Cp[q + 3];
-            VPET_STEP(c0);
-            VPET_STEP(c1);
-            VPET_STEP(c2);
-            VPET_STEP(c3);
+            VPET_STEP(Hd, c0);
+            VPET_STEP(Hd, c1);
+            VPET_STEP(Hd, c2);
+            VPET_STEP(Hd, c3);
         }
 #endif
 #pragma nounroll
-        for (; q < n; ++q) VPET_STEP(Cp[q]);
+        for (; q < n; ++q) VPET_STEP(Hd, Cp[q]);
         k += n;
         const double SS = FR[4 * f], PP = FR[4 * f + 1], R = FR[4 * f + 2];
         double X[U];
@@ -365,17 +378,22 @@ __device__ __forceinline__ void run_frames(const Tab& T, int F, int k0, DrawStat
 #pragma unroll
             for (int j = 0; j < NE; ++j) {
                 const bool accj = (j == 0) ? ACC0 : ACC1;
-                x = fma(eD[j][u], Ha[j][u] - H[j][u], x);
+                x = fma(eD[j][u], Hs[j][u] - Hd[j][u], x);
                 if (accj) {
                     x = fma(eA[j][u], acc[j][u], x);
                     acc[j][u] = 0.0;
                 }
-                Ha[j][u] = H[j][u];
             }
             X[u] = x;
         }
         sink(f, n, X);
+    };
+    int f = 0;
+    for (; f + 2 <= F; f += 2) {
+        frame(f, HA, HB);
+        frame(f + 1, HB, HA);
     }
+    if (f < F) frame(f, HA, HB);
 #undef VPET_STEP
 }
 
@@ -684,7 +702,7 @@ __device__ __forceinline__ bool slot_used(int kind, int q) {
 // KINDS: the one model kind of a single-model call (a smaller kernel with
 // fewer live registers), or 0 for any mix of models.
 template <int KINDS, bool L1>
-__global__ __launch_bounds__(256) void vpet_infer_kernel(InferArgs P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void vpet_infer_kernel(InferArgs P) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long row = blockIdx.x;
