@@ -11,6 +11,13 @@
  * means and variances and model probabilities (Eq. (6); Sec. II-D3; Ki per
  * accepted sample as in Sec. III-B2).
  *
+ * Entry points: vpet_abc_infer (the whole path, independent draws per voxel),
+ * vpet_abc_simulate and vpet_abc_draws (single steps, for checking),
+ * vpet_abc_bank_build + vpet_abc_infer_bank (Alg. 1 with one bank of draws
+ * shared by every voxel), vpet_abc_stream_bank (the bank form over a volume in
+ * a file), and the learned proposal vpet_proposal_* (not in the paper) whose
+ * outputs drive importance-weighted draws in vpet_abc_infer.
+ *
  * Conventions shared by every entry point
  *  - Every function returns a vpet_status and never throws or aborts.  On a
  *    status other than VPET_OK, vpet_abc_last_error() returns a message for the
