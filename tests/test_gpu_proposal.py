@@ -141,6 +141,42 @@ def test_forward_parity(n, sched):
     assert np.array_equal(g[:, prop.NOUT:], np.zeros((n, 96 - prop.NOUT)))  # zero padding weights
 
 
+def test_forward_parity_across_row_chunks():
+    """The forward pass runs in chunks of 2^17 rows: rows on both sides of the
+    chunk boundaries of a 2^18 + 333-row batch match the oracle."""
+    p = _params(8)
+    n_s = 64
+    ft, cp, _, y_s = _tacs(n_s, 13)
+    n = (1 << 18) + 333
+    idx = np.concatenate([np.arange(8), (1 << 17) - 8 + np.arange(16), (1 << 18) - 8 + np.arange(16),
+                          n - 8 + np.arange(8)])
+    y = np.tile(y_s, (n // n_s + 1, 1))[:n]
+    out = V.proposal_forward(torch.from_numpy(pack(p)).to(DEV), torch.from_numpy(y).to(DEV))
+    torch.cuda.synchronize()
+    g = out[torch.from_numpy(idx).to(DEV)].cpu().numpy().astype(np.float64)
+    x = prop.features(y[idx])
+    o, _ = prop.forward(p, x)
+    sig = forward_sigma(p, x)
+    assert np.all(np.abs(g[:, :prop.NOUT] - o) <= 6.0 * sig + 1e-6 * (1.0 + np.abs(o)))
+
+
+def test_training_is_deterministic():
+    """Same seeds, same weights bit for bit (no atomics feed the gradients)."""
+    ft, cp, _, _ = _tacs(1, 1)
+    th_b, x_b = V.bank_build([IRR], W.box_array([IRR]), 20_000, 3, cp, ft, H)
+    runs = []
+    for _ in range(2):
+        p = V.proposal_init(11)
+        V.proposal_train(p, th_b, x_b, ft, steps=40, batch=1000, lr=1e-3, noise_level=0.05,
+                         decay_lambda=W.LAMBDA_F18, seed=4)
+        runs.append(p.cpu().numpy())
+    assert np.array_equal(runs[0].view(np.uint32), runs[1].view(np.uint32))
+    p = V.proposal_init(11)
+    V.proposal_train(p, th_b, x_b, ft, steps=40, batch=1000, lr=1e-3, noise_level=0.05,
+                     decay_lambda=W.LAMBDA_F18, seed=5)
+    assert not np.array_equal(runs[0], p.cpu().numpy())  # the noise seed matters
+
+
 @pytest.mark.parametrize("targets", ["truth", "model"])
 def test_loss_and_gradient_parity(targets):
     """Targets: the TACs' true parameters under an untrained network (a large
