@@ -418,12 +418,39 @@ def learned_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, cpu: bool, bud
         m_plain = r100["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
         del r100
     sub = 65536
+    y_sub = y[:sub].contiguous()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r1m = V.infer(y[:sub].contiguous(), ft, cp, cfg.dt, [IRR], box, 1_000_000, n_acc / 1_000_000, cfg.infer_seed)
+    r1m = V.infer(y_sub, ft, cp, cfg.dt, [IRR], box, 1_000_000, n_acc / 1_000_000, cfg.infer_seed)
     torch.cuda.synchronize()
     t1m = time.perf_counter() - t0
     m1m = r1m["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
+    del r1m
+
+    # equal-error sweep on the subset: plain ABC at 100k and 1M prior draws
+    # against the learned proposal at a range of draw counts (network forward
+    # pass included), n = 100 accepted throughout
+    def timed(n_draws, proposal):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        kw = {}
+        if proposal:
+            kw = dict(proposal=V.proposal_forward(params, y_sub), prior_share=share, sd_scale=scale)
+        r = V.infer(y_sub, ft, cp, cfg.dt, [IRR], box, n_draws, n_acc / n_draws, cfg.infer_seed, **kw)
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t
+        m = r["moments"][:, 0, 5, 0].cpu().numpy().astype(np.float64)
+        return {"draws": n_draws, "ki_rmse": float(math.sqrt(np.nanmean((m - ki[:sub]) ** 2))),
+                "voxels_per_s": sub / dt_}
+    timed(2500, True)  # warm-up of the subset shapes
+    plain_pts = [timed(100_000, False), {"draws": 1_000_000, "ki_rmse": None, "voxels_per_s": sub / t1m}]
+    plain_pts[1]["ki_rmse"] = float(math.sqrt(np.nanmean((m1m[:, 0] - ki[:sub]) ** 2)))
+    learned_pts = [timed(nd, True) for nd in (2500, 5000, 10_000, 20_000)]
+    equal_error = {"subset_voxels": sub, "plain": plain_pts, "learned": learned_pts}
+    for pp in plain_pts:  # the fewest learned draws at or below this plain error, and the throughput ratio
+        ok = [q for q in learned_pts if q["ki_rmse"] <= pp["ki_rmse"]]
+        key = f"speedup_at_plain_{pp['draws'] // 1000}k_error"
+        equal_error[key] = (round(ok[0]["voxels_per_s"] / pp["voxels_per_s"], 2) if ok else None)
 
     def rmse(m, n=nv):
         return float(math.sqrt(np.nanmean((m[:n, 0] - ki[:n]) ** 2)))
@@ -449,7 +476,8 @@ def learned_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, cpu: bool, bud
                "ki_rmse_plain_1M_subset": rmse(m1m, sub), "plain_1M_voxels_per_s": sub / t1m,
                "median_ess": float(np.nanmedian(ess)),
                "frac_within_3_mc_se_of_plain_1M": agree(m_is, ess[:sub]),
-               "frac_within_3_mc_se_of_plain_1M_plain_100k": agree(m_plain, float(n_acc))}}
+               "frac_within_3_mc_se_of_plain_1M_plain_100k": agree(m_plain, float(n_acc))},
+           "equal_error": equal_error}
     if cpu:
         import oracle.proposal as prop
         rng = np.random.default_rng(0)
@@ -498,7 +526,8 @@ def main_learned(args, dev):
                    "simulations of the same forward model",
            "config": {"workload": cfg.name + "-learned-proposal", "frames": ft.size - 1, "minutes": float(ft[-1]),
                       "grid_dt_min": cfg.dt, **lf["config"], "parallelism": "single GPU"},
-           "roofline": lf["roofline"], "training": lf["training"], "comparison": lf["comparison"]}
+           "roofline": lf["roofline"], "training": lf["training"], "comparison": lf["comparison"],
+           "equal_error": lf["equal_error"]}
     if "cpu_baseline" in lf:
         out["cpu_baseline"] = lf["cpu_baseline"]
     print(json.dumps(out), flush=True)
