@@ -119,9 +119,15 @@ def cpu_baseline(cfg, ft, cp, y, y_dev, budget_s: float):
         "max_rel_err_moments_all": float(rel.max()) if rel.size else None,
         "max_abs_err_model_prob": float(np.abs(g_prob - ref["model_prob"]).max()),
     }
+    # the same oracle on one thread, over a few voxels
+    n1 = max(1, min(nv, int(budget_s / 8 / max(per_vox * threads, 1e-9))))
+    t0 = time.perf_counter()
+    oracle.infer(y[:n1], ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed, nthreads=1)
+    dt1 = time.perf_counter() - t0
     base = {"value": nv / dt, "unit": "voxels/s", "cores": threads, "kind": "oracle",
             "sample": f"first {nv} voxels of the same volume, all {cfg.n_draws} draws each, FP64, "
-                      f"OpenMP over voxels ({dt:.1f} s)"}
+                      f"OpenMP over voxels ({dt:.1f} s)",
+            "value_1_thread": n1 / dt1, "sample_1_thread": f"first {n1} voxels, one thread ({dt1:.1f} s)"}
     return base, err
 
 
