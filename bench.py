@@ -320,6 +320,21 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     kernel_ms = float(np.mean(launch_ms))
 
+    # once more end to end: the TACs from pinned host memory to the device, the
+    # call, the outputs back to pinned host memory (not the line's value)
+    y_pin = torch.from_numpy(y_host).pin_memory()
+    outs = {k: v for k, v in res.items() if torch.is_tensor(v)}
+    out_pin = {k: torch.empty(v.shape, dtype=v.dtype).pin_memory() for k, v in outs.items()}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y_e2e = y_pin.to(dev, non_blocking=True)
+    V.infer(y_e2e, ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed, out=res)
+    for k, v in outs.items():
+        out_pin[k].copy_(v, non_blocking=True)
+    torch.cuda.synchronize()
+    e2e_s = time.perf_counter() - t0
+    del y_e2e, y_pin, out_pin
+
     fl = flops_per_draw(n_steps, F) * cfg.n_voxels * cfg.n_draws * len(models)
     achieved = fl / (kernel_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_F64_VECTOR_TFLOPS,
@@ -336,7 +351,9 @@ def main():
                       "grid_dt_min": cfg.dt, "draws_per_voxel": cfg.n_draws, "accept_frac": cfg.accept_frac,
                       "n_accept": V.accept_count(M * cfg.n_draws, cfg.accept_frac), "models": ["2TCM-irreversible"], "draws": "per-voxel Philox4x32-10",
                       "parallelism": "single GPU"},
-           "roofline": roofline}
+           "roofline": roofline,
+           "end_to_end_voxels_per_s": cfg.n_voxels / e2e_s,
+           "end_to_end_note": "TACs host->device, the call, outputs device->host (pinned host memory), one run"}
     if not args.no_cpu_baseline:
         base, err = cpu_baseline(cfg, ft, cp, y_host, y, args.cpu_budget)
         out["cpu_baseline"] = base
