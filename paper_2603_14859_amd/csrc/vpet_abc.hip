@@ -1735,6 +1735,12 @@ struct GemmArgs {
     const float* mask;
     long long ldm;
     int M, N, K, relu, accumulate;
+    // split K: block z sums k in [z kchunk, (z+1) kchunk) and, with part set,
+    // stores its raw partial tile at part + z pstride ([M][N]); a second
+    // kernel adds the partials in order and applies the epilogue
+    int kchunk;
+    float* part;
+    long long pstride;
 };
 
 // Split of 8 fp32 values into bf16 hi = rn(x) and lo = rn(x - hi), packed.
@@ -1758,14 +1764,15 @@ __global__ __launch_bounds__(256) void vpet_gemm_bf16x3_kernel(GemmArgs G) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m0 = blockIdx.y * 64 + (wave >> 1) * 32, n0 = blockIdx.x * 64 + (wave & 1) * 32;
     const int am = m0 + (lane & 31), bn = n0 + (lane & 31), kk = 8 * (lane >> 5);
+    const int kbeg = blockIdx.z * G.kchunk, kend = min(G.K, kbeg + G.kchunk);
     f32x16_t acc = {};
-    for (int k0 = 0; k0 < G.K; k0 += 16) {
+    for (int k0 = kbeg; k0 < kend; k0 += 16) {
         float a[8], b[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = k0 + kk + e;
-            a[e] = (am < G.M && k < G.K) ? G.A[am * G.sam + k * G.sak] : 0.0f;
-            b[e] = (bn < G.N && k < G.K) ? G.B[k * G.sbk + bn * G.sbn] : 0.0f;
+            a[e] = (am < G.M && k < kend) ? G.A[am * G.sam + (long long)k * G.sak] : 0.0f;
+            b[e] = (bn < G.N && k < kend) ? G.B[(long long)k * G.sbk + bn * G.sbn] : 0.0f;
         }
         uint4 ah, al, bh, bl;
         split_bf16x8(a, ah, al);
@@ -1781,12 +1788,30 @@ __global__ __launch_bounds__(256) void vpet_gemm_bf16x3_kernel(GemmArgs G) {
         const int m = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), n = n0 + (lane & 31);
         if (m >= G.M || n >= G.N) continue;
         float v = acc[r];
+        if (G.part) {
+            G.part[blockIdx.z * G.pstride + (long long)m * G.N + n] = v;
+            continue;
+        }
         if (G.bias) v += G.bias[n];
         if (G.relu) v = fmaxf(v, 0.0f);
         if (G.mask && !(G.mask[(long long)m * G.ldm + n] > 0.0f)) v = 0.0f;
         float* c = G.C + (long long)m * G.ldc + n;
         *c = G.accumulate ? *c + v : v;
     }
+}
+
+// C = epilogue(sum over the S split-K partials, in order): bias, relu, mask.
+__global__ __launch_bounds__(256) void vpet_gemm_reduce_kernel(GemmArgs G, int S) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long long)G.M * G.N) return;
+    const int m = (int)(e / G.N), n = (int)(e - (long long)m * G.N);
+    float v = 0.0f;
+    for (int z = 0; z < S; ++z) v += G.part[z * G.pstride + e];
+    if (G.bias) v += G.bias[n];
+    if (G.relu) v = fmaxf(v, 0.0f);
+    if (G.mask && !(G.mask[(long long)m * G.ldm + n] > 0.0f)) v = 0.0f;
+    float* c = G.C + (long long)m * G.ldc + n;
+    *c = G.accumulate ? *c + v : v;
 }
 
 // db[n] = sum_m dY[m][n] (one block per column).
@@ -3368,11 +3393,15 @@ __global__ __launch_bounds__(256) void vpet_net_targets_kernel(const float* thet
 // Activations of one batch of up to `rows` samples.
 struct NetWork {
     float *X, *H1, *H2, *O, *dO, *dH1, *dH2, *Z;
+    float* part;  // split-K partials: kSplitMax tiles of at most kNetH x kNetH
     long long rows;
 };
 
+constexpr int kSplitMax = 16;
+
 size_t net_work_bytes(long long rows) {
-    return sizeof(float) * (size_t)rows * (kNetIn + 4 * kNetH + 2 * kNetOut + kMixD) + 8 * 256;
+    return sizeof(float) * ((size_t)rows * (kNetIn + 4 * kNetH + 2 * kNetOut + kMixD) +
+                            (size_t)kSplitMax * kNetH * kNetH) + 9 * 256;
 }
 
 void net_work_carve(char* base, long long rows, NetWork& w) {
@@ -3390,31 +3419,51 @@ void net_work_carve(char* base, long long rows, NetWork& w) {
     w.O = take((size_t)rows * kNetOut);
     w.dO = take((size_t)rows * kNetOut);
     w.Z = take((size_t)rows * kMixD);
+    w.part = take((size_t)kSplitMax * kNetH * kNetH);
 }
 
+// A product with few output tiles and a long K (the weight gradients: K =
+// batch rows) is split along K over up to kSplitMax blocks per tile, so that
+// the launch fills the chip; the partials are added in a fixed order, which
+// keeps the result deterministic.
 void gemm(hipStream_t st, const float* A, long long sam, long long sak, const float* B, long long sbk, long long sbn,
-          float* C, long long ldc, int M, int N, int K, const float* bias, int relu, const float* mask, long long ldm) {
-    GemmArgs G{A, sam, sak, B, sbk, sbn, C, ldc, bias, mask, ldm, M, N, K, relu, 0};
-    hipLaunchKernelGGL(vpet_gemm_bf16x3_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64)), dim3(256),
-                       0, st, G);
+          float* C, long long ldc, int M, int N, int K, const float* bias, int relu, const float* mask, long long ldm,
+          float* part) {
+    GemmArgs G{A, sam, sak, B, sbk, sbn, C, ldc, bias, mask, ldm, M, N, K, relu, 0, K, nullptr, 0};
+    const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
+    int S = 1;
+    if (part && tiles < 128 && K >= 512 && (long long)M * N <= (long long)kNetH * kNetH) {
+        S = std::min(std::min(kSplitMax, (256 + tiles - 1) / tiles), K / 256);
+        G.kchunk = ((K + S - 1) / S + 15) & ~15;
+        S = (K + G.kchunk - 1) / G.kchunk;
+    }
+    if (S > 1) {
+        G.part = part;
+        G.pstride = (long long)M * N;
+    }
+    hipLaunchKernelGGL(vpet_gemm_bf16x3_kernel, dim3((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)S),
+                       dim3(256), 0, st, G);
+    if (S > 1)
+        hipLaunchKernelGGL(vpet_gemm_reduce_kernel, dim3((unsigned)(((long long)M * N + 255) / 256)), dim3(256), 0, st,
+                           G, S);
 }
 
 // H1 = relu(X W1 + b1), H2 = relu(H1 W2 + b2), O = H2 W3 + b3 for n rows of X.
 void net_forward(hipStream_t st, const float* p, const NetWork& w, int n) {
-    gemm(st, w.X, kNetIn, 1, p + kOffW1, kNetH, 1, w.H1, kNetH, n, kNetH, kNetIn, p + kOffB1, 1, nullptr, 0);
-    gemm(st, w.H1, kNetH, 1, p + kOffW2, kNetH, 1, w.H2, kNetH, n, kNetH, kNetH, p + kOffB2, 1, nullptr, 0);
-    gemm(st, w.H2, kNetH, 1, p + kOffW3, kNetOut, 1, w.O, kNetOut, n, kNetOut, kNetH, p + kOffB3, 0, nullptr, 0);
+    gemm(st, w.X, kNetIn, 1, p + kOffW1, kNetH, 1, w.H1, kNetH, n, kNetH, kNetIn, p + kOffB1, 1, nullptr, 0, w.part);
+    gemm(st, w.H1, kNetH, 1, p + kOffW2, kNetH, 1, w.H2, kNetH, n, kNetH, kNetH, p + kOffB2, 1, nullptr, 0, w.part);
+    gemm(st, w.H2, kNetH, 1, p + kOffW3, kNetOut, 1, w.O, kNetOut, n, kNetOut, kNetH, p + kOffB3, 0, nullptr, 0, w.part);
 }
 
 // Gradients of the mean negative log density into g (overwritten), given dO.
 void net_backward(hipStream_t st, const float* p, const NetWork& w, int n, float* g) {
-    gemm(st, w.H2, 1, kNetH, w.dO, kNetOut, 1, g + kOffW3, kNetOut, kNetH, kNetOut, n, nullptr, 0, nullptr, 0);
+    gemm(st, w.H2, 1, kNetH, w.dO, kNetOut, 1, g + kOffW3, kNetOut, kNetH, kNetOut, n, nullptr, 0, nullptr, 0, w.part);
     hipLaunchKernelGGL(vpet_colsum_kernel, dim3(kNetOut), dim3(256), 0, st, w.dO, (long long)kNetOut, n, g + kOffB3);
-    gemm(st, w.dO, kNetOut, 1, p + kOffW3, 1, kNetOut, w.dH2, kNetH, n, kNetH, kNetOut, nullptr, 0, w.H2, kNetH);
-    gemm(st, w.H1, 1, kNetH, w.dH2, kNetH, 1, g + kOffW2, kNetH, kNetH, kNetH, n, nullptr, 0, nullptr, 0);
+    gemm(st, w.dO, kNetOut, 1, p + kOffW3, 1, kNetOut, w.dH2, kNetH, n, kNetH, kNetOut, nullptr, 0, w.H2, kNetH, w.part);
+    gemm(st, w.H1, 1, kNetH, w.dH2, kNetH, 1, g + kOffW2, kNetH, kNetH, kNetH, n, nullptr, 0, nullptr, 0, w.part);
     hipLaunchKernelGGL(vpet_colsum_kernel, dim3(kNetH), dim3(256), 0, st, w.dH2, (long long)kNetH, n, g + kOffB2);
-    gemm(st, w.dH2, kNetH, 1, p + kOffW2, 1, kNetH, w.dH1, kNetH, n, kNetH, kNetH, nullptr, 0, w.H1, kNetH);
-    gemm(st, w.X, 1, kNetIn, w.dH1, kNetH, 1, g + kOffW1, kNetH, kNetIn, kNetH, n, nullptr, 0, nullptr, 0);
+    gemm(st, w.dH2, kNetH, 1, p + kOffW2, 1, kNetH, w.dH1, kNetH, n, kNetH, kNetH, nullptr, 0, w.H1, kNetH, w.part);
+    gemm(st, w.X, 1, kNetIn, w.dH1, kNetH, 1, g + kOffW1, kNetH, kNetIn, kNetH, n, nullptr, 0, nullptr, 0, w.part);
     hipLaunchKernelGGL(vpet_colsum_kernel, dim3(kNetH), dim3(256), 0, st, w.dH1, (long long)kNetH, n, g + kOffB1);
 }
 

@@ -177,12 +177,12 @@ def test_training_is_deterministic():
     assert not np.array_equal(runs[0], p.cpu().numpy())  # the noise seed matters
 
 
-@pytest.mark.parametrize("targets", ["truth", "model"])
-def test_loss_and_gradient_parity(targets):
+@pytest.mark.parametrize("targets,n", [("truth", 333), ("model", 333), ("model", 2048)])
+def test_loss_and_gradient_parity(targets, n):
     """Targets: the TACs' true parameters under an untrained network (a large
     loss), or draws near the most likely component of a network whose sds
-    are near 0.2 (a loss of the size reached in training)."""
-    n = 333
+    are near 0.2 (a loss of the size reached in training).  2048 rows: the
+    weight-gradient products run split along the rows (split-K)."""
     ft, cp, th, y = _tacs(n, 5)
     th32 = np.zeros((n, V.PSTRIDE), dtype=np.float32)
     th32[:, :th.shape[1]] = th
