@@ -392,8 +392,10 @@ int vpet_proposal_loss_grad(const float* params, const float* tacs, const float*
  * noise_level e^{decay_lambda tmid_f} max(x_f, 0) / dt_f to each frame
  * (Sec. III-A1 noise; Philox stream 4 keyed by seed); frame_times is host
  * [n_frames + 1].  out_loss (host, optional, [steps]) receives each step's
- * batch loss, which makes the call synchronous.  Scratch (Adam moments and
- * one batch of activations) is allocated and freed in stream order.
+ * batch loss, which makes the call synchronous.  Scratch (Adam moments, one
+ * batch of activations and the partial sums of the weight-gradient products,
+ * which are split over the batch rows and added in a fixed order, so training
+ * is deterministic) is allocated and freed in stream order.
  * Errors: VPET_E_ARG, VPET_E_GRID (frame bounds), VPET_E_LIMIT, VPET_E_NOMEM,
  * VPET_E_HIP. */
 int vpet_proposal_train(float* params, const float* bank_theta, const double* bank_x, int64_t n_bank,
