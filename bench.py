@@ -394,7 +394,7 @@ def learned_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, cpu: bool, bud
     F = ft.size - 1
     n_steps = int(round(float(ft[-1] - ft[0]) / np.float32(cfg.dt)))
     n_is, n_acc, share, scale = 20_000, 100, 0.1, 1.5
-    train = {"bank_draws": 1_000_000, "steps": 5000, "batch": 2048, "lr": 1e-3, "noise_level": 0.05}
+    train = {"bank_draws": 1_000_000, "steps": 5000, "batch": 2048, "lr": 5e-4, "noise_level": 0.05}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     thb, xb = V.bank_build([IRR], box, train["bank_draws"], 17, cp, ft, cfg.dt)

@@ -382,7 +382,7 @@ def proposal_loss_grad(params, tacs, theta, stream=None):
     return loss, g
 
 
-def proposal_train(params, bank_theta, bank_x, frame_times, *, steps: int, batch: int = 4096, lr: float = 1e-3,
+def proposal_train(params, bank_theta, bank_x, frame_times, *, steps: int, batch: int = 4096, lr: float = 5e-4,
                    noise_level: float = 0.1, decay_lambda: float = 0.0, seed: int = 0, stream=None):
     """Adam steps on params (in place) over a shared irreversible-2TCM bank;
     returns the per-step batch losses (numpy, waits for the stream)."""

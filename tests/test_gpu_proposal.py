@@ -400,7 +400,7 @@ def test_training_lowers_held_out_loss_and_beats_prior_draws():
     th32[:, :th_t.shape[1]] = th_t
     y_d, th_d = torch.from_numpy(y).to(DEV), torch.from_numpy(th32).to(DEV)
     l0 = float(V.proposal_loss_grad(p, y_d, th_d)[0].item())
-    losses = V.proposal_train(p, th_b, x_b, ft, steps=5000, batch=2048, lr=1e-3, noise_level=0.05,
+    losses = V.proposal_train(p, th_b, x_b, ft, steps=5000, batch=2048, lr=5e-4, noise_level=0.05,
                               decay_lambda=W.LAMBDA_F18, seed=9)
     l1 = float(V.proposal_loss_grad(p, y_d, th_d)[0].item())
     print(f"[proposal train] batch loss {losses[:50].mean():.3f} -> {losses[-50:].mean():.3f}; "
