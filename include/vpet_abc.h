@@ -174,11 +174,15 @@ typedef struct {
     int64_t* out_fallback_voxels;
     /* vpet_abc_infer only: device [n_voxels][VPET_PROPOSAL_NOUT] outputs of the
      * learned proposal network (vpet_proposal_forward) for each voxel.  When
-     * set, the n_draws draws of each voxel come from its mixture (Philox
-     * stream 2) instead of the prior, draws outside the prior box are
-     * discarded, and the moments are weighted by prior / proposal
-     * (importance-weighted ABC: the target is unchanged).  The irreversible
-     * 2TCM alone (VPET_E_MODEL otherwise); model probability 1. */
+     * set, the n_draws draws of each voxel come from its mixture instead of
+     * the prior, draws outside the prior box are discarded, and the moments
+     * are weighted by prior / proposal (importance-weighted ABC: the target is
+     * unchanged).  Draw i of voxel v takes one Philox4x32-10 block, counter
+     * (i, v, 2, 0), the seed as key: u0 = ((w0 & 255) | (w1 & 255) << 8 |
+     * (w2 & 255) << 16) 2^-24 chooses the prior (u0 < share) or a mixture
+     * component, and u_j = (w_j >> 8) 2^-24 (j = 0..3) give either the
+     * uniform box draw or two Box-Muller pairs.  The irreversible 2TCM alone
+     * (VPET_E_MODEL otherwise); model probability 1. */
     const float* proposal;
     /* device [n_voxels]: effective sample size (sum w)^2 / sum w^2 of each
      * voxel's accepted weights; needs proposal. */
