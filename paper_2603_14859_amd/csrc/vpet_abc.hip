@@ -581,6 +581,34 @@ __device__ void block_bitonic_sort(uint64_t* a, int len) {
     }
 }
 
+// The block's n smallest keys after every wavefront has merged its own list
+// (wave w's n best, sorted, at keys_all[w cap ..]): they are among the waves'
+// first n keys, so for a small n those are gathered into wpv pow2(n)
+// consecutive slots (padded with kNoKey) and only they are sorted; the result
+// is keys_all[0, n) ascending either way.
+__device__ void block_topn_sort(uint64_t* keys_all, int wpv, int cap, int n) {
+    const int np2 = n <= 1 ? 1 : (1 << (32 - __builtin_clz((unsigned)(n - 1))));
+    if (np2 >= cap || n > 4 * kWave) {
+        block_bitonic_sort(keys_all, wpv * cap);
+        return;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = lane + kWave * q;
+        r[q] = j < n ? keys_all[(size_t)wave * cap + j] : kNoKey;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = lane + kWave * q;
+        if (j < np2) keys_all[(size_t)wave * np2 + j] = r[q];
+    }
+    __syncthreads();
+    block_bitonic_sort(keys_all, wpv * np2);
+}
+
 // Running top-n of one wavefront: keys[0, n) is the sorted set (padded with
 // kNoKey), keys[n, n + nbuf) the unsorted candidates, keys[.., cap) free.
 struct TopN {
@@ -828,7 +856,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void v
     }
     top.merge();
     __syncthreads();
-    if (P.wpv > 1) block_bitonic_sort(keys_all, P.wpv * P.cap);
+    if (P.wpv > 1) block_topn_sort(keys_all, P.wpv, P.cap, n);
     const uint64_t* acc = keys_all;  // the n accepted keys, ascending
 
     if (P.out_idx)
@@ -2311,7 +2339,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void v
     }
     top.merge();
     __syncthreads();
-    if (P.wpv > 1) block_bitonic_sort(keys_all, P.wpv * P.cap);
+    if (P.wpv > 1) block_topn_sort(keys_all, P.wpv, P.cap, n);
     const uint64_t* acc = keys_all;
     if (P.out_idx)
         for (int j = tid; j < n; j += blockDim.x)

@@ -192,11 +192,14 @@ def test_infer_ties_nan_voxels_and_offsets():
     assert np.array_equal(g["accept_idx"], np.tile(np.arange(70), (2, 1)))
 
 
-def test_infer_deterministic_across_launch_shapes():
+# n = 36, then n = 256 and 257 on either side of the size up to which the
+# block merge sorts only each wavefront's first n keys
+@pytest.mark.parametrize("n_draws,p", [(900, 0.02), (1280, 0.1), (1285, 0.1)])
+def test_infer_deterministic_across_launch_shapes(n_draws, p):
     ft, cp, y = _inputs(W.SCHED_22x60, 33, seed=8)
     models = [W.M_2TCM_IRR, W.M_2TCM_REV]
     boxes = W.box_array(models)
-    outs = [_gpu_infer(y, ft, cp, models, boxes, 900, 0.02, 4, waves_per_voxel=w) for w in (1, 2, 4, 4)]
+    outs = [_gpu_infer(y, ft, cp, models, boxes, n_draws, p, 4, waves_per_voxel=w) for w in (1, 2, 4, 4)]
     for o in outs[1:]:
         for k in ("accept_idx", "accept_dist", "threshold", "moments", "model_prob"):
             assert np.array_equal(o[k], outs[0][k], equal_nan=True), k

@@ -319,6 +319,26 @@ def test_is_abc_parity_l1_and_caller_weights():
     assert np.isnan(g["moments"][2]).all() and np.isfinite(g["moments"][4, 0, 5, 0])
 
 
+# n = 30, then n = 256 and 257 on either side of the size up to which the
+# block merge sorts only each wavefront's first n keys
+@pytest.mark.parametrize("n_draws,p", [(3000, 0.01), (2560, 0.1), (2570, 0.1)])
+def test_is_abc_deterministic_across_launch_shapes(n_draws, p):
+    rng = np.random.default_rng(24)
+    ft, cp, th, y = _tacs(12, 8)
+    o = torch.from_numpy(_synthetic_outputs(th, rng)).to(DEV)
+    box, _, _ = _box_lohi()
+    outs = []
+    for w in (1, 2, 4, 4):
+        res = V.infer(torch.from_numpy(y).to(DEV), ft, cp, H, [IRR], box[None], n_draws, p, 31, debug=True,
+                      proposal=o, prior_share=0.1, sd_scale=1.2, waves_per_voxel=w)
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu().numpy() for k, v in res.items() if torch.is_tensor(v)})
+    assert outs[0]["accept_idx"].shape[1] == int(n_draws * p + 1e-6)
+    for o2 in outs[1:]:
+        for k in ("accept_idx", "accept_dist", "threshold", "moments", "model_prob", "ess"):
+            assert np.array_equal(o2[k], outs[0][k], equal_nan=True), k
+
+
 def test_is_abc_full_size_sampled():
     """1,048,576 voxels x 100,000 proposal draws (30 frames, 0.1 % accepted);
     sampled voxels against the oracle."""
