@@ -402,7 +402,7 @@ def test_training_lowers_held_out_loss_and_beats_prior_draws():
     weighted ABC with 20k draws from the trained proposal (defensive share
     0.1, sd x 1.5) reaches the Ki error of plain ABC with 1M prior draws (and
     a clearly lower one than with 100k), at a smaller ABC threshold; and plain
-    ABC judges it: against plain ABC with 1M prior draws its posterior means
+    ABC is the yardstick: against plain ABC with 1M prior draws its posterior means
     of Ki agree within 3 Monte Carlo SE for at least as many voxels as those
     of plain ABC with 100k draws do.  (Posteriors at different ABC thresholds
     differ by more than Monte Carlo error, so neither agrees for every voxel.)"""
