@@ -584,8 +584,10 @@ __device__ void block_bitonic_sort(uint64_t* a, int len) {
 // The block's n smallest keys after every wavefront has merged its own list
 // (wave w's n best, sorted, at keys_all[w cap ..]): they are among the waves'
 // first n keys, so for a small n those are gathered into wpv pow2(n)
-// consecutive slots (padded with kNoKey) and only they are sorted; the result
-// is keys_all[0, n) ascending either way.
+// consecutive slots (padded with kNoKey) and only they are ordered: by rank
+// (one key per thread, ties of the padding broken by slot) when they fit the
+// block, else by a bitonic sort.  The result is keys_all[0, n) ascending
+// either way.
 __device__ void block_topn_sort(uint64_t* keys_all, int wpv, int cap, int n) {
     const int np2 = n <= 1 ? 1 : (1 << (32 - __builtin_clz((unsigned)(n - 1))));
     if (np2 >= cap || n > 4 * kWave) {
@@ -606,7 +608,27 @@ __device__ void block_topn_sort(uint64_t* keys_all, int wpv, int cap, int n) {
         if (j < np2) keys_all[(size_t)wave * np2 + j] = r[q];
     }
     __syncthreads();
-    block_bitonic_sort(keys_all, wpv * np2);
+    const int len = wpv * np2, t = (int)threadIdx.x;
+    if (len > (int)blockDim.x) {
+        block_bitonic_sort(keys_all, len);
+        return;
+    }
+    uint64_t c = kNoKey;
+    int rank = len;
+    if (t < len) {  // len is even: two keys per 16-byte read, four reads in flight
+        const ulonglong2* k2 = reinterpret_cast<const ulonglong2*>(keys_all);
+        c = keys_all[t];
+        rank = 0;
+#pragma unroll 4
+        for (int j = 0; j < (len >> 1); ++j) {
+            const ulonglong2 o = k2[j];
+            rank += (o.x < c || (o.x == c && 2 * j < t)) ? 1 : 0;
+            rank += (o.y < c || (o.y == c && 2 * j + 1 < t)) ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    if (rank < n) keys_all[rank] = c;
+    __syncthreads();
 }
 
 // Running top-n of one wavefront: keys[0, n) is the sorted set (padded with
@@ -616,10 +638,14 @@ struct TopN {
     int n, cap, nbuf;
     uint64_t tau;
 
+    // Sorts only pow2(n + nbuf) keys: the slots above hold kNoKey or keys
+    // dropped by an earlier merge, none of which can re-enter the top n.
     __device__ void merge() {
-        for (int j = n + nbuf + lane_id(); j < cap; j += kWave) keys[j] = kNoKey;
+        const int used = n + nbuf;
+        const int len = used <= 2 ? 2 : min(cap, 1 << (32 - __builtin_clz((unsigned)(used - 1))));
+        for (int j = used + lane_id(); j < len; j += kWave) keys[j] = kNoKey;
         wave_lds_sync();
-        wave_bitonic_sort(keys, cap);
+        wave_bitonic_sort(keys, len);
         tau = keys[n - 1];
         nbuf = 0;
     }
