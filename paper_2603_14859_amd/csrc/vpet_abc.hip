@@ -192,9 +192,10 @@ struct Exp1 {
 // 1/x = c r, 1/c = x r, 1/beta = h/x (x = beta h > 0 here; x = 0 gives NaN
 // reciprocals, which the guards below and the accumulating frame path never
 // use).
-// 1 - e^{-x} for 0 <= x <= 0.3 by its Taylor series x sum_{n>=0} (-x)^n / (n+1)!
-// to n = 13 (the first omitted term is below 2e-18 relative).
-__device__ __forceinline__ double one_minus_exp_small(double x) {
+// b/h = (x - (1 - e^{-x})) / x^2 = sum_{n>=0} (-x)^n / (n+2)! for 0 <= x <= 0.3,
+// to n = 12 (the first omitted term is below 3e-19 of the sum).  Then
+// c/x = 1 - x (b/h) and c = 1 - e^{-x} = x (c/x), neither with cancellation.
+__device__ __forceinline__ double b_over_h_small(double x) {
     double p = 1.0 / 87178291200.0;  // 1/14!
     p = fma(p, -x, 1.0 / 6227020800.0);
     p = fma(p, -x, 1.0 / 479001600.0);
@@ -207,33 +208,45 @@ __device__ __forceinline__ double one_minus_exp_small(double x) {
     p = fma(p, -x, 1.0 / 120.0);
     p = fma(p, -x, 1.0 / 24.0);
     p = fma(p, -x, 1.0 / 6.0);
-    p = fma(p, -x, 0.5);
-    p = fma(p, -x, 1.0);
-    return x * p;
+    return fma(p, -x, 0.5);
 }
 
-// The general case out of line: it is rare on the usual grids, and inlined it
-// would cost registers on every path.
-__device__ __attribute__((noinline)) double one_minus_exp(double x) { return -expm1(-x); }
+// c = 1 - e^{-x}, b/h and c/x for any x >= 0, out of line: it is rare on the
+// usual grids, and inlined it would cost registers on every path.  b/h is
+// (x - c)/x^2, or its Taylor series below x = 0.01 (cancellation).
+struct ExpTerms {
+    double c, bh, cx;
+};
+__device__ __attribute__((noinline)) ExpTerms exp_terms_general(double x) {
+    ExpTerms t;
+    t.c = -expm1(-x);
+    const double rx = 1.0 / x;
+    const double bs = 0.5 + x * (-1.0 / 6.0 + x * (1.0 / 24.0 + x * (-1.0 / 120.0 + x * (1.0 / 720.0))));
+    const double bd = (x - t.c) * rx * rx;
+    t.bh = (x < 0.01) ? bs : bd;
+    t.cx = (x > 0.0) ? t.c * rx : 1.0;
+    return t;
+}
 
 template <bool DIV = false>
 __device__ __forceinline__ Exp1 exp_setup(double beta, double amp, double h, double C0, double* bA) {
     const double x = beta * h;
     // the series when every lane of the wavefront has a small step exponent
     // (a wave-uniform choice), the library expm1 otherwise
-    double c;
-    if (__ballot(!(x >= 0.0 && x <= 0.3)) == 0ull)
-        c = one_minus_exp_small(x);
-    else
-        c = one_minus_exp(x);
+    double c, bh, cx;  // 1 - e^{-x}, b/h, c/x
+    if (__ballot(!(x >= 0.0 && x <= 0.3)) == 0ull) {
+        bh = b_over_h_small(x);
+        cx = fma(-x, bh, 1.0);
+        c = x * cx;
+    } else {
+        const ExpTerms t = exp_terms_general(x);
+        c = t.c;
+        bh = t.bh;
+        cx = t.cx;
+    }
     const double r = 1.0 / (x * c);
     const double rx = c * r;
     const double rc = x * r;
-    // b/h: (x - c)/x^2, or its Taylor series for x < 0.01 (cancellation)
-    const double bs = 0.5 + x * (-1.0 / 6.0 + x * (1.0 / 24.0 + x * (-1.0 / 120.0 + x * (1.0 / 720.0))));
-    const double bd = (x - c) * rx * rx;
-    const double bh = (x < 0.01) ? bs : bd;
-    const double cx = (x > 0.0) ? c * rx : 1.0;  // c / x
     const double xc = (x > 0.0) ? x * rc : 1.0;  // x / c
     Exp1 e;
     e.rbeta = h * rx;
