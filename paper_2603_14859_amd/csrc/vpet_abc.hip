@@ -188,7 +188,7 @@ struct Exp1 {
 
 // One decaying exponential exp(-beta t), amplitude A (already times 1 - vB),
 // or A = amp / beta with DIV.  Returns the b coefficient (times A) through *bA
-// for the PP term.  One division serves 1/x, 1/c and 1/beta: r = 1/(x c),
+// for the PP term.  One reciprocal serves 1/x, 1/c and 1/beta: r = 1/(x c),
 // 1/x = c r, 1/c = x r, 1/beta = h/x (x = beta h > 0 here; x = 0 gives NaN
 // reciprocals, which the guards below and the accumulating frame path never
 // use).
@@ -244,7 +244,13 @@ __device__ __forceinline__ Exp1 exp_setup(double beta, double amp, double h, dou
         bh = t.bh;
         cx = t.cx;
     }
-    const double r = 1.0 / (x * c);
+    // r = 1/(x c): the hardware reciprocal estimate refined by two Newton-Raphson
+    // steps, each squaring the relative error (within about an ulp of the
+    // quotient; x c = 0 gives NaN, which the guards here never use)
+    const double xcp = x * c;
+    double r = __builtin_amdgcn_rcp(xcp);
+    r = fma(r, fma(-xcp, r, 1.0), r);
+    r = fma(r, fma(-xcp, r, 1.0), r);
     const double rx = c * r;
     const double rc = x * r;
     const double xc = (x > 0.0) ? x * rc : 1.0;  // x / c
