@@ -130,6 +130,49 @@ def test_simulate_parity(model, sched):
     assert err.max() <= TAC_RTOL
 
 
+# Rates up to 6/min put the step exponent x = rate * 0.2 min well above 0.3,
+# where a wavefront leaves the short series for the general set-up (expm1 and
+# the divided difference); the slow draws at the front keep whole wavefronts on
+# the series, so both paths run in one launch.
+FAST = {W.M_1TCM: {1: (0.01, 6.0)}, W.M_2TCM_IRR: {1: (0.01, 4.0), 2: (0.001, 2.0)},
+        W.M_2TCM_REV: {1: (0.01, 4.0), 2: (0.001, 2.0), 3: (0.0, 1.0)}}
+
+
+def _fast_box(model):
+    box = W.box_array([model])[0]
+    for s, lohi in FAST[model].items():
+        box[s] = lohi
+    return box
+
+
+@pytest.mark.parametrize("model", [W.M_1TCM, W.M_2TCM_IRR, W.M_2TCM_REV])
+def test_simulate_parity_fast_rates(model):
+    import oracle as ora
+    ft = W.frame_times(W.SCHED_30x50)
+    _, cp = W.grid(H, float(np.sum(W.SCHED_30x50)))
+    box = _fast_box(model)
+    rng = np.random.default_rng(model + 40)
+    th = W.true_params(rng, 20_000, model, box)
+    th[:4096, 1] = np.float32(0.05)  # 64 wavefronts of slow draws: the series path
+    if model != W.M_1TCM:
+        th[:4096, 2] = np.float32(0.01)
+    if model == W.M_2TCM_REV:
+        th[:4096, 3] = np.float32(0.01)
+    got = V.simulate(model, torch.from_numpy(th).to(DEV), cp, ft, H).cpu().numpy()
+    want = ora.simulate(model, th, cp, H, ft)
+    err = tac_rel_err(got, want)
+    print(f"[simulate fast rates] model={model} max rel err {err.max():.3e}")
+    assert err.max() <= TAC_RTOL
+
+
+@pytest.mark.parametrize("models", [(W.M_2TCM_IRR,), (W.M_1TCM, W.M_2TCM_IRR, W.M_2TCM_REV)])
+def test_infer_parity_fast_rates(models):
+    import oracle as ora
+    ft, cp, y = _inputs(W.SCHED_30x50, 24, model=W.M_2TCM_IRR, seed=19)
+    boxes = np.stack([_fast_box(m) for m in models])
+    _check_infer(ora, y, ft, cp, list(models), boxes, 1200, 0.02, 31)
+
+
 # ---------------------------------------------------------------------------
 # A0-A6 end to end: the small configuration at full size
 # ---------------------------------------------------------------------------
