@@ -135,7 +135,7 @@ typedef struct {
     /* floor in the default weights as a fraction of max_f y_vf; 0 -> 0.01. */
     float weight_floor_frac;
     /* 0: d = sum_f w_f (y_f - x_f)^2 (default); 1: d = sum_f sqrt(w_f) |y_f - x_f|
-     * (the L1 distance recommended in Sec. IV). */
+     * (the L1 distance recommended in Sec. V, Conclusions and Limitations). */
     int32_t distance;
     /* Debug / parity outputs (device, may be NULL): accepted global draw
      * indices [V][n] and their fp32 distances [V][n] in ascending (d, g) order,
