@@ -77,6 +77,7 @@ def lib():
         L.ora_infer_bank.argtypes = [P, i64, i32, P, i32, f64, P, P, i32, P, i64, f64, u64, f64, f64, i32, P, i32,
                                      P, P, P, P, P]
         L.ora_infer_bank.restype = i64
+        L.ora_summarize_set.argtypes = [P, i64, P, i32, P, i64, u64, u64, ctypes.c_uint32, P, P, P]
         L.ora_gamma_variate.argtypes = [f64, f64, f64, f64]
         L.ora_gamma_variate.restype = f64
         _lib = L
@@ -246,6 +247,22 @@ def voxel_distances(y_v, frame_times, input_fn, dt, models, boxes, n_draws, seed
                               _p(mo), M, _p(bx), int(n_draws), int(seed), int(v_global), float(lam),
                               float(floor), int(bool(l1)), None if w is None else _p(w), _p(out))
     return out
+
+
+def summarize_set(idx, models, boxes, n_draws, seed, v_global=0, bank_theta=None):
+    """The oracle's FP64 summaries (moments [M][8][2], probabilities [M]) of an
+    explicit accepted set of global draw indices: regenerated per-voxel draws of
+    voxel v_global, or rows of the shared bank's parameters bank_theta."""
+    ii = _c(idx, np.int32)
+    mo = _c(models, np.uint32)
+    M = mo.shape[0]
+    bx = _c(boxes, np.float64).reshape(M, NSLOT, 2)
+    th = None if bank_theta is None else _c(bank_theta, np.float32)
+    mom = np.empty((M, NSLOT, 2), dtype=np.float64)
+    pr = np.empty(M, dtype=np.float64)
+    lib().ora_summarize_set(_p(ii), ii.shape[0], _p(mo), M, _p(bx), int(n_draws), int(seed), int(v_global),
+                            0 if th is None else 1, None if th is None else _p(th), _p(mom), _p(pr))
+    return mom, pr
 
 
 # --------------------------------------------------------------------------

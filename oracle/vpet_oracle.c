@@ -345,14 +345,20 @@ void ora_frame_average(const double* nodes, const int32_t* kf, int F, double* ou
 /* Frame-averaged TACs of n parameter rows theta[n][8] (fp32, as drawn). */
 void ora_simulate(uint32_t model, const float* theta, int64_t n, const double* cp, int K, double h,
                   const int32_t* kf, int F, double* out) {
-    double* nodes = (double*)malloc(sizeof(double) * (size_t)(K + 1));
-    double th[ORA_NSLOT];
-    for (int64_t r = 0; r < n; ++r) {
-        for (int s = 0; s < ORA_NSLOT; ++s) th[s] = (double)theta[8 * r + s];
-        ora_simulate_nodes(model, th, cp, K, h, nodes);
-        ora_frame_average(nodes, kf, F, out + (size_t)F * r);
+    /* rows are independent; each thread works on its own rows (the result does
+     * not depend on the thread count) */
+#pragma omp parallel
+    {
+        double* nodes = (double*)malloc(sizeof(double) * (size_t)(K + 1));
+        double th[ORA_NSLOT];
+#pragma omp for schedule(static)
+        for (int64_t r = 0; r < n; ++r) {
+            for (int s = 0; s < ORA_NSLOT; ++s) th[s] = (double)theta[8 * r + s];
+            ora_simulate_nodes(model, th, cp, K, h, nodes);
+            ora_frame_average(nodes, kf, F, out + (size_t)F * r);
+        }
+        free(nodes);
     }
-    free(nodes);
 }
 
 /* Same on an FP64 parameter array (used by closed-form and grid tests). */
@@ -638,11 +644,16 @@ void ora_voxel_distances(const float* yv, int F, const float* cp_f32, int K, dou
 void ora_bank(const uint32_t* models, int M, const double* boxes, int64_t n_draws, uint64_t seed,
               const float* cp_f32, int K, double h, const int32_t* kf, int F, float* theta_out, double* x_out) {
     double* cp = (double*)malloc(sizeof(double) * (size_t)(K + 1));
-    double* nodes = (double*)malloc(sizeof(double) * (size_t)(K + 1));
     for (int k = 0; k <= K; ++k) cp[k] = (double)cp_f32[k];
-    for (int m = 0; m < M; ++m)
-        for (int64_t i = 0; i < n_draws; ++i) {
-            int64_t g = (int64_t)m * n_draws + i;
+    const int64_t n_tot = (int64_t)M * n_draws;
+    /* rows are independent; each thread works on its own rows */
+#pragma omp parallel
+    {
+        double* nodes = (double*)malloc(sizeof(double) * (size_t)(K + 1));
+#pragma omp for schedule(static)
+        for (int64_t g = 0; g < n_tot; ++g) {
+            const int m = (int)(g / n_draws);
+            const int64_t i = g % n_draws;
             float* thf = theta_out + 8 * g;
             double th[8];
             ora_draw(models[m], boxes + (size_t)m * 16, seed, 0u, (uint64_t)i, (uint32_t)m, 1u, thf, NULL, NULL);
@@ -650,7 +661,8 @@ void ora_bank(const uint32_t* models, int M, const double* boxes, int64_t n_draw
             ora_simulate_nodes(models[m], th, cp, K, h, nodes);
             ora_frame_average(nodes, kf, F, x_out + (size_t)F * g);
         }
-    free(nodes);
+        free(nodes);
+    }
     free(cp);
 }
 
@@ -711,4 +723,22 @@ int64_t ora_infer_bank(const float* y, int64_t V, int F, const float* cp_f32, in
     free(xb);
     free(theta);
     return n;
+}
+
+/* Posterior summaries (the reduction above: Eq. (6), Sec. II-D3, Sec. III-B2)
+ * of an explicit accepted set idx[0..n) of global draw indices, for parity
+ * checks of voxels whose accepted set differs from the oracle's by draws at
+ * the threshold.  theta_tab != NULL: the shared-bank form (parameters of
+ * every bank row); otherwise each draw is regenerated from its Philox
+ * counter for voxel vg and the given stream. */
+void ora_summarize_set(const int32_t* idx, int64_t n, const uint32_t* models, int M, const double* boxes,
+                       int64_t n_draws, uint64_t seed, uint64_t vg, uint32_t stream, const float* theta_tab,
+                       double* mom, double* pr) {
+    ora_cand* cand = (ora_cand*)malloc(sizeof(ora_cand) * (size_t)(n > 0 ? n : 1));
+    for (int64_t j = 0; j < n; ++j) {
+        cand[j].d = 0.0;
+        cand[j].g = (uint32_t)idx[j];
+    }
+    summarize(cand, n, M, models, boxes, n_draws, seed, vg, stream, theta_tab, mom, pr);
+    free(cand);
 }

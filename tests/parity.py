@@ -9,6 +9,8 @@
 """
 import numpy as np
 
+import workloads as W
+
 TAC_RTOL = 1e-5
 THRESH_RTOL = 1e-5
 MEAN_RTOL = 1e-3
@@ -65,3 +67,78 @@ def oracle_moments_of(ora_mod, models, boxes, seed, v_global, idx, n_draws):
             mom[mm, 3] = np.nan
         mom[mm, 6:] = np.nan
     return mom, prob
+
+
+def spread_sample(n_voxels, k=40, seed=0, edges=(256, 131072, 262144)):
+    """Sorted, unique voxel indices spread over a volume: the first and last two
+    voxels, both sides of the first few multiples of every size in `edges`
+    (workgroup blocks and voxel chunks of the launches) and of the last one,
+    the rest uniform at random; at least k of them."""
+    s = {0, 1, n_voxels - 2, n_voxels - 1}
+    for e in edges:
+        mults = list(range(e, n_voxels, e))
+        for b in mults[:2] + mults[-1:]:
+            s.update((b - 1, b))
+    rng = np.random.default_rng(seed)
+    while len(s) < k:
+        s.add(int(rng.integers(0, n_voxels)))
+    return np.array(sorted(v for v in s if 0 <= v < n_voxels), dtype=np.int64)
+
+
+_VOLUMES = {}
+
+
+def large_volume(cfg):
+    """Observed TACs of every voxel of the 1M-voxel irreversible-2TCM
+    configuration: oracle curves of the seeded true parameters plus the seeded
+    noise (each voxel its own curve; cached per process)."""
+    import oracle as ora
+    if cfg.name not in _VOLUMES:
+        th, eps = cfg.truth()
+        clean = ora.simulate(cfg.models[0], th, cfg.input_fn(), cfg.dt, cfg.frame_times)
+        _VOLUMES[cfg.name] = (th, W.add_noise(clean, cfg.frame_times, eps))
+    return _VOLUMES[cfg.name]
+
+
+def check_voxels(g_idx, g_mom, g_prob, o, dist_of, moments_of, mean_rtol=1e-5, var_rtol=1e-4, mean_atol=1e-7,
+                 var_atol=1e-9, prob_atol=1e-7, label=""):
+    """Every row j (a sampled voxel): the GPU's accepted set equals the
+    oracle's except draws whose oracle distance lies within THRESH_RTOL of
+    the oracle's threshold (dist_of(j): oracle distances of every draw, by
+    global index); the moments and model probabilities equal the oracle's
+    (its outputs when the sets agree, its FP64 reduction of the GPU's own set,
+    moments_of(j, idx) -> (mom, prob), when they differ).  No voxel is
+    exempt.  Returns the number of voxels with threshold swaps."""
+    swaps = 0
+    for j in range(g_idx.shape[0]):
+        gi = np.asarray(g_idx[j])
+        a_g, a_o = set(gi.tolist()), set(np.asarray(o["accept_idx"][j]).tolist())
+        assert len(a_g) == gi.size, f"{label} row {j}: repeated draw indices"
+        if a_g == a_o:
+            ref_mom, ref_prob = o["moments"][j], o["model_prob"][j]
+        else:
+            swaps += 1
+            d = dist_of(j)
+            h = o["threshold"][j]
+            for g in a_g ^ a_o:
+                gap = abs(d[g] - h) / h
+                assert gap <= THRESH_RTOL, f"{label} row {j}: draw {g} swapped at relative gap {gap:.3e}"
+            ref_mom, ref_prob = moments_of(j, gi)
+        gm = np.asarray(g_mom[j], dtype=np.float64)
+        assert np.array_equal(np.isnan(gm), np.isnan(ref_mom)), f"{label} row {j}: NaN pattern"
+        ok = ~np.isnan(ref_mom)
+        assert np.allclose(gm[..., 0][ok[..., 0]], ref_mom[..., 0][ok[..., 0]], rtol=mean_rtol, atol=mean_atol), \
+            f"{label} row {j}: means"
+        assert np.allclose(gm[..., 1][ok[..., 1]], ref_mom[..., 1][ok[..., 1]], rtol=var_rtol, atol=var_atol), \
+            f"{label} row {j}: variances"
+        assert np.allclose(np.asarray(g_prob[j], dtype=np.float64), ref_prob, rtol=0, atol=prob_atol,
+                           equal_nan=True), f"{label} row {j}: model probabilities"
+    return swaps
+
+
+def bank_distances(ora_mod, y_v, x_bank, ft, dt, n_nodes, l1=False, weights_v=None, lam=None):
+    """Oracle distances of one voxel to every bank row (FP64, the pinned weights)."""
+    kw = {} if lam is None else {"lam": lam}
+    w = ora_mod.weights(y_v, ft, dt, n_nodes, **kw) if weights_v is None else np.asarray(weights_v, np.float64)
+    r = np.asarray(y_v, dtype=np.float64) - x_bank
+    return (np.sqrt(w) * np.abs(r)).sum(1) if l1 else (w * r * r).sum(1)

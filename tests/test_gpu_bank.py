@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from parity import MEAN_RTOL, THRESH_RTOL  # noqa: F401
+from parity import MEAN_RTOL, THRESH_RTOL, bank_distances, check_voxels, large_volume, spread_sample  # noqa: F401
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -174,29 +174,32 @@ def test_infer_bank_limits():
 
 
 def test_infer_bank_full_size_sampled():
-    """1,048,576 voxels against a 100,000-draw bank (30 frames, 0.1 % accepted), sampled voxels vs the oracle."""
+    """1,048,576 voxels against a 100,000-draw bank (30 frames, 0.1 % accepted),
+    every voxel its own oracle curve plus noise, in the launch shape the
+    benchmark times; 96 voxels spread over the volume (its ends, contraction
+    block and voxel-chunk edges, random) against the oracle's bank form, each
+    under the swap rule, none exempt."""
     import oracle as ora
     cfg = W.CFG_LARGE
     ft, cp = cfg.frame_times, cfg.input_fn()
-    th, eps = cfg.truth()
-    rng = np.random.default_rng(4)
-    sample = np.sort(rng.choice(cfg.n_voxels, 5, replace=False))
-    y_s = W.add_noise(ora.simulate(W.M_2TCM_IRR, th[sample], cp, H, ft), ft, eps[sample])
-    y = np.tile(y_s, (cfg.n_voxels // len(sample) + 1, 1))[:cfg.n_voxels]
-    y[sample] = y_s
+    _, y = large_volume(cfg)
+    sample = spread_sample(cfg.n_voxels, k=96, seed=4)
     models = list(cfg.models)
     boxes = cfg.box_array()
     th_g, x_g = V.bank_build(models, boxes, cfg.n_draws, cfg.infer_seed, cp, ft, H)
     res = V.infer_bank(torch.from_numpy(y).to(DEV), ft, H, cp.size, models, cfg.n_draws, cfg.accept_frac, th_g, x_g,
                        debug=True)
     torch.cuda.synchronize()
-    o = ora.infer_bank(y_s, ft, cp, H, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed)
-    idx = res["accept_idx"][torch.from_numpy(sample).to(DEV)].cpu().numpy()
-    mom = res["moments"][torch.from_numpy(sample).to(DEV)].cpu().numpy()
-    for j in range(len(sample)):
-        if set(idx[j].tolist()) == set(o["accept_idx"][j].tolist()):
-            ok = ~np.isnan(o["moments"][j])
-            assert np.allclose(mom[j][ok], o["moments"][j][ok], rtol=1e-5, atol=1e-7)
-    same = sum(set(idx[j].tolist()) == set(o["accept_idx"][j].tolist()) for j in range(len(sample)))
-    assert same >= len(sample) - 1
+    sel = torch.from_numpy(sample).to(DEV)
+    g_idx, g_mom, g_prob = (res[k][sel].cpu().numpy() for k in ("accept_idx", "moments", "model_prob"))
     assert torch.isfinite(res["model_prob"]).all()
+    del res, th_g, x_g
+    y_s = y[sample]
+    o = ora.infer_bank(y_s, ft, cp, H, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed)
+    th_o, x_o = ora.bank(models, boxes, cfg.n_draws, cfg.infer_seed, cp, H, ft)
+    swaps = check_voxels(
+        g_idx, g_mom, g_prob, o,
+        dist_of=lambda j: bank_distances(ora, y_s[j], x_o, ft, H, cp.size),
+        moments_of=lambda j, idx: ora.summarize_set(idx, models, boxes, cfg.n_draws, cfg.infer_seed, bank_theta=th_o),
+        label="bank 1M")
+    print(f"[bank full size] {len(sample)} sampled voxels, {swaps} with threshold swaps")

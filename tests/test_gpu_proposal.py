@@ -27,7 +27,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from parity import THRESH_RTOL
+from parity import THRESH_RTOL, large_volume, spread_sample
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -234,27 +234,34 @@ def _synthetic_outputs(th, rng, spread=0.2, sd=0.3):
     return o
 
 
-def _check_is(y, ft, cp, o, n_draws, p, seed, v_off=0, share=0.0, scale=1.0, l1=False, weights=None):
+def _check_is(y, ft, cp, o, n_draws, p, seed, v_off=0, share=0.0, scale=1.0, l1=False, weights=None,
+              sample=None):
+    """Importance-weighted ABC on the GPU for every voxel of y; the voxels of
+    `sample` (default: all) against the oracle, each under the swap rule."""
     box, lo, hi = _box_lohi()
     res = V.infer(torch.from_numpy(y).to(DEV), ft, cp, H, [IRR], box[None], n_draws, p, seed, debug=True,
                   proposal=torch.from_numpy(o).to(DEV), voxel_offset=v_off, prior_share=share, sd_scale=scale,
                   distance="l1" if l1 else "l2",
                   weights=None if weights is None else torch.from_numpy(weights).to(DEV))
     torch.cuda.synchronize()
-    g = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()}
+    rows = np.arange(y.shape[0]) if sample is None else np.asarray(sample)
+    sel = torch.from_numpy(rows).to(DEV)
+    g = {k: (v[sel].cpu().numpy() if torch.is_tensor(v) else v) for k, v in res.items()}
+    g["ess_all"] = res["ess"]
+    del res
     n = g["n"]
     swaps = 0
-    for v in range(y.shape[0]):
+    for j, v in enumerate(rows):
         bad_w = weights is not None and not (np.isfinite(weights[v]).all() and (weights[v] >= 0).all())
         if not np.isfinite(y[v]).all() or not (np.max(y[v]) > 0) or bad_w:  # no valid observation
-            assert np.isnan(g["moments"][v]).all() and np.isnan(g["ess"][v]) and (g["accept_idx"][v] == -1).all()
+            assert np.isnan(g["moments"][j]).all() and np.isnan(g["ess"][j]) and (g["accept_idx"][j] == -1).all()
             continue
         ov = o[v].astype(np.float64)
         order, mom, ess, d = prop.infer_is(y[v], ft, cp, H, box, ov, n_draws, p, seed, v + v_off,
                                            prior_share=share, sd_scale=scale, l1=l1,
                                            weights_v=None if weights is None else weights[v])
         assert order.size == n
-        gi = g["accept_idx"][v]
+        gi = g["accept_idx"][j]
         a_g = set(gi[gi >= 0].tolist())
         a_o = set(order[np.isfinite(d[order])].tolist())
         if a_g != a_o:
@@ -272,15 +279,15 @@ def _check_is(y, ft, cp, o, n_draws, p, seed, v_off=0, share=0.0, scale=1.0, l1=
             mom = np.full((8, 2), np.nan)
             mom[[0, 1, 2, 4, 5], 0] = mean
             mom[[0, 1, 2, 4, 5], 1] = var
-        gm = g["moments"][v, 0].astype(np.float64)
+        gm = g["moments"][j, 0].astype(np.float64)
         assert np.array_equal(np.isnan(gm), np.isnan(mom)), f"voxel {v}: NaN pattern"
         ok = ~np.isnan(mom)
         assert np.allclose(gm[ok], mom[ok], rtol=1e-5, atol=1e-7), f"voxel {v}: moments"
         if np.isnan(ess):
-            assert np.isnan(g["ess"][v]) and np.isnan(g["model_prob"][v, 0])
+            assert np.isnan(g["ess"][j]) and np.isnan(g["model_prob"][j, 0])
         else:
-            assert g["ess"][v] == pytest.approx(ess, rel=1e-5)
-            assert g["model_prob"][v, 0] == 1.0
+            assert g["ess"][j] == pytest.approx(ess, rel=1e-5)
+            assert g["model_prob"][j, 0] == 1.0
     print(f"[IS-ABC parity] V={y.shape[0]} n={n} share={share} scale={scale} voxels with threshold swaps: {swaps}")
     return g
 
@@ -340,40 +347,17 @@ def test_is_abc_deterministic_across_launch_shapes(n_draws, p):
 
 
 def test_is_abc_full_size_sampled():
-    """1,048,576 voxels x 100,000 proposal draws (30 frames, 0.1 % accepted);
-    sampled voxels against the oracle."""
+    """1,048,576 voxels x 100,000 proposal draws (30 frames, 0.1 % accepted),
+    every voxel its own oracle curve plus noise and its own mixture; 48 voxels
+    spread over the volume against the oracle, each under the swap rule, none
+    exempt."""
     cfg = W.CFG_LARGE
     ft, cp = cfg.frame_times, cfg.input_fn()
-    th, eps = cfg.truth()
-    import oracle as ora
-    rng = np.random.default_rng(6)
-    sample = np.sort(rng.choice(cfg.n_voxels, 3, replace=False))
-    y_s = W.add_noise(ora.simulate(IRR, th[sample], cp, H, ft), ft, eps[sample])
-    o_s = _synthetic_outputs(th[sample], rng)
-    reps = cfg.n_voxels // len(sample) + 1
-    y = np.tile(y_s, (reps, 1))[:cfg.n_voxels]
-    o = np.tile(o_s, (reps, 1))[:cfg.n_voxels]
-    y[sample] = y_s
-    o[sample] = o_s
-    box, _, _ = _box_lohi()
-    res = V.infer(torch.from_numpy(y).to(DEV), ft, cp, H, [IRR], box[None], cfg.n_draws, cfg.accept_frac,
-                  cfg.infer_seed, debug=True, proposal=torch.from_numpy(o).to(DEV))
-    torch.cuda.synchronize()
-    sel = torch.from_numpy(sample).to(DEV)
-    idx = res["accept_idx"][sel].cpu().numpy()
-    mom = res["moments"][sel].cpu().numpy()
-    ess = res["ess"][sel].cpu().numpy()
-    same = 0
-    for j, v in enumerate(sample):
-        order, m_o, e_o, d = prop.infer_is(y_s[j], ft, cp, H, box, o_s[j].astype(np.float64), cfg.n_draws,
-                                           cfg.accept_frac, cfg.infer_seed, int(v))
-        if set(idx[j].tolist()) == set(order.tolist()):
-            same += 1
-            ok = ~np.isnan(m_o)
-            assert np.allclose(mom[j, 0][ok], m_o[ok], rtol=1e-5, atol=1e-7)
-            assert ess[j] == pytest.approx(e_o, rel=1e-5)
-    assert same >= len(sample) - 1
-    assert torch.isfinite(res["ess"]).all()
+    th, y = large_volume(cfg)
+    o = _synthetic_outputs(th, np.random.default_rng(6))
+    sample = spread_sample(cfg.n_voxels, k=48, seed=6)
+    g = _check_is(y, ft, cp, o, cfg.n_draws, cfg.accept_frac, cfg.infer_seed, sample=sample)
+    assert torch.isfinite(g["ess_all"]).all()
 
 
 def test_adam_first_step_is_lr_sign():

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from parity import THRESH_RTOL
+from parity import THRESH_RTOL, bank_distances, check_voxels, spread_sample
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -161,34 +161,38 @@ def test_reference_models_refused_by_per_voxel_path_and_mixing():
 
 
 def test_reference_full_size_sampled():
-    """1,556,480 voxels (128 x 128 x 95), 40 frames / 90 min, against one bank of
-    200k MRTM + 200k lp-ntPET draws, 0.1 % accepted (n = 400); sampled voxels
-    against the oracle."""
+    """1,556,480 voxels (128 x 128 x 95), 40 frames / 90 min, every voxel its
+    own curve (half activated), against one bank of 200k MRTM + 200k lp-ntPET
+    draws, 0.1 % accepted (n = 400); 64 voxels spread over the volume (its
+    ends, contraction block and voxel-chunk edges, random) against the
+    oracle's bank form, each under the swap rule, none exempt."""
     import oracle as ora
     cfg = W.CFG_LPNT
     ft, cr = cfg.frame_times, cfg.input_fn()
     boxes = W.box_array(MODELS)
-    rng = np.random.default_rng(8)
-    sample = np.sort(rng.choice(cfg.n_voxels, 3, replace=False))
-    ys, _ = _observed(cfg, 64)
-    y = np.tile(ys, (cfg.n_voxels // 64 + 1, 1))[:cfg.n_voxels]
+    y, active = _observed(cfg, cfg.n_voxels)
+    sample = spread_sample(cfg.n_voxels, k=64, seed=8, edges=(256, 131072))
     th_g, x_g = V.bank_build(MODELS, boxes, cfg.n_draws, cfg.infer_seed, cr, ft, cfg.dt)
     res = V.infer_bank(torch.from_numpy(y).to(DEV), ft, cfg.dt, cr.size, MODELS, cfg.n_draws, cfg.accept_frac,
                        th_g, x_g, decay_lambda=cfg.decay_lambda, debug=True)
     torch.cuda.synchronize()
     s_t = torch.from_numpy(sample).to(DEV)
-    idx = res["accept_idx"][s_t].cpu().numpy()
-    mom = res["moments"][s_t].cpu().numpy()
-    prob = res["model_prob"][s_t].cpu().numpy()
-    del res
-    o = ora.infer_bank(y[sample], ft, cr, cfg.dt, MODELS, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed,
+    g_idx, g_mom, g_prob = (res[k][s_t].cpu().numpy() for k in ("accept_idx", "moments", "model_prob"))
+    p_lp = res["model_prob"][:, 1].cpu().numpy()
+    del res, th_g, x_g
+    y_s = y[sample]
+    o = ora.infer_bank(y_s, ft, cr, cfg.dt, MODELS, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed,
                        lam=cfg.decay_lambda)
     assert o["n"] == 400
-    same = 0
-    for j in range(len(sample)):
-        if set(idx[j].tolist()) == set(o["accept_idx"][j].tolist()):
-            same += 1
-            ok = ~np.isnan(o["moments"][j])
-            assert np.allclose(mom[j][ok], o["moments"][j][ok], rtol=1e-5, atol=1e-6)
-            assert np.allclose(prob[j], o["model_prob"][j], atol=1e-7)
-    assert same >= len(sample) - 1
+    th_o, x_o = ora.bank(MODELS, boxes, cfg.n_draws, cfg.infer_seed, cr, cfg.dt, ft)
+    swaps = check_voxels(
+        g_idx, g_mom, g_prob, o,
+        dist_of=lambda j: bank_distances(ora, y_s[j], x_o, ft, cfg.dt, cr.size, lam=cfg.decay_lambda),
+        moments_of=lambda j, idx: ora.summarize_set(idx, MODELS, boxes, cfg.n_draws, cfg.infer_seed, bank_theta=th_o),
+        mean_atol=1e-6, label="lp-ntPET/MRTM 1.56M")
+    # model selection over the whole volume: activated voxels prefer lp-ntPET far more often
+    ok = np.isfinite(p_lp)
+    sens, fpr = np.mean(p_lp[ok & active] > 0.5), np.mean(p_lp[ok & ~active] > 0.5)
+    print(f"[reference full size] {len(sample)} sampled voxels, {swaps} with threshold swaps; "
+          f"P(lp-ntPET) > 1/2 for {sens:.3f} of activated and {fpr:.3f} of null voxels")
+    assert sens > 0.5 and fpr < 0.1

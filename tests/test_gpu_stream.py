@@ -1,11 +1,12 @@
 """Streaming of a volume stored in a file through the shared-bank form
 (total-body scale, Sec. III-B2): the outputs equal those of one
 vpet_abc_infer_bank call on the same data, chunk boundaries and a resumed run
-included."""
+included, and sampled streamed voxels equal the oracle's bank form."""
 import numpy as np
 import pytest
 
 import workloads as W
+from parity import bank_distances, check_voxels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -41,9 +42,10 @@ def test_stream_matches_one_call_and_resumes(tmp_path):
     y.astype(np.float32).tofile(path)
     th_g, x_g = V.bank_build(models, boxes, cfg.n_draws, cfg.infer_seed, cp, ft, cfg.dt)
     ref = V.infer_bank(torch.from_numpy(y).to(DEV), ft, cfg.dt, cp.size, models, cfg.n_draws, cfg.accept_frac,
-                       th_g, x_g)
+                       th_g, x_g, debug=True)
     torch.cuda.synchronize()
     ref_mom, ref_prob = ref["moments"].cpu().numpy(), ref["model_prob"].cpu().numpy()
+    ref_idx = ref["accept_idx"].cpu().numpy()
     prefix = tmp_path / "run"
     args = (str(path), cfg.n_voxels, ft, cfg.dt, cp.size, models, cfg.n_draws, cfg.accept_frac, th_g, x_g,
             str(prefix))
@@ -61,6 +63,28 @@ def test_stream_matches_one_call_and_resumes(tmp_path):
     assert V.stream_bank(*args, chunk_voxels=700, resume=False) == 5
     mom2, prob2 = V.load_stream_outputs(str(prefix), cfg.n_voxels, len(models))
     assert np.array_equal(np.asarray(mom2).view(np.uint32), ref_mom.view(np.uint32))
+    # streamed voxels against the oracle's bank form: both sides of every chunk
+    # boundary of both chunkings (1024 and 700), voxels written by the resumed
+    # run, the invalid voxel and random ones.  The streamed outputs equal the
+    # in-memory call's bit for bit (above), so that call's accepted sets are
+    # the streamed ones.
+    import oracle as ora
+    sample = sorted({0, 7, 1023, 1024, 2047, 2048, 2999, 699, 700, 1399, 1400, 2099, 2100, 2799, 2800}
+                    | set(np.random.default_rng(5).choice(cfg.n_voxels, 17, replace=False).tolist()))
+    sample = np.array(sample)
+    y_s = y[sample]
+    o = ora.infer_bank(y_s, ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed)
+    th_o, x_o = ora.bank(models, boxes, cfg.n_draws, cfg.infer_seed, cp, cfg.dt, ft)
+    valid = sample != 7
+    assert np.isnan(np.asarray(mom2)[7]).all() and (ref_idx[7] == -1).all()
+    vs = sample[valid]
+    swaps = check_voxels(
+        ref_idx[vs], np.asarray(mom2)[vs], np.asarray(prob2)[vs],
+        {k: o[k][valid] for k in ("accept_idx", "threshold", "moments", "model_prob")},
+        dist_of=lambda j: bank_distances(ora, y[vs[j]], x_o, ft, cfg.dt, cp.size),
+        moments_of=lambda j, idx: ora.summarize_set(idx, models, boxes, cfg.n_draws, cfg.infer_seed, bank_theta=th_o),
+        label="stream")
+    print(f"[stream vs oracle] {vs.size} streamed voxels, {swaps} with threshold swaps")
     # the reversible half prefers the reversible model on average
     p_rev = np.asarray(prob2)[:, 1]
     ok = ~np.isnan(p_rev)

@@ -344,3 +344,31 @@ def test_bad_caller_weights_invalidate_the_voxel(ora):
     for v in (1, 2):
         assert np.isnan(rb["moments"][v]).all() and (rb["accept_idx"][v] == -1).all()
     assert np.isfinite(rb["moments"][3, 0, 5, 0])
+
+
+def test_summarize_set_reproduces_the_oracle_summaries(ora):
+    """The reduction applied to an explicit set (used for voxels whose GPU set
+    differs at the threshold) equals the oracle's own summaries of its own
+    sets, per-voxel draws and shared bank; and it follows the set it is given."""
+    ft, cp = _setup()
+    models = [W.M_1TCM, W.M_2TCM_IRR, W.M_2TCM_REV]
+    boxes = W.box_array(models)
+    th, _ = W.CFG_SMALL.truth(4)
+    y = _observed(ora, W.M_2TCM_IRR, th, ft, cp)
+    res = ora.infer(y, ft, cp, H, models, boxes, 300, 0.05, 23, voxel_offset=11)
+    for v in range(y.shape[0]):
+        mom, pr = ora.summarize_set(res["accept_idx"][v][::-1], models, boxes, 300, 23, v_global=11 + v)
+        assert np.allclose(mom, res["moments"][v], rtol=1e-12, atol=1e-15, equal_nan=True)
+        assert np.array_equal(pr, res["model_prob"][v])
+    rb = ora.infer_bank(y, ft, cp, H, models, boxes, 300, 0.05, 23)
+    th_b, _ = ora.bank(models, boxes, 300, 23, cp, H, ft)
+    for v in range(y.shape[0]):
+        mom, pr = ora.summarize_set(rb["accept_idx"][v], models, boxes, 300, 23, bank_theta=th_b)
+        assert np.allclose(mom, rb["moments"][v], rtol=1e-12, atol=1e-15, equal_nan=True)
+        assert np.array_equal(pr, rb["model_prob"][v])
+    # a set of IRR draws only: probability 1 for IRR, the plain mean of those draws
+    idx = np.arange(300, 320)
+    mom, pr = ora.summarize_set(idx, models, boxes, 300, 23, bank_theta=th_b)
+    assert np.array_equal(pr, [0.0, 1.0, 0.0])
+    assert np.allclose(mom[1, 0, 0], th_b[idx, 0].astype(np.float64).mean(), rtol=1e-14)
+    assert np.isnan(mom[0]).all() and np.isnan(mom[2]).all()
