@@ -11,7 +11,8 @@
  * means and variances and model probabilities (Eq. (6); Sec. II-D3; Ki per
  * accepted sample as in Sec. III-B2).
  *
- * Entry points: vpet_abc_infer (the whole path, independent draws per voxel),
+ * Entry points: vpet_abc_infer (the whole path, independent draws per voxel;
+ * vpet_abc_infer_noalloc is the same call without device allocation),
  * vpet_abc_simulate and vpet_abc_draws (single steps, for checking),
  * vpet_abc_bank_build + vpet_abc_infer_bank (Alg. 1 with one bank of draws
  * shared by every voxel), vpet_abc_stream_bank (the bank form over a volume in
@@ -255,6 +256,26 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
                    const double* prior_box, int64_t n_draws, double accept_frac, uint64_t seed,
                    float* out_moments, float* out_model_prob, const vpet_abc_opts* opts,
                    void* hip_stream);
+
+/*
+ * vpet_abc_infer for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results, and no hipMalloc, hipFree or other
+ * allocating routine.  The call's draw-independent tables (input nodes,
+ * per-frame sums and lengths) are written in stream order into one 256 KB
+ * device array that the library holds on every GPU it runs on until the
+ * process ends; the largest grid (VPET_MAX_NODES nodes, VPET_MAX_FRAMES
+ * frames) needs about 165 KB, and a request beyond 256 KB returns
+ * VPET_E_LIMIT.  Every call on a GPU shares that array, which keeps the last
+ * call's tables: calls on one stream are ordered, but calls that overlap on
+ * one GPU (other streams, other host threads) race -- the caller orders them.
+ * Errors: those of vpet_abc_infer except VPET_E_NOMEM.
+ */
+int vpet_abc_infer_noalloc(const float* tacs, int64_t n_voxels, const float* frame_times,
+                           const float* input_fn, vpet_grid grid, uint32_t model_id,
+                           const double* prior_box, int64_t n_draws, double accept_frac, uint64_t seed,
+                           float* out_moments, float* out_model_prob, const vpet_abc_opts* opts,
+                           void* hip_stream);
 
 /*
  * The prior draws themselves (Alg. 1, lines 1-2), for checking and for

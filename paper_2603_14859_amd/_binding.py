@@ -26,7 +26,7 @@ MAX_ACCEPT = 3968
 EXPORTED = ("vpet_abc_accept_count", "vpet_abc_simulate", "vpet_abc_infer", "vpet_abc_draws",
             "vpet_abc_bank_ld", "vpet_abc_bank_build", "vpet_abc_infer_bank", "vpet_abc_stream_bank",
             "vpet_abc_last_error", "vpet_abc_version", "vpet_proposal_init", "vpet_proposal_forward",
-            "vpet_proposal_loss_grad", "vpet_proposal_train")
+            "vpet_proposal_loss_grad", "vpet_proposal_train", "vpet_abc_infer_noalloc")
 BANK_MAX_ACCEPT = 512
 BANK_MAX_FRAMES = 48
 PROPOSAL_NPARAM = 98912
@@ -64,6 +64,7 @@ def _load():
     L.vpet_abc_accept_count.argtypes = [i64, f64, ctypes.POINTER(ctypes.c_int64)]
     L.vpet_abc_simulate.argtypes = [u32, P, i64, P, P, Grid, P, P]
     L.vpet_abc_infer.argtypes = [P, i64, P, P, Grid, u32, P, i64, f64, u64, P, P, ctypes.POINTER(Opts), P]
+    L.vpet_abc_infer_noalloc.argtypes = L.vpet_abc_infer.argtypes
     L.vpet_abc_draws.argtypes = [u32, P, u64, P, P, P, i64, P, P, P]
     L.vpet_abc_bank_ld.argtypes = [ctypes.c_int32]
     L.vpet_abc_bank_ld.restype = ctypes.c_int
@@ -150,7 +151,7 @@ def simulate(model: int, theta, input_fn, frame_times, dt: float, out=None, stre
 def infer(tacs, frame_times, input_fn, dt: float, models, prior_box, n_draws: int, accept_frac: float,
           seed: int, *, weights=None, weight_floor=0.0, decay_lambda=0.0, distance="l2", debug=False,
           voxel_offset=0, waves_per_voxel=0, proposal=None, prior_share=0.0, sd_scale=1.0, out=None,
-          stream=None) -> dict:
+          stream=None, no_alloc=False) -> dict:
     """Voxelwise rejection ABC on observed TACs [V][F] (fp32, device).
 
     Returns a dict of device tensors: moments [V][M][8][2], model_prob [V][M]
@@ -158,7 +159,9 @@ def infer(tacs, frame_times, input_fn, dt: float, models, prior_box, n_draws: in
     proposal: network outputs [V][96] (proposal_forward); the draws then come
     from each voxel's mixture (with a defensive prior share prior_share and
     every sd times sd_scale), the moments are importance-weighted and "ess"
-    [V] is returned as well.
+    [V] is returned as well.  no_alloc=True calls vpet_abc_infer_noalloc
+    (same results; the library allocates no device memory; pass `out` to keep
+    this binding from allocating the output tensors).
     """
     import torch
     tacs = _dev_f32(tacs, "tacs")
@@ -205,12 +208,18 @@ def infer(tacs, frame_times, input_fn, dt: float, models, prior_box, n_draws: in
             res["ess"] = torch.empty((V,), dtype=torch.float32, device=dev)
         o.out_ess = res["ess"].data_ptr()
     grid = Grid(float(dt), cp.size, F)
-    _check(lib.vpet_abc_infer(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p), cp.ctypes.data_as(ctypes.c_void_p),
-                              grid, mask, box.ctypes.data_as(ctypes.c_void_p), int(n_draws), float(accept_frac),
-                              int(seed) & ((1 << 64) - 1), _ptr(res["moments"]), _ptr(res["model_prob"]),
-                              ctypes.byref(o), _stream(stream)))
+    entry = lib.vpet_abc_infer_noalloc if no_alloc else lib.vpet_abc_infer
+    _check(entry(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p), cp.ctypes.data_as(ctypes.c_void_p),
+                 grid, mask, box.ctypes.data_as(ctypes.c_void_p), int(n_draws), float(accept_frac),
+                 int(seed) & ((1 << 64) - 1), _ptr(res["moments"]), _ptr(res["model_prob"]),
+                 ctypes.byref(o), _stream(stream)))
     res["n"] = n
     return res
+
+
+def infer_noalloc(*args, **kwargs) -> dict:
+    """infer() through vpet_abc_infer_noalloc, the entry point that allocates no device memory."""
+    return infer(*args, no_alloc=True, **kwargs)
 
 
 def draws(models, prior_box, seed: int, voxel, draw, model_pos, stream=None):

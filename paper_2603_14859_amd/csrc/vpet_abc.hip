@@ -2465,6 +2465,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void v
     }
 }
 
+// Table staging for the allocation-free entry point: 1 KB of table bytes per
+// launch, carried in the kernel argument (copied by the runtime at launch, so
+// no host staging buffer has to outlive the call).
+constexpr int kStageWords = 128;
+struct StageChunk {
+    unsigned long long w[kStageWords];
+};
+__global__ __launch_bounds__(kStageWords) void vpet_stage_kernel(StageChunk c, unsigned long long* dst, int nwords) {
+    if ((int)threadIdx.x < nwords) dst[threadIdx.x] = c.w[threadIdx.x];
+}
+
+}  // namespace
+
+// Device memory of vpet_abc_infer_noalloc: the draw-independent tables of the
+// call (input nodes, frame sums, frame lengths; at most 256 KB), one copy per
+// GPU for the life of the process.  Host code must not use this name as an
+// address: it reaches the array only through the pointer hipGetSymbolAddress
+// returns for the current device.
+static __device__ __align__(256) unsigned char scratch[256 * 1024];
+
+namespace {
+
 // ===========================================================================
 // Host side.
 // ===========================================================================
@@ -2637,6 +2659,20 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Uploads T into a slot and returns device pointers; the caller holds ctx.mu
 // until it has recorded ctx.ev[slot] after its launch.
+// Byte layout of the tables in device memory: C (FP64), the per-frame sums
+// (FP64) and the frame lengths in nodes (int32), each 256-byte aligned.
+struct TabLayout {
+    size_t offC, offF, offN, bytes;
+};
+TabLayout tab_layout(const HostTab& T) {
+    TabLayout L;
+    L.offC = 0;
+    L.offF = align256(L.offC + sizeof(double) * T.C.size());
+    L.offN = align256(L.offF + sizeof(double) * T.fr.size());
+    L.bytes = align256(L.offN + sizeof(int) * T.nf.size());
+    return L;
+}
+
 int upload_tables(DevCtx& ctx, const HostTab& T, hipStream_t st, Tab& tab, int& slot) {
     if (!ctx.ready) {
         hipError_t e = hipMalloc((void**)&ctx.dbuf, kSlots * kSlotBytes);
@@ -2649,10 +2685,8 @@ int upload_tables(DevCtx& ctx, const HostTab& T, hipStream_t st, Tab& tab, int& 
         }
         ctx.ready = true;
     }
-    const size_t offC = 0;
-    const size_t offF = align256(offC + sizeof(double) * T.C.size());
-    const size_t offN = align256(offF + sizeof(double) * T.fr.size());
-    const size_t bytes = align256(offN + sizeof(int) * T.nf.size());
+    const TabLayout L = tab_layout(T);
+    const size_t offC = L.offC, offF = L.offF, offN = L.offN, bytes = L.bytes;
     if (bytes > kSlotBytes) return fail(VPET_E_LIMIT, "tables need %zu bytes (> %zu)", bytes, kSlotBytes);
     slot = ctx.next;
     ctx.next = (ctx.next + 1) % kSlots;
@@ -2704,6 +2738,64 @@ int current_ctx(DevCtx** out) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev < 0 || dev >= 64) return fail(VPET_E_HIP, "device ordinal %d out of range", dev);
     *out = &g_ctx[dev];
+    return VPET_OK;
+}
+
+// Allocation-free table staging (vpet_abc_infer_noalloc).  The address of
+// `scratch` on a device is looked up once, with that device current, and kept;
+// every call on the device then writes its tables there in stream order.
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[64];
+
+int noalloc_scratch(unsigned char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(VPET_E_HIP, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(VPET_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_noalloc_ptr[dev]);
+    return VPET_OK;
+}
+
+// n bytes of host data to dst in 1 KB kernel arguments; the last word of a
+// chunk is zero-padded (dst must have room up to the next 8-byte boundary).
+int stage_bytes(const void* src, size_t n, unsigned char* dst, hipStream_t st) {
+    const unsigned char* s = static_cast<const unsigned char*>(src);
+    for (size_t off = 0; off < n; off += sizeof(StageChunk)) {
+        StageChunk c;
+        const size_t len = std::min(n - off, sizeof(StageChunk));
+        std::memset(&c, 0, sizeof c);
+        std::memcpy(&c, s + off, len);
+        hipLaunchKernelGGL(vpet_stage_kernel, dim3(1), dim3(kStageWords), 0, st, c,
+                           reinterpret_cast<unsigned long long*>(dst + off), (int)((len + 7) / 8));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "table staging launch");
+    }
+    return VPET_OK;
+}
+
+int stage_tables_noalloc(const HostTab& T, hipStream_t st, Tab& tab) {
+    const TabLayout L = tab_layout(T);
+    if (L.bytes > sizeof(scratch))
+        return fail(VPET_E_LIMIT, "tables need %zu bytes (> %zu, the allocation-free buffer)", L.bytes,
+                    sizeof(scratch));
+    unsigned char* base = nullptr;
+    int rc = noalloc_scratch(&base);
+    if (rc != VPET_OK) return rc;
+    if (!T.C.empty() && (rc = stage_bytes(T.C.data(), sizeof(double) * T.C.size(), base + L.offC, st)) != VPET_OK)
+        return rc;
+    if ((rc = stage_bytes(T.fr.data(), sizeof(double) * T.fr.size(), base + L.offF, st)) != VPET_OK) return rc;
+    if ((rc = stage_bytes(T.nf.data(), sizeof(int) * T.nf.size(), base + L.offN, st)) != VPET_OK) return rc;
+    tab.C = reinterpret_cast<const double*>(base + L.offC);
+    tab.fr = reinterpret_cast<const double*>(base + L.offF);
+    tab.nf = reinterpret_cast<const int*>(base + L.offN);
     return VPET_OK;
 }
 
@@ -2777,10 +2869,12 @@ int vpet_abc_simulate(uint32_t model_id, const float* theta, int64_t n, const fl
     return VPET_OK;
 }
 
-int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times, const float* input_fn,
-                   vpet_grid grid, uint32_t model_id, const double* prior_box, int64_t n_draws, double accept_frac,
-                   uint64_t seed, float* out_moments, float* out_model_prob, const vpet_abc_opts* opts,
-                   void* hip_stream) {
+// vpet_abc_infer and its allocation-free variant: identical kernels; the
+// tables go to the pooled slots or to `scratch`.
+static int infer_entry(bool noalloc, const float* tacs, int64_t n_voxels, const float* frame_times,
+                       const float* input_fn, vpet_grid grid, uint32_t model_id, const double* prior_box,
+                       int64_t n_draws, double accept_frac, uint64_t seed, float* out_moments,
+                       float* out_model_prob, const vpet_abc_opts* opts, void* hip_stream) {
     int kinds[kMaxModels];
     const int M = model_list(model_id, kinds);
     if (M < 1) return fail(VPET_E_MODEL, "unknown or empty model bitmask 0x%x", model_id);
@@ -2871,12 +2965,17 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
     P.out_dist = o.out_accept_dist;
     P.out_thr = o.out_threshold;
 
-    DevCtx* ctx;
-    if ((rc = current_ctx(&ctx)) != VPET_OK) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
-    std::lock_guard<std::mutex> lock(ctx->mu);
-    int slot;
-    if ((rc = upload_tables(*ctx, T, st, P.tab, slot)) != VPET_OK) return rc;
+    DevCtx* ctx = nullptr;
+    std::unique_lock<std::mutex> lock;
+    int slot = 0;
+    if (noalloc) {
+        if ((rc = stage_tables_noalloc(T, st, P.tab)) != VPET_OK) return rc;
+    } else {
+        if ((rc = current_ctx(&ctx)) != VPET_OK) return rc;
+        lock = std::unique_lock<std::mutex>(ctx->mu);
+        if ((rc = upload_tables(*ctx, T, st, P.tab, slot)) != VPET_OK) return rc;
+    }
     const size_t lds = lds_for(wpv);
     const long long chunk = 1LL << 30;
     for (long long base = 0; base < n_voxels; base += chunk) {
@@ -2909,9 +3008,27 @@ int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "infer launch");
     }
-    hipError_t e = hipEventRecord(ctx->ev[slot], st);
-    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (ctx) {
+        hipError_t e = hipEventRecord(ctx->ev[slot], st);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
     return VPET_OK;
+}
+
+int vpet_abc_infer(const float* tacs, int64_t n_voxels, const float* frame_times, const float* input_fn,
+                   vpet_grid grid, uint32_t model_id, const double* prior_box, int64_t n_draws, double accept_frac,
+                   uint64_t seed, float* out_moments, float* out_model_prob, const vpet_abc_opts* opts,
+                   void* hip_stream) {
+    return infer_entry(false, tacs, n_voxels, frame_times, input_fn, grid, model_id, prior_box, n_draws,
+                       accept_frac, seed, out_moments, out_model_prob, opts, hip_stream);
+}
+
+int vpet_abc_infer_noalloc(const float* tacs, int64_t n_voxels, const float* frame_times, const float* input_fn,
+                           vpet_grid grid, uint32_t model_id, const double* prior_box, int64_t n_draws,
+                           double accept_frac, uint64_t seed, float* out_moments, float* out_model_prob,
+                           const vpet_abc_opts* opts, void* hip_stream) {
+    return infer_entry(true, tacs, n_voxels, frame_times, input_fn, grid, model_id, prior_box, n_draws,
+                       accept_frac, seed, out_moments, out_model_prob, opts, hip_stream);
 }
 
 int vpet_abc_draws(uint32_t model_id, const double* prior_box, uint64_t seed, const int64_t* voxel,
@@ -3088,20 +3205,20 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     if ((rc = upload_blob(*ctx, omega.data(), sizeof(double) * F, st, &dom, slot)) != VPET_OK) return rc;
     A.omega = static_cast<const double*>(dom);
 
-    // voxel chunks bound the candidate scratch to ~4 GiB
+    // voxel chunks bound the candidate work to ~4 GiB
     const long long chunk = std::max<long long>(256, (1LL << 32) / ((long long)cap * (long long)cand_bytes));
     const long long cv = std::min<long long>(n_voxels, chunk);
     const int KB = 2 * ld;  // contraction length: [x, x^2] per frame
-    char* scratch = nullptr;
+    char* work = nullptr;
     const size_t sz_tau = align256(sizeof(float) * cv), sz_cnt = align256(sizeof(int) * cv);
     const size_t sz_fb = align256(sizeof(int) * cv) + 256, sz_cand = align256(cand_bytes * (size_t)cap * cv);
     const size_t sz_b = use_mfma ? align256(sizeof(uint16_t) * (size_t)KB * n_tot) : 0;
     const size_t sz_a = use_mfma ? align256(sizeof(uint16_t) * (size_t)KB * cv) : 0;
     const size_t sz_c = use_mfma ? align256(sizeof(float) * cv) : 0;
     const size_t sz_av = use_mfma ? align256(sizeof(double) * cv) : 0;
-    hipError_t e = hipMallocAsync((void**)&scratch, sz_tau + sz_cnt + sz_fb + sz_cand + 2 * sz_b + 2 * sz_a + 3 * sz_c + sz_av, st);
-    if (e != hipSuccess) return fail(VPET_E_NOMEM, "bank scratch: %s", hipGetErrorString(e));
-    char* q = scratch;
+    hipError_t e = hipMallocAsync((void**)&work, sz_tau + sz_cnt + sz_fb + sz_cand + 2 * sz_b + 2 * sz_a + 3 * sz_c + sz_av, st);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "bank work: %s", hipGetErrorString(e));
+    char* q = work;
     A.tau = reinterpret_cast<float*>(q);
     q += sz_tau;
     A.cnt = reinterpret_cast<int*>(q);
@@ -3232,7 +3349,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     }
     for (hipEvent_t ev : tev)
         if (ev) (void)hipEventDestroy(ev);  // after the waits above: nothing pending
-    e = hipFreeAsync(scratch, st);
+    e = hipFreeAsync(work, st);
     if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipFreeAsync");
     e = hipEventRecord(ctx->ev[slot], st);
     if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipEventRecord");
@@ -3582,11 +3699,11 @@ int vpet_proposal_forward(const float* params, const float* tacs, int64_t n, int
     if (!params || !tacs || !out) return fail(VPET_E_ARG, "params, tacs and out must not be NULL");
     hipStream_t st = (hipStream_t)hip_stream;
     const long long rows = std::min<long long>(n, 1LL << 17);
-    char* scratch = nullptr;
-    hipError_t e = hipMallocAsync((void**)&scratch, net_work_bytes(rows), st);
-    if (e != hipSuccess) return fail(VPET_E_NOMEM, "proposal scratch: %s", hipGetErrorString(e));
+    char* work = nullptr;
+    hipError_t e = hipMallocAsync((void**)&work, net_work_bytes(rows), st);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "proposal work: %s", hipGetErrorString(e));
     NetWork w;
-    net_work_carve(scratch, rows, w);
+    net_work_carve(work, rows, w);
     for (long long b0 = 0; b0 < n; b0 += rows) {
         const int cnt = (int)std::min<long long>(rows, n - b0);
         hipLaunchKernelGGL(vpet_net_features_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
@@ -3596,7 +3713,7 @@ int vpet_proposal_forward(const float* params, const float* tacs, int64_t n, int
         net_forward(st, params, wo, cnt);
     }
     e = hipGetLastError();
-    const hipError_t e2 = hipFreeAsync(scratch, st);
+    const hipError_t e2 = hipFreeAsync(work, st);
     if (e != hipSuccess) return hip_fail(e, "proposal forward");
     return e2 == hipSuccess ? VPET_OK : hip_fail(e2, "hipFreeAsync");
 }
@@ -3608,11 +3725,11 @@ int vpet_proposal_loss_grad(const float* params, const float* tacs, const float*
     if (n < 1 || n > (1LL << 20)) return fail(VPET_E_ARG, "n must lie in [1, 2^20]");
     if (!params || !tacs || !theta || !grad || !loss) return fail(VPET_E_ARG, "pointers must not be NULL");
     hipStream_t st = (hipStream_t)hip_stream;
-    char* scratch = nullptr;
-    hipError_t e = hipMallocAsync((void**)&scratch, net_work_bytes(n), st);
-    if (e != hipSuccess) return fail(VPET_E_NOMEM, "proposal scratch: %s", hipGetErrorString(e));
+    char* work = nullptr;
+    hipError_t e = hipMallocAsync((void**)&work, net_work_bytes(n), st);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "proposal work: %s", hipGetErrorString(e));
     NetWork w;
-    net_work_carve(scratch, n, w);
+    net_work_carve(work, n, w);
     const unsigned blk = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(vpet_net_features_kernel, dim3(blk), dim3(256), 0, st, tacs, (long long)n, n_frames, w.X);
     hipLaunchKernelGGL(vpet_net_targets_kernel, dim3(blk), dim3(256), 0, st, theta, (long long)n, w.Z);
@@ -3621,7 +3738,7 @@ int vpet_proposal_loss_grad(const float* params, const float* tacs, const float*
     hipLaunchKernelGGL(vpet_mix_loss_kernel, dim3(blk), dim3(256), 0, st, w.O, w.Z, (int)n, w.dO, loss);
     net_backward(st, params, w, (int)n, grad);
     e = hipGetLastError();
-    const hipError_t e2 = hipFreeAsync(scratch, st);
+    const hipError_t e2 = hipFreeAsync(work, st);
     if (e != hipSuccess) return hip_fail(e, "proposal loss/gradient");
     return e2 == hipSuccess ? VPET_OK : hip_fail(e2, "hipFreeAsync");
 }
@@ -3654,16 +3771,16 @@ int vpet_proposal_train(float* params, const float* bank_theta, const double* ba
     const void* dfac;
     if ((rc = upload_blob(*ctx, fac.data(), sizeof(double) * kNetIn, st, &dfac, slot)) != VPET_OK) return rc;
     const size_t pbytes = align256(sizeof(float) * kNetParams);
-    char* scratch = nullptr;
-    hipError_t e = hipMallocAsync((void**)&scratch, 3 * pbytes + align256(sizeof(float) * (size_t)steps) +
+    char* work = nullptr;
+    hipError_t e = hipMallocAsync((void**)&work, 3 * pbytes + align256(sizeof(float) * (size_t)steps) +
                                                         net_work_bytes(batch), st);
-    if (e != hipSuccess) return fail(VPET_E_NOMEM, "training scratch: %s", hipGetErrorString(e));
-    float* g = reinterpret_cast<float*>(scratch);
-    float* m = reinterpret_cast<float*>(scratch + pbytes);
-    float* v = reinterpret_cast<float*>(scratch + 2 * pbytes);
-    float* losses = reinterpret_cast<float*>(scratch + 3 * pbytes);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "training work: %s", hipGetErrorString(e));
+    float* g = reinterpret_cast<float*>(work);
+    float* m = reinterpret_cast<float*>(work + pbytes);
+    float* v = reinterpret_cast<float*>(work + 2 * pbytes);
+    float* losses = reinterpret_cast<float*>(work + 3 * pbytes);
     NetWork w;
-    net_work_carve(scratch + 3 * pbytes + align256(sizeof(float) * (size_t)steps), batch, w);
+    net_work_carve(work + 3 * pbytes + align256(sizeof(float) * (size_t)steps), batch, w);
     const unsigned pblk = (unsigned)((kNetParams + 255) / 256);
     hipLaunchKernelGGL(vpet_fill_kernel, dim3(pblk), dim3(256), 0, st, m, (long long)kNetParams, 0.0f);
     hipLaunchKernelGGL(vpet_fill_kernel, dim3(pblk), dim3(256), 0, st, v, (long long)kNetParams, 0.0f);
@@ -3713,7 +3830,7 @@ int vpet_proposal_train(float* params, const float* bank_theta, const double* ba
     }
     if (e == hipSuccess && out_loss)
         e = hipMemcpyAsync(out_loss, losses, sizeof(float) * (size_t)steps, hipMemcpyDeviceToHost, st);
-    const hipError_t e2 = hipFreeAsync(scratch, st);
+    const hipError_t e2 = hipFreeAsync(work, st);
     const hipError_t e3 = hipEventRecord(ctx->ev[slot], st);
     if (e == hipSuccess && out_loss) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "proposal training");
