@@ -338,6 +338,31 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
                         const vpet_abc_opts* opts, void* hip_stream);
 
 /*
+ * The BF16 contraction scan's own values, for checking its error bound (the
+ * screening step of vpet_abc_infer_bank with bank_scan = 2, Alg. 1 line 4 as
+ * a contraction).  With A_v = [-2 w y, w] (FP64 from the voxel's fp32 curve
+ * and weights, as in vpet_abc_infer_bank) and B_g = [x_g, x_g^2], both split
+ * into bf16 hi + lo parts, the scan computes S_vg ~ sum_k A_vk B_gk as
+ * hi*hi + hi*lo + lo*hi on the matrix cores with FP32 accumulation, and
+ * d_vg = a_v + sum_k A_vk B_gk exactly (a_v = sum_f w y^2).  This call runs
+ * the operand kernels and the scan kernel itself with a candidate test that
+ * admits every pair, and writes
+ *   out_s  device [n_voxels][n_rows] fp32: S_vg (NaN for an invalid voxel)
+ *   out_a  device [n_voxels] FP64: a_v (NaN for an invalid voxel, -inf for a
+ *          voxel with a negative caller weight)
+ * for bank_x device [n_rows][vpet_abc_bank_ld(F)] FP64 rows.  The scan's
+ * candidate test relies on |S_vg - sum_k A_vk B_gk| <= m E_vg with
+ * E_vg = sum_k |A_vk| |B_gk| and m = 2 (3 2^-16 + 3 K 2^-24), K = 2 ld.
+ * opts: weights, weight_floor_frac and decay_lambda are honoured.
+ * 1 <= n_rows <= 4096 and n_voxels <= 65536 (VPET_E_LIMIT beyond).  Device
+ * scratch is allocated and freed in stream order.
+ * Errors: VPET_E_ARG, VPET_E_GRID, VPET_E_LIMIT, VPET_E_NOMEM, VPET_E_HIP.
+ */
+int vpet_abc_bank_screen(const float* tacs, int64_t n_voxels, const float* frame_times, vpet_grid grid,
+                         const double* bank_x, int64_t n_rows, const vpet_abc_opts* opts, float* out_s,
+                         double* out_a, void* hip_stream);
+
+/*
  * Streamed shared-bank inference of a volume stored in a file (total-body
  * scale; the whole-volume study of Sec. III-B2).  The observed TACs are read
  * chunk by chunk from tacs_path (raw little-endian fp32, [n_voxels][F]

@@ -12,4 +12,4 @@ from ._binding import (E_ARG, E_GRID, E_HIP, E_LIMIT, E_MODEL, E_NOMEM, EXPORTED
                        lib, model_mask, simulate, version, bank_build, infer_bank, BANK_MAX_ACCEPT, BANK_MAX_FRAMES,
                        stream_bank, load_stream_outputs, E_IO, PROPOSAL_NPARAM, PROPOSAL_NOUT,
                        PROPOSAL_MAX_FRAMES, proposal_init, proposal_forward, proposal_loss_grad, proposal_train,
-                       infer_noalloc)
+                       infer_noalloc, bank_screen)

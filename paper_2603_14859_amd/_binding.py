@@ -26,7 +26,7 @@ MAX_ACCEPT = 3968
 EXPORTED = ("vpet_abc_accept_count", "vpet_abc_simulate", "vpet_abc_infer", "vpet_abc_draws",
             "vpet_abc_bank_ld", "vpet_abc_bank_build", "vpet_abc_infer_bank", "vpet_abc_stream_bank",
             "vpet_abc_last_error", "vpet_abc_version", "vpet_proposal_init", "vpet_proposal_forward",
-            "vpet_proposal_loss_grad", "vpet_proposal_train", "vpet_abc_infer_noalloc")
+            "vpet_proposal_loss_grad", "vpet_proposal_train", "vpet_abc_infer_noalloc", "vpet_abc_bank_screen")
 BANK_MAX_ACCEPT = 512
 BANK_MAX_FRAMES = 48
 PROPOSAL_NPARAM = 98912
@@ -79,6 +79,7 @@ def _load():
                                       ctypes.c_float, u64, P, P]
     L.vpet_abc_last_error.restype = ctypes.c_char_p
     L.vpet_abc_version.restype = ctypes.c_int
+    L.vpet_abc_bank_screen.argtypes = [P, i64, P, Grid, P, i64, ctypes.POINTER(Opts), P, P, P]
     for name in EXPORTED[:4] + EXPORTED[5:8] + EXPORTED[10:]:
         getattr(L, name).restype = ctypes.c_int
     return L
@@ -313,6 +314,35 @@ def infer_bank(tacs, frame_times, dt: float, n_nodes: int, models, n_draws: int,
     if debug:
         res["fallback_voxels"] = int(n_fallback.value)
     return res
+
+
+def bank_screen(tacs, frame_times, dt: float, n_nodes: int, bank_x, *, weights=None, weight_floor=0.0,
+                decay_lambda=0.0, stream=None):
+    """The BF16 contraction scan's computed S [V][N] (fp32) and a_v [V] (FP64) of
+    every (voxel, bank row) pair, for checking the scan's error bound."""
+    import torch
+    tacs = _dev_f32(tacs, "tacs")
+    V, F = tacs.shape
+    ft = _host(frame_times, np.float32)
+    if ft.size != F + 1:
+        raise ValueError("frame_times must have F + 1 entries")
+    if not (isinstance(bank_x, torch.Tensor) and bank_x.is_cuda and bank_x.dtype == torch.float64
+            and bank_x.is_contiguous() and bank_x.dim() == 2 and bank_x.shape[1] == int(lib.vpet_abc_bank_ld(F))):
+        raise TypeError("bank_x must be a contiguous float64 [N][bank_ld(F)] tensor on the GPU")
+    N = bank_x.shape[0]
+    o = Opts()
+    o.decay_lambda = float(decay_lambda)
+    o.weight_floor_frac = float(weight_floor)
+    if weights is not None:
+        weights = _dev_f32(weights, "weights")
+        if tuple(weights.shape) != (V, F):
+            raise ValueError("weights must be [V][F]")
+        o.weights = weights.data_ptr()
+    s = torch.empty((V, N), dtype=torch.float32, device=tacs.device)
+    a = torch.empty((V,), dtype=torch.float64, device=tacs.device)
+    _check(lib.vpet_abc_bank_screen(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p), Grid(float(dt), int(n_nodes), F),
+                                    _ptr(bank_x), N, ctypes.byref(o), _ptr(s), _ptr(a), _stream(stream)))
+    return s, a
 
 
 def stream_bank(tacs_path: str, n_voxels: int, frame_times, dt: float, n_nodes: int, models, n_draws: int,

@@ -1426,11 +1426,40 @@ __global__ void vpet_bank_reset_kernel(BankArgs P) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *P.fb_count = 0u;
 }
 
+// vpet_abc_bank_screen: every valid voxel's candidate test admits every row
+// (the operand kernel has marked invalid voxels with a_v = NaN).
+__global__ __launch_bounds__(256) void vpet_bank_passall_kernel(BankArgs P) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= P.V) return;
+    const double a = P.aval[v];
+    P.cthr[v] = a == a ? __builtin_inff() : -__builtin_inff();
+    P.cnt[v] = a == a ? 0 : -1;
+}
+
+// vpet_abc_bank_screen: voxel `blockIdx.x`'s candidates (computed S, bank row)
+// scattered to out_s[v][row]; rows never listed (invalid voxel) stay NaN.
+__global__ __launch_bounds__(256) void vpet_bank_scatter_kernel(BankArgs P, float* out_s, double* out_a) {
+    const long long v = blockIdx.x;
+    float* dst = out_s + (size_t)v * P.n_tot;
+    for (unsigned j = threadIdx.x; j < P.n_tot; j += blockDim.x) dst[j] = __builtin_nanf("");
+    if (threadIdx.x == 0) out_a[v] = P.aval[v];
+    __syncthreads();
+    const int c = P.cnt[v];
+    const uint64_t* src = P.cand + (size_t)v * P.cap;
+    for (int j = threadIdx.x; j < c && j < P.cap; j += blockDim.x) {
+        const uint64_t e = src[j];
+        const uint32_t g = (uint32_t)e;
+        if (g < P.n_tot) dst[g] = __uint_as_float((uint32_t)(e >> 32));
+    }
+}
+
 // --- BF16 contraction -------------------------------------------------------
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 constexpr int kMfmaVox = 256;  // voxels per block: 8 wavefronts x 32 rows
 constexpr int kMfmaRows = 32;  // bank rows per tile
+constexpr int kScreenMaxRows = 4096;     // vpet_abc_bank_screen: bank rows (the largest candidate list)
+constexpr int kScreenMaxVoxels = 1 << 16;
 
 __device__ __forceinline__ uint16_t bf16_rn(float f) {  // round to nearest even
     const uint32_t u = __float_as_uint(f);
@@ -2799,6 +2828,35 @@ int stage_tables_noalloc(const HostTab& T, hipStream_t st, Tab& tab) {
     return VPET_OK;
 }
 
+// Frame bounds of the bank form (validated) and the weights' decay factors
+// omega_f = dt_f exp(-lambda tmid_f) (the input function is not needed).
+int bank_omega(const float* frame_times, vpet_grid grid, double decay_lambda, std::vector<double>& omega) {
+    if (!frame_times) return fail(VPET_E_ARG, "frame_times must not be NULL");
+    if (!(std::isfinite(grid.dt) && grid.dt > 0.0f)) return fail(VPET_E_GRID, "grid.dt must be finite and > 0");
+    if (grid.n_nodes < 2 || grid.n_frames < 1) return fail(VPET_E_GRID, "grid needs n_nodes >= 2, n_frames >= 1");
+    if (grid.n_frames > VPET_BANK_MAX_FRAMES)
+        return fail(VPET_E_LIMIT, "the bank form supports up to %d frames", VPET_BANK_MAX_FRAMES);
+    const double h = (double)grid.dt, lambda = decay_lambda > 0.0 ? decay_lambda : std::log(2.0) / 109.8;
+    const int F = grid.n_frames, K = grid.n_nodes - 1;
+    omega.assign(F, 0.0);
+    int kprev = -1;
+    for (int f = 0; f <= F; ++f) {
+        const double tau = (double)frame_times[f];
+        if (!std::isfinite(tau)) return fail(VPET_E_GRID, "frame_times[%d] is not finite", f);
+        const double kd = std::nearbyint(tau / h);
+        if (std::fabs(kd * h - tau) > 1e-6 * std::fmax(1.0, std::fabs(tau)))
+            return fail(VPET_E_GRID, "frame bound %g is not on the %g-min grid", tau, h);
+        if (kd < 0.0 || kd > (double)K) return fail(VPET_E_GRID, "frame bound %g lies outside the grid", tau);
+        const int k = (int)kd;
+        if (f > 0) {
+            if (k <= kprev) return fail(VPET_E_GRID, "frame bounds must increase strictly");
+            omega[f - 1] = (double)(k - kprev) * h * std::exp(-lambda * 0.5 * (double)(k + kprev) * h);
+        }
+        kprev = k;
+    }
+    return VPET_OK;
+}
+
 int pow2_at_least(int x) {
     int p = 1;
     while (p < x) p <<= 1;
@@ -3140,28 +3198,9 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         return fail(VPET_E_LIMIT, "n = %lld exceeds VPET_BANK_MAX_ACCEPT = %d", (long long)n_acc,
                     VPET_BANK_MAX_ACCEPT);
     // frame bounds and weights' decay factors (the input function is not needed)
-    if (!frame_times) return fail(VPET_E_ARG, "frame_times must not be NULL");
-    if (grid.n_nodes < 2 || grid.n_frames < 1) return fail(VPET_E_GRID, "grid needs n_nodes >= 2, n_frames >= 1");
-    if (grid.n_frames > VPET_BANK_MAX_FRAMES)
-        return fail(VPET_E_LIMIT, "the bank form supports up to %d frames", VPET_BANK_MAX_FRAMES);
-    const double h = (double)grid.dt, lambda = o.decay_lambda > 0.0 ? o.decay_lambda : std::log(2.0) / 109.8;
-    const int F = grid.n_frames, K = grid.n_nodes - 1;
-    std::vector<double> omega(F);
-    int kprev = -1;
-    for (int f = 0; f <= F; ++f) {
-        const double tau = (double)frame_times[f];
-        if (!std::isfinite(tau)) return fail(VPET_E_GRID, "frame_times[%d] is not finite", f);
-        const double kd = std::nearbyint(tau / h);
-        if (std::fabs(kd * h - tau) > 1e-6 * std::fmax(1.0, std::fabs(tau)))
-            return fail(VPET_E_GRID, "frame bound %g is not on the %g-min grid", tau, h);
-        if (kd < 0.0 || kd > (double)K) return fail(VPET_E_GRID, "frame bound %g lies outside the grid", tau);
-        const int k = (int)kd;
-        if (f > 0) {
-            if (k <= kprev) return fail(VPET_E_GRID, "frame bounds must increase strictly");
-            omega[f - 1] = (double)(k - kprev) * h * std::exp(-lambda * 0.5 * (double)(k + kprev) * h);
-        }
-        kprev = k;
-    }
+    const int F = grid.n_frames;
+    std::vector<double> omega;
+    if ((rc = bank_omega(frame_times, grid, o.decay_lambda, omega)) != VPET_OK) return rc;
     if (n_voxels == 0) return VPET_OK;
     if (!tacs || !out_moments || !out_model_prob || !bank_theta || !bank_x)
         return fail(VPET_E_ARG, "tacs, bank and output pointers must not be NULL");
@@ -3356,6 +3395,105 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     return rc;
 }
 
+
+int vpet_abc_bank_screen(const float* tacs, int64_t n_voxels, const float* frame_times, vpet_grid grid,
+                         const double* bank_x, int64_t n_rows, const vpet_abc_opts* opts, float* out_s,
+                         double* out_a, void* hip_stream) {
+    if (n_voxels < 0) return fail(VPET_E_ARG, "n_voxels must be >= 0");
+    if (n_voxels > kScreenMaxVoxels)
+        return fail(VPET_E_LIMIT, "bank_screen takes at most %d voxels", kScreenMaxVoxels);
+    if (n_rows < 1) return fail(VPET_E_ARG, "n_rows must be >= 1");
+    if (n_rows > kScreenMaxRows) return fail(VPET_E_LIMIT, "bank_screen takes at most %d bank rows", kScreenMaxRows);
+    vpet_abc_opts o{};
+    if (opts) o = *opts;
+    if (!(std::isfinite(o.decay_lambda) && o.decay_lambda >= 0.0))
+        return fail(VPET_E_ARG, "opts.decay_lambda must be finite and >= 0");
+    if (!(std::isfinite(o.weight_floor_frac) && o.weight_floor_frac >= 0.0f))
+        return fail(VPET_E_ARG, "opts.weight_floor_frac must be finite and >= 0");
+    std::vector<double> omega;
+    int rc = bank_omega(frame_times, grid, o.decay_lambda, omega);
+    if (rc != VPET_OK) return rc;
+    if (n_voxels == 0) return VPET_OK;
+    if (!tacs || !bank_x || !out_s || !out_a) return fail(VPET_E_ARG, "device pointers must not be NULL");
+    const int F = grid.n_frames, ld = vpet_abc_bank_ld(F), KB = 2 * ld;
+    const int cap = pow2_at_least((int)n_rows);
+    BankArgs A{};
+    A.tacs = tacs;
+    A.weights = o.weights;
+    A.bank_x = bank_x;
+    A.floor_frac = o.weight_floor_frac > 0.0f ? (double)o.weight_floor_frac : 0.01;
+    A.F = F;
+    A.ld = ld;
+    A.M = 1;
+    A.cap = cap;
+    A.V = n_voxels;
+    A.n_tot = (unsigned)n_rows;
+    A.K = KB;
+    DevCtx* ctx;
+    if ((rc = current_ctx(&ctx)) != VPET_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int slot;
+    const void* dom;
+    if ((rc = upload_blob(*ctx, omega.data(), sizeof(double) * F, st, &dom, slot)) != VPET_OK) return rc;
+    A.omega = static_cast<const double*>(dom);
+    const size_t V = (size_t)n_voxels;
+    const size_t sz_cnt = align256(sizeof(int) * V), sz_cand = align256(sizeof(uint64_t) * (size_t)cap * V);
+    const size_t sz_b = align256(sizeof(uint16_t) * (size_t)KB * (size_t)n_rows);
+    const size_t sz_a = align256(sizeof(uint16_t) * (size_t)KB * V);
+    const size_t sz_c = align256(sizeof(float) * V), sz_av = align256(sizeof(double) * V);
+    char* work = nullptr;
+    hipError_t e = hipMallocAsync((void**)&work, sz_cnt + sz_cand + 2 * sz_b + 2 * sz_a + 4 * sz_c + sz_av, st);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "screen work: %s", hipGetErrorString(e));
+    char* q = work;
+    A.cnt = reinterpret_cast<int*>(q);
+    q += sz_cnt;
+    A.cand = reinterpret_cast<uint64_t*>(q);
+    q += sz_cand;
+    A.bhi = reinterpret_cast<uint16_t*>(q);
+    q += sz_b;
+    A.blo = reinterpret_cast<uint16_t*>(q);
+    q += sz_b;
+    A.ahi = reinterpret_cast<uint16_t*>(q);
+    q += sz_a;
+    A.alo = reinterpret_cast<uint16_t*>(q);
+    q += sz_a;
+    A.cthr = reinterpret_cast<float*>(q);
+    q += sz_c;
+    A.cthr1 = reinterpret_cast<float*>(q);
+    q += sz_c;
+    A.tau = reinterpret_cast<float*>(q);
+    q += sz_c;
+    A.tau1 = reinterpret_cast<float*>(q);
+    q += sz_c;
+    A.aval = reinterpret_cast<double*>(q);
+    const dim3 b256(256), rows((unsigned)((n_rows + 255) / 256)), lanes((unsigned)((V + 255) / 256));
+    const dim3 mblocks((unsigned)((V + kMfmaVox - 1) / kMfmaVox)), per_voxel((unsigned)V);
+#define VPET_SCREEN(LDV)                                                                   \
+    do {                                                                                   \
+        hipLaunchKernelGGL((vpet_bank_bops_kernel<LDV>), rows, b256, 0, st, A);            \
+        hipLaunchKernelGGL((vpet_bank_aops_kernel<LDV>), lanes, b256, 0, st, A);           \
+        hipLaunchKernelGGL(vpet_bank_passall_kernel, lanes, b256, 0, st, A);               \
+        launch_mfma<2 * LDV, false>(mblocks, st, A);                                       \
+    } while (0)
+    switch (ld) {
+        case 8: VPET_SCREEN(8); break;
+        case 16: VPET_SCREEN(16); break;
+        case 24: VPET_SCREEN(24); break;
+        case 32: VPET_SCREEN(32); break;
+        case 40: VPET_SCREEN(40); break;
+        default: VPET_SCREEN(48); break;
+    }
+#undef VPET_SCREEN
+    hipLaunchKernelGGL(vpet_bank_scatter_kernel, per_voxel, b256, 0, st, A, out_s, out_a);
+    e = hipGetLastError();
+    if (e != hipSuccess) rc = hip_fail(e, "screen launch");
+    e = hipFreeAsync(work, st);
+    if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipFreeAsync");
+    e = hipEventRecord(ctx->ev[slot], st);
+    if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipEventRecord");
+    return rc;
+}
 
 // ===========================================================================
 // Streaming driver: a volume in a file, two chunks in flight.
