@@ -195,6 +195,15 @@ typedef struct {
     double proposal_prior_share;
     /* With proposal: factor (> 0) on every component's sd; 0 -> 1. */
     double proposal_sd_scale;
+    /* With proposal: device [n_voxels] fp32 thresholds h_v.  Of the n kept
+     * draws, only those with fp32 distance <= h_v enter the moments, the
+     * weights and the ESS: ABC with a given threshold (the indicator form of
+     * Eq. (7)) instead of a given fraction.  The caller picks n large enough
+     * that the n-th distance (out_threshold) exceeds h_v; otherwise the kept
+     * draws are the n closest ones below h_v.  A voxel with no kept draw at or
+     * below h_v (or h_v NaN) gets NaN moments, probability and ESS.  NULL =
+     * every kept draw counts. */
+    const float* accept_below;
 } vpet_abc_opts;
 
 /*
@@ -338,6 +347,86 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
                         const vpet_abc_opts* opts, void* hip_stream);
 
 /*
+ * Shared-bank form with a learned proposal (not in the paper: the bank of
+ * Alg. 1, lines 1-3, drawn from a proposal instead of the prior, with every
+ * bank row weighted by prior / proposal so that each voxel's ABC target is
+ * unchanged).  The voxels are grouped by the posterior that the network
+ * (vpet_proposal_forward) gives for them, and each group gets its own bank:
+ *  1. cells: each voxel's mixture over z = log theta (a head over `dims`
+ *     parameters) has mean m_j and second moment s_j per parameter; cell
+ *     coordinate j is floor(bins (exp(m_j) - lo_j) / (hi_j - lo_j)) clamped to
+ *     [0, bins - 1] over the prior box of the head's parameters (the box of
+ *     the last model listed), and the cells are numbered along a serpentine
+ *     walk (coordinate j runs backwards when the number of the coordinates
+ *     before it is odd), so that consecutive cells are neighbours; a voxel
+ *     whose observation is invalid (as in vpet_abc_infer) comes last;
+ *  2. groups: the voxels sorted by cell (ties by voxel index) are cut into
+ *     groups of group_voxels consecutive voxels (G = ceil(n_voxels /
+ *     group_voxels) groups);
+ *  3. proposals: group g's Gaussian has, per head parameter, the mean mu_j =
+ *     avg m_j and the sd sqrt(avg s_j - mu_j^2) * sd_scale over its valid
+ *     members (FP64 sums, stored in fp32), mixed with the prior with the
+ *     defensive share a = prior_share: the proposal is a p + (1 - a) q_g;
+ *  4. banks: n_draws rows per model per group; row i of list position m of
+ *     group g uses Philox4x32-10 counters (i, G0 + g, 3, m << 16) and (i,
+ *     G0 + g, 3, m << 16 | 1) (G0 = first_group; the second counter only for
+ *     five-parameter models), the seed as
+ *     key; u0 = ((w0 & 255) | (w1 & 255) << 8 | (w2 & 255) << 16) 2^-24 < a
+ *     (or a group without valid members) draws every parameter uniformly,
+ *     theta_p = fp32(lo_p + u_p wid_p) (lo_p, wid_p = hi_p - lo_p in fp32);
+ *     otherwise theta_p = fp32(exp(mu_d + sd_d n_p)) for each parameter with
+ *     a head parameter d (a draw outside the box gets weight 0) and a
+ *     uniform draw from u_6 for k4 under a four-parameter head; u_p = (w_p >>
+ *     8) 2^-24 (p < 4), u_4, u_5, u_6 = (v0, v1, v2 >> 8) 2^-24, normals n_2q,
+ *     n_2q+1 = r cos, r sin (2 pi u_2q+1), r = sqrt(-2 ln(u_2q + 2^-24));
+ *     log w = -log(a + (1 - a) e^L), L = sum over the head's parameters of
+ *     log N(z_p; mu_d, sd_d) - z_p + log wid_p (z_p = log theta_p for a
+ *     uniform draw); every row is simulated as in vpet_abc_bank_build;
+ *  5. each voxel runs the bank form of vpet_abc_infer_bank against its
+ *     group's bank (n = floor(M n_draws p + 1e-6) closest rows, the exact
+ *     accepted set whatever the scan), and the accepted rows count with their
+ *     weights: per model m, probability sum_m w / sum w and weighted means
+ *     and variances sum w (t - mean)^2 / sum w (Ki in slot 5; FP64).
+ *   model_id      VPET_M_2TCM_IRR and/or VPET_M_2TCM_REV.  A four-parameter
+ *                 head (K1, k2, k3, vB) drives both (k4 of the reversible
+ *                 model then comes from the prior); a five-parameter head
+ *                 (K1, k2, k3, k4, vB) drives the irreversible model through
+ *                 its four shared parameters.
+ *   proposal      device [n_voxels][VPET_PROPOSAL_NOUT] network outputs
+ *   groups        the grouping (below); n_draws per model per group
+ *   opts          weights, weight_floor_frac, decay_lambda, distance, the
+ *                 debug outputs (out_accept_idx holds rows of the group's bank
+ *                 as numbered in out_bank_theta), bank_pilot, bank_scan,
+ *                 out_scan_ms, out_fallback_voxels, out_ess and accept_below
+ *                 are honoured; proposal, voxel_offset and waves_per_voxel
+ *                 must be unset.
+ * Device scratch (the grouping, about 40 + 4 F bytes per voxel; the banks and
+ * candidate lists of one chunk of whole groups, each within 4 GiB) is
+ * allocated and freed in stream order.
+ * Errors: VPET_E_ARG, VPET_E_MODEL, VPET_E_GRID, VPET_E_LIMIT (bins^dims >
+ * 4096, n > VPET_BANK_MAX_ACCEPT, F > VPET_BANK_MAX_FRAMES, more than 2^31 - 1
+ * voxels), VPET_E_NOMEM, VPET_E_HIP.
+ */
+typedef struct {
+    int32_t dims;          /* 4 or 5: the network head (vpet_proposal_train)         */
+    int32_t bins;          /* cells per parameter, >= 1, bins^dims <= 4096            */
+    int32_t group_voxels;  /* voxels per group: a positive multiple of 256            */
+    double prior_share;    /* defensive share a in [0, 1]                             */
+    double sd_scale;       /* factor (> 0) on each group's sd; 0 -> 1                 */
+    int64_t first_group;   /* added to the group index g in the Philox counters       */
+    int32_t* out_group;    /* device [n_voxels] group of each voxel, or NULL          */
+    float* out_bank_theta; /* device [G][M n_draws][VPET_PSTRIDE] bank draws, or NULL */
+    double* out_bank_logw; /* device [G][M n_draws] log weights, or NULL              */
+} vpet_bank_groups;
+
+int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float* frame_times,
+                                const float* input_fn, vpet_grid grid, uint32_t model_id,
+                                const double* prior_box, const float* proposal,
+                                const vpet_bank_groups* groups, int64_t n_draws, double accept_frac,
+                                uint64_t seed, float* out_moments, float* out_model_prob,
+                                const vpet_abc_opts* opts, void* hip_stream);
+
+/*
  * The BF16 contraction scan's own values, for checking its error bound (the
  * screening step of vpet_abc_infer_bank with bank_scan = 2, Alg. 1 line 4 as
  * a contraction).  With A_v = [-2 w y, w] (FP64 from the voxel's fp32 curve
@@ -396,6 +485,29 @@ int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* f
                          int64_t max_chunks, const vpet_abc_opts* opts, int64_t* out_done, void* hip_stream);
 
 /*
+ * vpet_abc_stream_bank with a learned proposal: the same streaming (file in,
+ * two chunks in flight, outputs and progress on disk, resume), where each
+ * chunk runs the network (vpet_proposal_forward with params) and then
+ * vpet_abc_infer_bank_learned on the chunk's voxels; the grouping is made
+ * within each chunk (a voxel's outputs depend on the chunk it is in, which
+ * chunk_voxels fixes), and chunk c numbers its groups from first_group +
+ * c ceil(chunk_voxels / group_voxels) in the Philox counters.  model_id, prior_box, groups (the out_* members must
+ * be NULL), n_draws, accept_frac and seed as vpet_abc_infer_bank_learned;
+ * opts as vpet_abc_stream_bank (out_ess and accept_below refused).  F <= 32.
+ * The progress file names this kind of run, so a resume does not continue a
+ * prior-bank run or the reverse.  Device buffers of one chunk's network
+ * outputs are allocated and freed by the call, which returns when the
+ * processed chunks are on disk.
+ * Errors: those of vpet_abc_stream_bank and vpet_abc_infer_bank_learned.
+ */
+int vpet_abc_stream_bank_learned(const char* tacs_path, int64_t n_voxels, const float* frame_times,
+                                 const float* input_fn, vpet_grid grid, uint32_t model_id,
+                                 const double* prior_box, const float* params, const vpet_bank_groups* groups,
+                                 int64_t n_draws, double accept_frac, uint64_t seed, int64_t chunk_voxels,
+                                 const char* out_prefix, int32_t resume, int64_t max_chunks,
+                                 const vpet_abc_opts* opts, int64_t* out_done, void* hip_stream);
+
+/*
  * Learned proposal for importance-weighted ABC (not in the paper: an
  * amortised proposal for the prior draws of Alg. 1, lines 1-2; the ABC
  * target is unchanged because accepted draws carry the weight prior /
@@ -425,18 +537,30 @@ int vpet_proposal_init(float* params, uint64_t seed, void* hip_stream);
 int vpet_proposal_forward(const float* params, const float* tacs, int64_t n, int32_t n_frames, float* out,
                           void* hip_stream);
 
+/* Heads.  The outputs are read as a mixture over D = dims parameters:
+ * dims = 4 (the layout above): z = log(K1, k2, k3, vB), outputs 0..71;
+ * dims = 5: z = log(K1, k2, k3, k4, vB), outputs 0..7 logits, 8..47 means
+ * (component c, parameter j at 8 + 5 c + j), 48..87 raw scales (48 + 5 c +
+ * j).  A five-parameter head is trained on reversible-2TCM draws (k4 in slot
+ * 3) and drives the reversible model of vpet_abc_infer_bank_learned, and the
+ * irreversible one through the marginal of its other four parameters. */
+
 /* Training loss and its gradient for one batch: loss[0] = mean over the n
- * rows of -log q(z | tacs), z = log(max(theta, 1e-6)) of slots K1, k2, k3, vB
- * of theta [n][VPET_PSTRIDE] (fp32, the bank layout); grad
- * [VPET_PROPOSAL_NPARAM] is overwritten with d loss / d params.  1 <= n <=
- * 2^20.  Errors: VPET_E_ARG, VPET_E_LIMIT, VPET_E_NOMEM, VPET_E_HIP. */
+ * rows of -log q(z | tacs), z = log(max(theta, 1e-6)) of the head's slots
+ * (K1, k2, k3, vB for dims = 4; K1, k2, k3, k4, vB for dims = 5) of theta
+ * [n][VPET_PSTRIDE] (fp32, the bank layout); grad [VPET_PROPOSAL_NPARAM] is
+ * overwritten with d loss / d params (the unused outputs get zero gradient).
+ * 1 <= n <= 2^20.  Errors: VPET_E_ARG (also dims not 4 or 5), VPET_E_LIMIT,
+ * VPET_E_NOMEM, VPET_E_HIP. */
 int vpet_proposal_loss_grad(const float* params, const float* tacs, const float* theta, int64_t n,
-                            int32_t n_frames, float* grad, float* loss, void* hip_stream);
+                            int32_t n_frames, int32_t dims, float* grad, float* loss, void* hip_stream);
 
 /* `steps` Adam steps (beta 0.9, 0.999, eps 1e-8; the step size follows a
- * cosine decay from learning_rate at the first step towards 0) on params,
- * trained on the shared bank of vpet_abc_bank_build (bank_theta, bank_x with
- * n_bank rows of one irreversible 2TCM bank): step t takes `batch`
+ * cosine decay from learning_rate at the first step towards 0) on params, a
+ * head over `dims` parameters (4 or 5, as vpet_proposal_loss_grad), trained
+ * on the shared bank of vpet_abc_bank_build (bank_theta, bank_x with n_bank
+ * rows of one irreversible 2TCM bank for dims = 4, one reversible 2TCM bank
+ * for dims = 5): step t takes `batch`
  * consecutive rows of a seeded affine permutation of the bank (a new one per
  * pass) and adds fresh Gaussian noise of variance
  * noise_level e^{decay_lambda tmid_f} max(x_f, 0) / dt_f to each frame
@@ -449,9 +573,9 @@ int vpet_proposal_loss_grad(const float* params, const float* tacs, const float*
  * Errors: VPET_E_ARG, VPET_E_GRID (frame bounds), VPET_E_LIMIT, VPET_E_NOMEM,
  * VPET_E_HIP. */
 int vpet_proposal_train(float* params, const float* bank_theta, const double* bank_x, int64_t n_bank,
-                        const float* frame_times, int32_t n_frames, double noise_level, double decay_lambda,
-                        int64_t steps, int32_t batch, float learning_rate, uint64_t seed, float* out_loss,
-                        void* hip_stream);
+                        const float* frame_times, int32_t n_frames, int32_t dims, double noise_level,
+                        double decay_lambda, int64_t steps, int32_t batch, float learning_rate, uint64_t seed,
+                        float* out_loss, void* hip_stream);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char* vpet_abc_last_error(void);

@@ -15,7 +15,9 @@ is unchanged).  Definitions:
   32 -> 256 -> 256 -> 72 (8 mixture logits, 8 x 4 means, 8 x 4 raw scales);
 * mixture over z = log(theta) of the D = 4 free parameters (K1, k2, k3, vB of
   the irreversible 2TCM): weights softmax(logits); log sd = LS0 + (LS1 - LS0)
-  sigmoid(raw) (a smooth clamp to [LS0, LS1]);
+  sigmoid(raw) (a smooth clamp to [LS0, LS1]).  A head over D = 5 parameters
+  (K1, k2, k3, k4, vB of the reversible 2TCM) reads outputs 8 + 5 c + j
+  (means) and 48 + 5 c + j (raw scales) instead (88 outputs in use);
 * training loss: mean negative log density of z = log(theta) of the training
   draws (clamped at 1e-6 before the log), minimised with Adam;
 * inference-time options: an sd scale s (every component's log sd + log s,
@@ -49,11 +51,22 @@ LS0, LS1 = -6.0, 2.0
 FREE_SLOTS = (0, 1, 2, 4)  # K1, k2, k3, vB of the irreversible 2TCM
 
 
-def init_params(rng: np.random.Generator) -> dict:
+def head_slots(dims: int = D):
+    """theta slots of a head's parameters: (K1, k2, k3, vB) or (K1, k2, k3, k4, vB)."""
+    return {4: (0, 1, 2, 4), 5: (0, 1, 2, 3, 4)}[dims]
+
+
+def head_outputs(dims: int = D) -> int:
+    """Outputs in use by a head over dims parameters."""
+    return C + 2 * C * dims
+
+
+def init_params(rng: np.random.Generator, dims: int = D) -> dict:
     """He-normal weights, zero biases (FP64)."""
+    no = head_outputs(dims)
     return {"W1": rng.standard_normal((NF, H)) * math.sqrt(2.0 / NF), "b1": np.zeros(H),
             "W2": rng.standard_normal((H, H)) * math.sqrt(2.0 / H), "b2": np.zeros(H),
-            "W3": rng.standard_normal((H, NOUT)) * math.sqrt(1.0 / H), "b3": np.zeros(NOUT)}
+            "W3": rng.standard_normal((H, no)) * math.sqrt(1.0 / H), "b3": np.zeros(no)}
 
 
 def features(y: np.ndarray) -> np.ndarray:
@@ -72,13 +85,13 @@ def forward(p: dict, x: np.ndarray):
     return o, (x, a1, h1, a2, h2)
 
 
-def mixture(o: np.ndarray, sd_scale: float = 1.0):
-    """(log pi [B][C], mu [B][C][D], log sd [B][C][D]) of network outputs."""
+def mixture(o: np.ndarray, sd_scale: float = 1.0, dims: int = D):
+    """(log pi [B][C], mu [B][C][dims], log sd [B][C][dims]) of network outputs."""
     logits = o[:, :C]
     m = logits.max(axis=1, keepdims=True)
     logpi = logits - m - np.log(np.exp(logits - m).sum(axis=1, keepdims=True))
-    mu = o[:, C:C + C * D].reshape(-1, C, D)
-    raw = o[:, C + C * D:C + 2 * C * D].reshape(-1, C, D)
+    mu = o[:, C:C + C * dims].reshape(-1, C, dims)
+    raw = o[:, C + C * dims:C + 2 * C * dims].reshape(-1, C, dims)
     logsd = LS0 + (LS1 - LS0) / (1.0 + np.exp(-raw))
     if sd_scale != 1.0:
         logsd = logsd + math.log(sd_scale)
@@ -86,25 +99,26 @@ def mixture(o: np.ndarray, sd_scale: float = 1.0):
 
 
 def log_density(o: np.ndarray, z: np.ndarray, sd_scale: float = 1.0) -> np.ndarray:
-    """log q(z) per row (the mixture density of z)."""
-    logpi, mu, logsd = mixture(o, sd_scale)
+    """log q(z) per row (the mixture density of z; the head's size is z's width)."""
+    logpi, mu, logsd = mixture(o, sd_scale, dims=z.shape[1])
     t = (z[:, None, :] - mu) * np.exp(-logsd)
     comp = logpi + (-0.5 * t * t - logsd - 0.5 * math.log(2.0 * math.pi)).sum(axis=2)
     mx = comp.max(axis=1, keepdims=True)
     return (mx + np.log(np.exp(comp - mx).sum(axis=1, keepdims=True)))[:, 0]
 
 
-def targets(theta: np.ndarray) -> np.ndarray:
-    """z = log(theta) of the free parameters (theta clamped at 1e-6)."""
-    t = np.asarray(theta, dtype=np.float64)[:, FREE_SLOTS]
+def targets(theta: np.ndarray, dims: int = D) -> np.ndarray:
+    """z = log(theta) of the head's parameters (theta clamped at 1e-6)."""
+    t = np.asarray(theta, dtype=np.float64)[:, list(head_slots(dims))]
     return np.log(np.maximum(t, 1e-6))
 
 
 def loss_and_grad(p: dict, x: np.ndarray, z: np.ndarray):
-    """Mean negative log density and its gradient with respect to every parameter."""
-    B = x.shape[0]
+    """Mean negative log density and its gradient with respect to every
+    parameter (a head over z's width of parameters)."""
+    B, Dz = x.shape[0], z.shape[1]
     o, (x, a1, h1, a2, h2) = forward(p, x)
-    logpi, mu, logsd = mixture(o)
+    logpi, mu, logsd = mixture(o, dims=Dz)
     sd_inv = np.exp(-logsd)
     t = (z[:, None, :] - mu) * sd_inv
     comp = logpi + (-0.5 * t * t - logsd - 0.5 * math.log(2.0 * math.pi)).sum(axis=2)
@@ -114,10 +128,10 @@ def loss_and_grad(p: dict, x: np.ndarray, z: np.ndarray):
     r = np.exp(comp - lse)                     # responsibilities [B][C]
     do = np.zeros_like(o)
     do[:, :C] = (np.exp(logpi) - r) / B        # d(-log q)/d logits
-    do[:, C:C + C * D] = (-(r[:, :, None] * t * sd_inv) / B).reshape(B, -1)
+    do[:, C:C + C * Dz] = (-(r[:, :, None] * t * sd_inv) / B).reshape(B, -1)
     s = (logsd - LS0) / (LS1 - LS0)            # sigmoid(raw)
     dlogsd = r[:, :, None] * (1.0 - t * t) / B
-    do[:, C + C * D:] = (dlogsd * (LS1 - LS0) * s * (1.0 - s)).reshape(B, -1)
+    do[:, C + C * Dz:C + 2 * C * Dz] = (dlogsd * (LS1 - LS0) * s * (1.0 - s)).reshape(B, -1)
     g = {"W3": h2.T @ do, "b3": do.sum(axis=0)}
     dh2 = (do @ p["W3"].T) * (a2 > 0.0)
     g["W2"], g["b2"] = h1.T @ dh2, dh2.sum(axis=0)
@@ -201,14 +215,16 @@ def philox_words(v: int, n: int, seed: int) -> np.ndarray:
 
 
 def infer_is(y_v, frame_times, input_fn, dt, box, o_v, n_draws, accept_frac, seed, v_global, lam=None,
-             prior_share=0.0, sd_scale=1.0, l1=False, weights_v=None):
+             prior_share=0.0, sd_scale=1.0, l1=False, weights_v=None, accept_below=None):
     """Importance-weighted fixed-budget ABC of one voxel (irreversible 2TCM):
     n_draws proposal draws, the n closest valid ones accepted (ties to the lower
     draw index), weighted summaries.  Distances as in the plain method: the
     noise-weighted L2 sum_f w_f (y_f - x_f)^2, or L1 sum_f sqrt(w_f) |y_f - x_f|,
-    with the default weights or the caller's weights_v.  Returns (accepted
-    indices, moments [8][2] with Ki in slot 5 and NaN in unused slots, ESS,
-    distances of every draw)."""
+    with the default weights or the caller's weights_v.  With accept_below = h,
+    only the accepted draws whose distance (rounded to fp32, as the ranking
+    keys are) is at most h enter the summaries: ABC at a given threshold, the
+    indicator form of Eq. (7).  Returns (accepted indices, moments [8][2] with
+    Ki in slot 5 and NaN in unused slots, ESS, distances of every draw)."""
     import oracle as ora
     lam = ora.DEFAULT_LAMBDA if lam is None else lam
     lo = np.array([np.float32(box[s][0]) for s in FREE_SLOTS], dtype=np.float64)
@@ -233,6 +249,8 @@ def infer_is(y_v, frame_times, input_fn, dt, box, o_v, n_draws, accept_frac, see
     n = ora.accept_count(n_draws, accept_frac)
     order = np.lexsort((np.arange(n_draws), d))[:n]
     keep = order[np.isfinite(d[order])]
+    if accept_below is not None:
+        keep = keep[d[keep].astype(np.float32) <= np.float32(accept_below)]
     t = theta[keep].astype(np.float64)
     t[:, 5] = t[:, 0] * t[:, 2] / (t[:, 1] + t[:, 2])
     mom = np.full((8, 2), np.nan)

@@ -26,7 +26,8 @@ MAX_ACCEPT = 3968
 EXPORTED = ("vpet_abc_accept_count", "vpet_abc_simulate", "vpet_abc_infer", "vpet_abc_draws",
             "vpet_abc_bank_ld", "vpet_abc_bank_build", "vpet_abc_infer_bank", "vpet_abc_stream_bank",
             "vpet_abc_last_error", "vpet_abc_version", "vpet_proposal_init", "vpet_proposal_forward",
-            "vpet_proposal_loss_grad", "vpet_proposal_train", "vpet_abc_infer_noalloc", "vpet_abc_bank_screen")
+            "vpet_proposal_loss_grad", "vpet_proposal_train", "vpet_abc_infer_noalloc", "vpet_abc_bank_screen",
+            "vpet_abc_infer_bank_learned", "vpet_abc_stream_bank_learned")
 BANK_MAX_ACCEPT = 512
 BANK_MAX_FRAMES = 48
 PROPOSAL_NPARAM = 98912
@@ -53,7 +54,15 @@ class Opts(ctypes.Structure):
                 ("bank_scan", ctypes.c_int32), ("out_scan_ms", ctypes.POINTER(ctypes.c_float)),
                 ("out_fallback_voxels", ctypes.POINTER(ctypes.c_int64)),
                 ("proposal", ctypes.c_void_p), ("out_ess", ctypes.c_void_p),
-                ("proposal_prior_share", ctypes.c_double), ("proposal_sd_scale", ctypes.c_double)]
+                ("proposal_prior_share", ctypes.c_double), ("proposal_sd_scale", ctypes.c_double),
+                ("accept_below", ctypes.c_void_p)]
+
+
+class BankGroups(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32), ("bins", ctypes.c_int32), ("group_voxels", ctypes.c_int32),
+                ("prior_share", ctypes.c_double), ("sd_scale", ctypes.c_double), ("first_group", ctypes.c_int64),
+                ("out_group", ctypes.c_void_p), ("out_bank_theta", ctypes.c_void_p),
+                ("out_bank_logw", ctypes.c_void_p)]
 
 
 def _load():
@@ -74,12 +83,17 @@ def _load():
                                        ctypes.c_int32, i64, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_int64), P]
     L.vpet_proposal_init.argtypes = [P, u64, P]
     L.vpet_proposal_forward.argtypes = [P, P, i64, ctypes.c_int32, P, P]
-    L.vpet_proposal_loss_grad.argtypes = [P, P, P, i64, ctypes.c_int32, P, P, P]
-    L.vpet_proposal_train.argtypes = [P, P, P, i64, P, ctypes.c_int32, f64, f64, i64, ctypes.c_int32,
+    L.vpet_proposal_loss_grad.argtypes = [P, P, P, i64, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    L.vpet_proposal_train.argtypes = [P, P, P, i64, P, ctypes.c_int32, ctypes.c_int32, f64, f64, i64, ctypes.c_int32,
                                       ctypes.c_float, u64, P, P]
     L.vpet_abc_last_error.restype = ctypes.c_char_p
     L.vpet_abc_version.restype = ctypes.c_int
     L.vpet_abc_bank_screen.argtypes = [P, i64, P, Grid, P, i64, ctypes.POINTER(Opts), P, P, P]
+    L.vpet_abc_infer_bank_learned.argtypes = [P, i64, P, P, Grid, u32, P, P, ctypes.POINTER(BankGroups), i64, f64, u64,
+                                              P, P, ctypes.POINTER(Opts), P]
+    L.vpet_abc_stream_bank_learned.argtypes = [ctypes.c_char_p, i64, P, P, Grid, u32, P, P, ctypes.POINTER(BankGroups),
+                                               i64, f64, u64, i64, ctypes.c_char_p, ctypes.c_int32, i64,
+                                               ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_int64), P]
     for name in EXPORTED[:4] + EXPORTED[5:8] + EXPORTED[10:]:
         getattr(L, name).restype = ctypes.c_int
     return L
@@ -151,8 +165,8 @@ def simulate(model: int, theta, input_fn, frame_times, dt: float, out=None, stre
 
 def infer(tacs, frame_times, input_fn, dt: float, models, prior_box, n_draws: int, accept_frac: float,
           seed: int, *, weights=None, weight_floor=0.0, decay_lambda=0.0, distance="l2", debug=False,
-          voxel_offset=0, waves_per_voxel=0, proposal=None, prior_share=0.0, sd_scale=1.0, out=None,
-          stream=None, no_alloc=False) -> dict:
+          voxel_offset=0, waves_per_voxel=0, proposal=None, prior_share=0.0, sd_scale=1.0, accept_below=None,
+          out=None, stream=None, no_alloc=False) -> dict:
     """Voxelwise rejection ABC on observed TACs [V][F] (fp32, device).
 
     Returns a dict of device tensors: moments [V][M][8][2], model_prob [V][M]
@@ -160,7 +174,9 @@ def infer(tacs, frame_times, input_fn, dt: float, models, prior_box, n_draws: in
     proposal: network outputs [V][96] (proposal_forward); the draws then come
     from each voxel's mixture (with a defensive prior share prior_share and
     every sd times sd_scale), the moments are importance-weighted and "ess"
-    [V] is returned as well.  no_alloc=True calls vpet_abc_infer_noalloc
+    [V] is returned as well; accept_below [V] (fp32, device) then restricts the
+    weighted summaries to the kept draws with distance <= accept_below[v] (ABC
+    at a given threshold).  no_alloc=True calls vpet_abc_infer_noalloc
     (same results; the library allocates no device memory; pass `out` to keep
     this binding from allocating the output tensors).
     """
@@ -208,6 +224,11 @@ def infer(tacs, frame_times, input_fn, dt: float, models, prior_box, n_draws: in
         if "ess" not in res:
             res["ess"] = torch.empty((V,), dtype=torch.float32, device=dev)
         o.out_ess = res["ess"].data_ptr()
+    if accept_below is not None:
+        accept_below = _dev_f32(accept_below, "accept_below")
+        if tuple(accept_below.shape) != (V,):
+            raise ValueError("accept_below must be [V]")
+        o.accept_below = accept_below.data_ptr()
     grid = Grid(float(dt), cp.size, F)
     entry = lib.vpet_abc_infer_noalloc if no_alloc else lib.vpet_abc_infer
     _check(entry(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p), cp.ctypes.data_as(ctypes.c_void_p),
@@ -316,6 +337,96 @@ def infer_bank(tacs, frame_times, dt: float, n_nodes: int, models, n_draws: int,
     return res
 
 
+def infer_bank_learned(tacs, frame_times, input_fn, dt: float, models, prior_box, proposal, n_draws: int,
+                       accept_frac: float, seed: int, *, dims=4, bins=4, group_voxels=256, prior_share=0.1,
+                       sd_scale=1.0, weights=None, weight_floor=0.0, decay_lambda=0.0, distance="l2", debug=False,
+                       bank_pilot=0, bank_scan="auto", time_scan=False, accept_below=None, return_bank=False,
+                       first_group=0, out=None, stream=None) -> dict:
+    """Shared-bank ABC with a learned proposal: voxels grouped by their network
+    posterior (proposal [V][96] from proposal_forward with a head over `dims`
+    parameters), one bank of n_draws rows per model per group drawn from the
+    group's Gaussian mixed with the prior, rows weighted by prior / proposal.
+    Returns moments, model_prob and ess (device); with debug, accept_idx
+    (rows of the voxel's group bank), accept_dist, threshold and
+    fallback_voxels; with return_bank, group [V], bank_theta [G][M n][8] and
+    bank_logw [G][M n]; with time_scan, scan_ms."""
+    import torch
+    tacs = _dev_f32(tacs, "tacs")
+    V, F = tacs.shape
+    mask = model_mask(models)
+    M = len(models)
+    box = _host(prior_box, np.float64).reshape(M, PSTRIDE, 2)
+    cp = _host(input_fn, np.float32)
+    ft = _host(frame_times, np.float32)
+    if ft.size != F + 1:
+        raise ValueError("frame_times must have F + 1 entries")
+    proposal = _dev_f32(proposal, "proposal")
+    if tuple(proposal.shape) != (V, PROPOSAL_NOUT):
+        raise ValueError(f"proposal must be [V][{PROPOSAL_NOUT}]")
+    n = accept_count(M * int(n_draws), accept_frac)
+    dev = tacs.device
+    res = out if out is not None else {
+        "moments": torch.empty((V, M, PSTRIDE, 2), dtype=torch.float32, device=dev),
+        "model_prob": torch.empty((V, M), dtype=torch.float32, device=dev)}
+    if "ess" not in res:
+        res["ess"] = torch.empty((V,), dtype=torch.float32, device=dev)
+    if debug and "accept_idx" not in res:
+        res["accept_idx"] = torch.empty((V, n), dtype=torch.int32, device=dev)
+        res["accept_dist"] = torch.empty((V, n), dtype=torch.float32, device=dev)
+        res["threshold"] = torch.empty((V,), dtype=torch.float32, device=dev)
+    gp = BankGroups()
+    gp.dims, gp.bins, gp.group_voxels = int(dims), int(bins), int(group_voxels)
+    gp.prior_share, gp.sd_scale = float(prior_share), float(sd_scale)
+    gp.first_group = int(first_group)
+    if return_bank:
+        G = -(-V // int(group_voxels))
+        res["group"] = torch.empty((V,), dtype=torch.int32, device=dev)
+        res["bank_theta"] = torch.empty((G, M * int(n_draws), PSTRIDE), dtype=torch.float32, device=dev)
+        res["bank_logw"] = torch.empty((G, M * int(n_draws)), dtype=torch.float64, device=dev)
+        gp.out_group = res["group"].data_ptr()
+        gp.out_bank_theta = res["bank_theta"].data_ptr()
+        gp.out_bank_logw = res["bank_logw"].data_ptr()
+    o = Opts()
+    o.decay_lambda = float(decay_lambda)
+    if weights is not None:
+        weights = _dev_f32(weights, "weights")
+        if tuple(weights.shape) != (V, F):
+            raise ValueError("weights must be [V][F]")
+        o.weights = weights.data_ptr()
+    o.weight_floor_frac = float(weight_floor)
+    o.distance = {"l2": 0, "l1": 1}[distance]
+    if debug:
+        o.out_accept_idx = res["accept_idx"].data_ptr()
+        o.out_accept_dist = res["accept_dist"].data_ptr()
+        o.out_threshold = res["threshold"].data_ptr()
+    o.bank_pilot = int(bank_pilot)
+    o.bank_scan = {"auto": 0, "f64": 1, "bf16": 2}[bank_scan]
+    o.out_ess = res["ess"].data_ptr()
+    if accept_below is not None:
+        accept_below = _dev_f32(accept_below, "accept_below")
+        if tuple(accept_below.shape) != (V,):
+            raise ValueError("accept_below must be [V]")
+        o.accept_below = accept_below.data_ptr()
+    scan_ms = ctypes.c_float(0.0)
+    n_fallback = ctypes.c_int64(0)
+    if time_scan:
+        o.out_scan_ms = ctypes.pointer(scan_ms)
+    if debug:
+        o.out_fallback_voxels = ctypes.pointer(n_fallback)
+    _check(lib.vpet_abc_infer_bank_learned(_ptr(tacs), V, ft.ctypes.data_as(ctypes.c_void_p),
+                                           cp.ctypes.data_as(ctypes.c_void_p), Grid(float(dt), cp.size, F), mask,
+                                           box.ctypes.data_as(ctypes.c_void_p), _ptr(proposal), ctypes.byref(gp),
+                                           int(n_draws), float(accept_frac), int(seed) & ((1 << 64) - 1),
+                                           _ptr(res["moments"]), _ptr(res["model_prob"]), ctypes.byref(o),
+                                           _stream(stream)))
+    res["n"] = n
+    if time_scan:
+        res["scan_ms"] = float(scan_ms.value)
+    if debug:
+        res["fallback_voxels"] = int(n_fallback.value)
+    return res
+
+
 def bank_screen(tacs, frame_times, dt: float, n_nodes: int, bank_x, *, weights=None, weight_floor=0.0,
                 decay_lambda=0.0, stream=None):
     """The BF16 contraction scan's computed S [V][N] (fp32) and a_v [V] (FP64) of
@@ -371,6 +482,38 @@ def stream_bank(tacs_path: str, n_voxels: int, frame_times, dt: float, n_nodes: 
     return int(done.value)
 
 
+def stream_bank_learned(tacs_path: str, n_voxels: int, frame_times, input_fn, dt: float, models, prior_box, params,
+                        n_draws: int, accept_frac: float, seed: int, out_prefix: str, *, dims=4, bins=4,
+                        group_voxels=256, prior_share=0.1, sd_scale=1.0, chunk_voxels: int = 1 << 20,
+                        resume: bool = True, max_chunks: int = 0, weight_floor=0.0, decay_lambda=0.0,
+                        distance="l2", bank_pilot=0, bank_scan="auto", stream=None) -> int:
+    """stream_bank with a learned proposal: per chunk the network (params) and
+    infer_bank_learned; outputs as stream_bank.  Returns the completed chunks."""
+    params = _params(params)
+    ft = _host(frame_times, np.float32)
+    cp = _host(input_fn, np.float32)
+    M = len(models)
+    box = _host(prior_box, np.float64).reshape(M, PSTRIDE, 2)
+    gp = BankGroups()
+    gp.dims, gp.bins, gp.group_voxels = int(dims), int(bins), int(group_voxels)
+    gp.prior_share, gp.sd_scale = float(prior_share), float(sd_scale)
+    o = Opts()
+    o.decay_lambda = float(decay_lambda)
+    o.weight_floor_frac = float(weight_floor)
+    o.distance = {"l2": 0, "l1": 1}[distance]
+    o.bank_pilot = int(bank_pilot)
+    o.bank_scan = {"auto": 0, "f64": 1, "bf16": 2}[bank_scan]
+    done = ctypes.c_int64(0)
+    _check(lib.vpet_abc_stream_bank_learned(str(tacs_path).encode(), int(n_voxels), ft.ctypes.data_as(ctypes.c_void_p),
+                                            cp.ctypes.data_as(ctypes.c_void_p), Grid(float(dt), cp.size, ft.size - 1),
+                                            model_mask(models), box.ctypes.data_as(ctypes.c_void_p), _ptr(params),
+                                            ctypes.byref(gp), int(n_draws), float(accept_frac),
+                                            int(seed) & ((1 << 64) - 1), int(chunk_voxels), str(out_prefix).encode(),
+                                            int(bool(resume)), int(max_chunks), ctypes.byref(o), ctypes.byref(done),
+                                            _stream(stream)))
+    return int(done.value)
+
+
 def load_stream_outputs(out_prefix: str, n_voxels: int, n_models: int):
     """Read-only memory maps of a streamed run's moments [V][M][8][2] and
     model probabilities [V][M] (fp32)."""
@@ -406,9 +549,10 @@ def proposal_forward(params, tacs, out=None, stream=None):
     return out
 
 
-def proposal_loss_grad(params, tacs, theta, stream=None):
+def proposal_loss_grad(params, tacs, theta, dims=4, stream=None):
     """(loss [1], grad [PROPOSAL_NPARAM]) device tensors of one batch:
-    TACs [n][F] and parameter rows theta [n][8]."""
+    TACs [n][F] and parameter rows theta [n][8]; a head over `dims` (4 or 5)
+    parameters."""
     import torch
     params, tacs, theta = _params(params), _dev_f32(tacs, "tacs"), _dev_f32(theta, "theta")
     n, F = tacs.shape
@@ -416,15 +560,16 @@ def proposal_loss_grad(params, tacs, theta, stream=None):
         raise ValueError("theta must be [n][8]")
     g = torch.empty((PROPOSAL_NPARAM,), dtype=torch.float32, device=tacs.device)
     loss = torch.empty((1,), dtype=torch.float32, device=tacs.device)
-    _check(lib.vpet_proposal_loss_grad(_ptr(params), _ptr(tacs), _ptr(theta), n, F, _ptr(g), _ptr(loss),
+    _check(lib.vpet_proposal_loss_grad(_ptr(params), _ptr(tacs), _ptr(theta), n, F, int(dims), _ptr(g), _ptr(loss),
                                        _stream(stream)))
     return loss, g
 
 
 def proposal_train(params, bank_theta, bank_x, frame_times, *, steps: int, batch: int = 4096, lr: float = 5e-4,
-                   noise_level: float = 0.1, decay_lambda: float = 0.0, seed: int = 0, stream=None):
-    """Adam steps on params (in place) over a shared irreversible-2TCM bank;
-    returns the per-step batch losses (numpy, waits for the stream)."""
+                   noise_level: float = 0.1, decay_lambda: float = 0.0, seed: int = 0, dims: int = 4, stream=None):
+    """Adam steps on params (in place) over a shared bank (irreversible 2TCM
+    for dims = 4, reversible for dims = 5); returns the per-step batch losses
+    (numpy, waits for the stream)."""
     import torch
     params = _params(params)
     if not (bank_x.dtype == torch.float64 and bank_theta.dtype == torch.float32):
@@ -432,7 +577,7 @@ def proposal_train(params, bank_theta, bank_x, frame_times, *, steps: int, batch
     ft = _host(frame_times, np.float32)
     losses = np.zeros(int(steps), dtype=np.float32)
     _check(lib.vpet_proposal_train(_ptr(params), _ptr(bank_theta), _ptr(bank_x), int(bank_theta.shape[0]),
-                                   ft.ctypes.data_as(ctypes.c_void_p), ft.size - 1, float(noise_level),
+                                   ft.ctypes.data_as(ctypes.c_void_p), ft.size - 1, int(dims), float(noise_level),
                                    float(decay_lambda), int(steps), int(batch), float(lr),
                                    int(seed) & ((1 << 64) - 1),
                                    losses.ctypes.data_as(ctypes.c_void_p) if steps > 0 else None, _stream(stream)))

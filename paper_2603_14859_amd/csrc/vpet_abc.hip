@@ -36,6 +36,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -117,6 +118,7 @@ struct InferArgs {
     double prop_share;     // defensive prior share a of the proposal a p + (1 - a) q
     double prop_logscale;  // log of the sd scale of every mixture component
     double prop_logvol;    // sum_j log(phi_j - plo_j): minus the log prior density
+    const float* below;    // [V] given ABC thresholds (kept draws above them do not count), or nullptr
 };
 
 // ---------------------------------------------------------------------------
@@ -1094,7 +1096,27 @@ struct BankArgs {
     int* out_idx;
     float* out_dist;
     float* out_thr;
+    // Grouped banks (learned proposal): the voxels of this launch are
+    // positions pos0 + row of a grouped order, position p belongs to group
+    // p / grp_vox and is screened against that group's grp_rows bank rows,
+    // which start at row (p / grp_vox - g0) grp_rows of bank_x / bank_theta.
+    // grp_vox = 0: one bank of n_tot rows for every voxel.
+    long long pos0, g0;
+    unsigned grp_vox, grp_rows;
+    const double* bank_logw;  // [rows] log importance weight of each bank row, or nullptr (weight 1)
+    const int* out_row;       // [positions] output row of each position, or nullptr (the launch row)
+    float* out_ess;           // [V] effective sample size of the accepted weights (with bank_logw)
+    const float* below;       // [V] given ABC thresholds (by output row), or nullptr
 };
+
+// First bank row of the bank that voxel `row` of the launch is screened against.
+__device__ __forceinline__ unsigned bank_row_base(const BankArgs& P, long long row) {
+    if (P.grp_vox == 0u) return 0u;
+    return (unsigned)(((unsigned long long)(P.pos0 + row) / P.grp_vox - (unsigned long long)P.g0) * P.grp_rows);
+}
+__device__ __forceinline__ long long bank_out_row(const BankArgs& P, long long row) {
+    return P.out_row ? (long long)P.out_row[P.pos0 + row] : row;
+}
 
 // Per-lane observed curve and weights of voxel `row` (a lane per voxel).
 template <int LD, bool L1>
@@ -1184,7 +1206,9 @@ __global__ __launch_bounds__(256) void vpet_bank_scan_kernel(BankArgs P) {
     const long long row = live ? row0 : P.V - 1;
     double Y[LD], Wt[LD];
     const bool valid = lane_curve<LD, L1>(P, row, Y, Wt);
-    const cdp X = (cdp)P.bank_x;
+    // a block's 256 voxels share one bank (groups hold whole 256-voxel tiles)
+    const unsigned gb = bank_row_base(P, (long long)blockIdx.x * blockDim.x);
+    const cdp X = (cdp)(P.bank_x + (size_t)gb * LD);
     if (PILOT) {
         float top[kBankTopK];
 #pragma unroll
@@ -1208,7 +1232,7 @@ __global__ __launch_bounds__(256) void vpet_bank_scan_kernel(BankArgs P) {
         for (unsigned g = 0; g < P.n_tot; ++g) {
             const float fd = key_dist(bank_distance<LD, L1>(X + (size_t)g * LD, Y, Wt));
             if (fd <= tau) {
-                if (c < P.cap) out[c] = ((uint64_t)__float_as_uint(fd) << 32) | g;
+                if (c < P.cap) out[c] = ((uint64_t)__float_as_uint(fd) << 32) | (gb + g);
                 ++c;
             }
         }
@@ -1236,16 +1260,103 @@ __device__ __forceinline__ void bank_slot_values(int kind, const float* t, doubl
     if (kind == KIND_MRTM || kind == KIND_LPNT) val[7] = val[1] / val[2] - 1.0;
 }
 
+__device__ double block_max(double v, double* red, int nw);
+
+// Weighted outputs (bank rows with log weights, the learned-proposal bank):
+// of the n accepted keys those at or below the voxel's given threshold (if
+// any) count with weight w = exp(log w - max); per model m the probability
+// sum_m w / sum w and the weighted mean and variance sum w (t - mean)^2 /
+// sum w of every slot; the ESS (sum w)^2 / sum w^2 over every model.
+__device__ void bank_outputs_weighted(const BankArgs& P, long long row, long long orow, const uint64_t* acc,
+                                      double* red) {
+    const int n = (int)P.n_acc;
+    const int tid = threadIdx.x, nw = blockDim.x >> 6;
+    const unsigned gb = bank_row_base(P, row);
+    const float h_v = P.below ? P.below[orow] : __builtin_inff();
+    auto log_w = [&](int j, double& lw) {
+        if (acc[j] == kNoKey || !(__uint_as_float((uint32_t)(acc[j] >> 32)) <= h_v)) return false;
+        lw = P.bank_logw[(uint32_t)acc[j]];
+        return lw > -__builtin_inf();
+    };
+    double lmax = -__builtin_inf();
+    for (int j = tid; j < n; j += blockDim.x) {
+        double lw;
+        if (log_w(j, lw)) lmax = fmax(lmax, lw);
+    }
+    lmax = block_max(lmax, red, nw);
+    double tot[2] = {0.0, 0.0};  // sum w, sum w^2 over every model
+    for (int j = tid; j < n; j += blockDim.x) {
+        double lw;
+        if (!log_w(j, lw)) continue;
+        const double w = exp(lw - lmax);
+        tot[0] += w;
+        tot[1] = fma(w, w, tot[1]);
+    }
+    block_sum<2>(tot, red, nw);
+    for (int m = 0; m < P.M; ++m) {
+        const int kind = P.kinds[m];
+        double s1[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s1[q] = 0.0;
+        double val[8];
+        for (int j = tid; j < n; j += blockDim.x) {
+            double lw;
+            const uint32_t g = (uint32_t)acc[j];
+            if (!log_w(j, lw) || (g - gb) / P.n_draws != (uint32_t)m) continue;
+            const double w = exp(lw - lmax);
+            bank_slot_values(kind, P.bank_theta + (size_t)g * VPET_PSTRIDE, val);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s1[q] = fma(w, val[q], s1[q]);
+            s1[8] += w;
+        }
+        block_sum<9>(s1, red, nw);
+        const double sw = s1[8];
+        double mean[8], s2[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            mean[q] = s1[q] / sw;
+            s2[q] = 0.0;
+        }
+        for (int j = tid; j < n; j += blockDim.x) {
+            double lw;
+            const uint32_t g = (uint32_t)acc[j];
+            if (!log_w(j, lw) || (g - gb) / P.n_draws != (uint32_t)m) continue;
+            const double w = exp(lw - lmax);
+            bank_slot_values(kind, P.bank_theta + (size_t)g * VPET_PSTRIDE, val);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double dv = val[q] - mean[q];
+                s2[q] = fma(w * dv, dv, s2[q]);
+            }
+        }
+        block_sum<8>(s2, red, nw);
+        if (tid < 16) {
+            const int q = tid >> 1;
+            float outv = __builtin_nanf("");
+            if (bank_slot_used(kind, q) && sw > 0.0) outv = (tid & 1) == 0 ? (float)mean[q] : (float)(s2[q] / sw);
+            P.out_mom[((size_t)orow * P.M + m) * 16 + tid] = outv;
+        }
+        if (tid == 0) P.out_prob[(size_t)orow * P.M + m] = tot[0] > 0.0 ? (float)(sw / tot[0]) : __builtin_nanf("");
+    }
+    if (P.out_ess && tid == 0) P.out_ess[orow] = tot[0] > 0.0 ? (float)(tot[0] * tot[0] / tot[1]) : __builtin_nanf("");
+}
+
 // Outputs of one voxel from its n accepted keys (sorted, in LDS).
 __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* acc, double* red) {
     const int n = (int)P.n_acc;
     const int tid = threadIdx.x;
-    if (P.out_idx)
-        for (int j = tid; j < n; j += blockDim.x) P.out_idx[(size_t)row * n + j] = (int)(uint32_t)acc[j];
+    const long long orow = bank_out_row(P, row);
+    const unsigned gb = bank_row_base(P, row);
+    if (P.out_idx)  // rows of the voxel's own bank
+        for (int j = tid; j < n; j += blockDim.x) P.out_idx[(size_t)orow * n + j] = (int)((uint32_t)acc[j] - gb);
     if (P.out_dist)
         for (int j = tid; j < n; j += blockDim.x)
-            P.out_dist[(size_t)row * n + j] = __uint_as_float((uint32_t)(acc[j] >> 32));
-    if (P.out_thr && tid == 0) P.out_thr[row] = __uint_as_float((uint32_t)(acc[n - 1] >> 32));
+            P.out_dist[(size_t)orow * n + j] = __uint_as_float((uint32_t)(acc[j] >> 32));
+    if (P.out_thr && tid == 0) P.out_thr[orow] = __uint_as_float((uint32_t)(acc[n - 1] >> 32));
+    if (P.bank_logw) {
+        bank_outputs_weighted(P, row, orow, acc, red);
+        return;
+    }
     for (int m = 0; m < P.M; ++m) {
         const int kind = P.kinds[m];
         double s1[9];
@@ -1254,7 +1365,7 @@ __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* a
         double val[8];
         for (int j = tid; j < n; j += blockDim.x) {
             const uint32_t g = (uint32_t)acc[j];
-            if (g / P.n_draws != (uint32_t)m) continue;
+            if ((g - gb) / P.n_draws != (uint32_t)m) continue;
             bank_slot_values(kind, P.bank_theta + (size_t)g * VPET_PSTRIDE, val);
 #pragma unroll
             for (int q = 0; q < 8; ++q) s1[q] += val[q];
@@ -1270,7 +1381,7 @@ __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* a
         }
         for (int j = tid; j < n; j += blockDim.x) {
             const uint32_t g = (uint32_t)acc[j];
-            if (g / P.n_draws != (uint32_t)m) continue;
+            if ((g - gb) / P.n_draws != (uint32_t)m) continue;
             bank_slot_values(kind, P.bank_theta + (size_t)g * VPET_PSTRIDE, val);
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -1288,22 +1399,24 @@ __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* a
                 else
                     outv = (cnt > 1.0) ? (float)(s2[q] / (cnt - 1.0)) : 0.0f;
             }
-            P.out_mom[((size_t)row * P.M + m) * 16 + tid] = outv;
+            P.out_mom[((size_t)orow * P.M + m) * 16 + tid] = outv;
         }
-        if (tid == 0) P.out_prob[(size_t)row * P.M + m] = (float)(cnt / (double)n);
+        if (tid == 0) P.out_prob[(size_t)orow * P.M + m] = (float)(cnt / (double)n);
     }
 }
 
 __device__ void bank_invalid(const BankArgs& P, long long row) {
     const int n = (int)P.n_acc;
     const float qnan = __builtin_nanf("");
-    for (int j = threadIdx.x; j < P.M * 16; j += blockDim.x) P.out_mom[(size_t)row * P.M * 16 + j] = qnan;
-    for (int j = threadIdx.x; j < P.M; j += blockDim.x) P.out_prob[(size_t)row * P.M + j] = qnan;
+    const long long orow = bank_out_row(P, row);
+    for (int j = threadIdx.x; j < P.M * 16; j += blockDim.x) P.out_mom[(size_t)orow * P.M * 16 + j] = qnan;
+    for (int j = threadIdx.x; j < P.M; j += blockDim.x) P.out_prob[(size_t)orow * P.M + j] = qnan;
     if (P.out_idx)
-        for (int j = threadIdx.x; j < n; j += blockDim.x) P.out_idx[(size_t)row * n + j] = -1;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) P.out_idx[(size_t)orow * n + j] = -1;
     if (P.out_dist)
-        for (int j = threadIdx.x; j < n; j += blockDim.x) P.out_dist[(size_t)row * n + j] = qnan;
-    if (P.out_thr && threadIdx.x == 0) P.out_thr[row] = qnan;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) P.out_dist[(size_t)orow * n + j] = qnan;
+    if (P.out_thr && threadIdx.x == 0) P.out_thr[orow] = qnan;
+    if (P.out_ess && threadIdx.x == 0) P.out_ess[orow] = qnan;
 }
 
 // One wavefront per voxel: sort the candidates, keep the n smallest.  With
@@ -1406,12 +1519,13 @@ __global__ __launch_bounds__(512) void vpet_bank_fallback_kernel(BankArgs P) {
         __syncthreads();  // the previous voxel's outputs have read the keys
         for (int j = lane_id(); j < P.fb_cap; j += kWave) top.keys[j] = kNoKey;
         wave_lds_sync();
+        const unsigned gb = bank_row_base(P, row);
         for (unsigned g0 = (unsigned)wave * kWave; g0 < P.n_tot; g0 += (unsigned)nw * kWave) {
             const unsigned g = g0 + (unsigned)lane_id();
             uint64_t key[1] = {kNoKey};
             if (g < P.n_tot) {
-                const float fd = key_dist(row_distance<LD, L1>(P.bank_x + (size_t)g * LD, Y, Wt));
-                key[0] = ((uint64_t)__float_as_uint(fd) << 32) | g;
+                const float fd = key_dist(row_distance<LD, L1>(P.bank_x + (size_t)(gb + g) * LD, Y, Wt));
+                key[0] = ((uint64_t)__float_as_uint(fd) << 32) | (gb + g);
             }
             top.insert(key);
         }
@@ -1604,6 +1718,7 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
     __shared__ __align__(16) unsigned char tile[2][2][TR * RS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const long long vbase = (long long)blockIdx.x * kMfmaVox;
+    const unsigned gb = bank_row_base(P, vbase);  // the block's bank (groups hold whole 256-voxel tiles)
 
     const long long arow = vbase + wave * 32 + (lane & 31);
     bf16x8_t ah[KS], al[KS];
@@ -1664,7 +1779,7 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
         for (int u = 0; u < CPT; ++u) {
             const unsigned g = tile_row0(t) + c_row[u];
             pre[u] = make_uint4(0, 0, 0, 0);
-            if (c_has[u] && g < n_rows) pre[u] = *reinterpret_cast<const uint4*>(c_src[u] + (size_t)g * K);
+            if (c_has[u] && g < n_rows) pre[u] = *reinterpret_cast<const uint4*>(c_src[u] + (size_t)(gb + g) * K);
         }
     };
     auto stash = [&](int buf) {
@@ -1698,7 +1813,7 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
                 if ((lane >> 5) == h && ((bits >> (lane & 31)) & 1u)) {
                     const unsigned pos = base + (unsigned)__popc(bits & lt);
                     if (pos < (unsigned)P.cap)
-                        wcand[(unsigned)i * (unsigned)P.cap + pos] = ((uint64_t)__float_as_uint(acc[r]) << 32) | g;
+                        wcand[(unsigned)i * (unsigned)P.cap + pos] = ((uint64_t)__float_as_uint(acc[r]) << 32) | (gb + g);
                 }
                 cntv = lane == i ? base + (unsigned)__popc(bits) : cntv;
             }
@@ -1821,8 +1936,14 @@ void launch_mfma(dim3 grid, hipStream_t st, const BankArgs& Q) {
 // and FP32 master weights updated by Adam.  Draws from the mixture are
 // weighted by prior / proposal, so the ABC target is unchanged.
 // ===========================================================================
-constexpr int kMixC = 8, kMixD = 4;
-constexpr int kNetIn = 32, kNetH = 256, kNetOut = 96, kNetOutUsed = 72;
+constexpr int kMixC = 8, kMixD = 4;  // kMixD: the importance-weighted per-voxel path (irreversible 2TCM)
+constexpr int kMixDMax = 5;          // a head over log(K1, k2, k3, k4, vB) for the reversible model
+constexpr int kNetIn = 32, kNetH = 256, kNetOut = 96;
+// outputs in use by a head over D parameters: 8 logits, 8 x D means, 8 x D raw scales
+__host__ __device__ constexpr int net_out_used(int D) { return kMixC + 2 * kMixC * D; }
+// theta slots of the D parameters of a head: (K1, k2, k3, vB) or (K1, k2, k3, k4, vB)
+template <int D>
+__device__ __forceinline__ int head_slot(int j) { return (D == 4 && j == 3) ? VPET_SLOT_VB : j; }
 constexpr double kLS0 = -6.0, kLS1 = 2.0;
 constexpr size_t kOffW1 = 0, kOffB1 = kOffW1 + (size_t)kNetIn * kNetH, kOffW2 = kOffB1 + kNetH,
                  kOffB2 = kOffW2 + (size_t)kNetH * kNetH, kOffW3 = kOffB2 + kNetH,
@@ -1935,8 +2056,10 @@ __global__ __launch_bounds__(256) void vpet_colsum_kernel(const float* dY, long 
     if (threadIdx.x == 0) out[n] = (float)(part[0] + part[1] + part[2] + part[3]);
 }
 
-// Mean negative log density of z[b][4] under the mixture of O[b][96] and its
-// gradient dO (already divided by the batch size); loss_acc += mean.
+// Mean negative log density of z[b][D] under the mixture of O[b][96] (a head
+// over D parameters) and its gradient dO (already divided by the batch size);
+// loss_acc += mean.
+template <int D>
 __global__ __launch_bounds__(256) void vpet_mix_loss_kernel(const float* O, const float* Z, int Bn, float* dO,
                                                             float* loss_acc) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1957,10 +2080,10 @@ __global__ __launch_bounds__(256) void vpet_mix_loss_kernel(const float* O, cons
             lg[c] = (double)o[c] - lse_l;  // log pi_c
             double q = lg[c];
 #pragma unroll
-            for (int j = 0; j < kMixD; ++j) {
-                const double sg = 1.0 / (1.0 + exp(-(double)o[kMixC + kMixC * kMixD + c * kMixD + j]));
+            for (int j = 0; j < D; ++j) {
+                const double sg = 1.0 / (1.0 + exp(-(double)o[kMixC + kMixC * D + c * D + j]));
                 const double lsd = kLS0 + (kLS1 - kLS0) * sg;
-                const double t = ((double)Z[b * kMixD + j] - (double)o[kMixC + c * kMixD + j]) * exp(-lsd);
+                const double t = ((double)Z[b * D + j] - (double)o[kMixC + c * D + j]) * exp(-lsd);
                 q += -0.5 * t * t - lsd - 0.9189385332046727;  // 0.5 log(2 pi)
             }
             comp[c] = q;
@@ -1977,16 +2100,16 @@ __global__ __launch_bounds__(256) void vpet_mix_loss_kernel(const float* O, cons
             const double r = exp(comp[c] - lse);
             d[c] = (float)((exp(lg[c]) - r) * rB);
 #pragma unroll
-            for (int j = 0; j < kMixD; ++j) {
-                const double sg = 1.0 / (1.0 + exp(-(double)o[kMixC + kMixC * kMixD + c * kMixD + j]));
+            for (int j = 0; j < D; ++j) {
+                const double sg = 1.0 / (1.0 + exp(-(double)o[kMixC + kMixC * D + c * D + j]));
                 const double lsd = kLS0 + (kLS1 - kLS0) * sg;
                 const double isd = exp(-lsd);
-                const double t = ((double)Z[b * kMixD + j] - (double)o[kMixC + c * kMixD + j]) * isd;
-                d[kMixC + c * kMixD + j] = (float)(-r * t * isd * rB);
-                d[kMixC + kMixC * kMixD + c * kMixD + j] = (float)(r * (1.0 - t * t) * (kLS1 - kLS0) * sg * (1.0 - sg) * rB);
+                const double t = ((double)Z[b * D + j] - (double)o[kMixC + c * D + j]) * isd;
+                d[kMixC + c * D + j] = (float)(-r * t * isd * rB);
+                d[kMixC + kMixC * D + c * D + j] = (float)(r * (1.0 - t * t) * (kLS1 - kLS0) * sg * (1.0 - sg) * rB);
             }
         }
-        for (int q = kNetOutUsed; q < kNetOut; ++q) d[q] = 0.0f;
+        for (int q = net_out_used(D); q < kNetOut; ++q) d[q] = 0.0f;
     }
     __shared__ double part[4];
     double s = wave_sum(nll);
@@ -2035,7 +2158,8 @@ __global__ __launch_bounds__(256) void vpet_net_features_kernel(const float* tac
 // (mul coprime with n_bank); the TAC gets fresh Gaussian noise
 // sd_f = sqrt(fac_f max(x_f, 0)) (fac_f = level e^{lambda tmid_f} / dt_f,
 // normals from Philox stream 4, counter (row, e, 4, f/4)); inputs as above and
-// targets z = log(max(theta, 1e-6)) of K1, k2, k3, vB.
+// targets z = log(max(theta, 1e-6)) of the head's D parameters.
+template <int D>
 __global__ __launch_bounds__(256) void vpet_net_batch_kernel(const float* bank_theta, const double* bank_x, int ld,
                                                              long long n_bank, int F, const double* fac,
                                                              unsigned long long j0, unsigned long long mul,
@@ -2046,9 +2170,8 @@ __global__ __launch_bounds__(256) void vpet_net_batch_kernel(const float* bank_t
     const unsigned long long row = ((j0 + (unsigned long long)b) % (unsigned long long)n_bank * mul + add) %
                                    (unsigned long long)n_bank;
     const float* t = bank_theta + row * VPET_PSTRIDE;
-    const int sl[kMixD] = {0, 1, 2, 4};
 #pragma unroll
-    for (int j = 0; j < kMixD; ++j) Z[b * kMixD + j] = (float)log(fmax((double)t[sl[j]], 1e-6));
+    for (int j = 0; j < D; ++j) Z[b * D + j] = (float)log(fmax((double)t[head_slot<D>(j)], 1e-6));
     const double* x = bank_x + row * (size_t)ld;
     for (int f0 = 0; f0 < kNetIn; f0 += 4) {
         uint32_t w[4];
@@ -2431,8 +2554,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void v
 
     // weights of the accepted draws: max, then sums, then the spread
     const int nw = blockDim.x >> 6;
+    const float h_v = P.below ? P.below[row] : __builtin_inff();
     auto accepted = [&](int j, float th[kMaxParams], double& lw) {
         if (acc[j] == kNoKey) return false;
+        if (!(__uint_as_float((uint32_t)(acc[j] >> 32)) <= h_v)) return false;  // given threshold
         double z[kMixD];
         proposal_draw<true>(*mix, P.key0, P.key1, vg, (uint32_t)acc[j], th, z);
         lw = proposal_log_weight(*mix, z);
@@ -2492,6 +2617,335 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void v
         P.out_prob[row] = sw > 0.0 ? 1.0f : __builtin_nanf("");
         if (P.out_ess) P.out_ess[row] = sw > 0.0 ? (float)(sw * sw / s1[7]) : __builtin_nanf("");
     }
+}
+
+// ===========================================================================
+// Learned-proposal bank (not in the paper): the shared bank of Alg. 1 drawn
+// from a proposal fitted to a group of voxels instead of the prior.  Voxels
+// are ordered by the cell of their network posterior (a serpentine walk over
+// a grid on the prior box, so that consecutive cells are neighbours), cut into
+// groups of S consecutive voxels, and each group gets one diagonal Gaussian in
+// z = log(theta), moment-matched to its members' mixtures, mixed with the
+// prior (defensive share a).  Every bank row carries the importance weight
+// prior / proposal, so each voxel's ABC target is unchanged.
+// ===========================================================================
+constexpr int kLbMaxDims = 5;
+constexpr int kLbBlock = 1024;        // voxels per histogram / scatter block
+constexpr int kLbMaxCells = 4096;     // bins^dims
+constexpr int kLbVox = kMfmaVox;      // groups hold whole tiles of the scans
+
+struct LbArgs {
+    const float* prop;     // [V][96] network outputs
+    const float* tacs;     // [V][F]
+    const float* weights;  // [V][F] caller weights or nullptr
+    long long V;
+    int F, D, bins, ncell, nb;
+    float clo[kLbMaxDims], cwid[kLbMaxDims];  // prior box of the head's parameters (cells)
+    unsigned* key;         // [V] cell along the serpentine walk; ncell for an invalid voxel
+    double* zmom;          // [V][2 D] mixture mean and second moment of z
+    int* hist;             // [nb][ncell + 1] block counts, then output offsets
+    int* perm;             // [V] voxel at each position of the grouped order
+    long long S;           // voxels per group
+    int* out_group;        // [V] group of each voxel (optional)
+    float* ys;             // [V][F] observed curves in the grouped order
+    float* ws;             // [V][F] caller weights in the grouped order (with weights)
+};
+
+struct LbGroup {
+    float mu[kLbMaxDims], sd[kLbMaxDims];
+    int cnt;  // valid members; 0: the group's rows are prior draws
+};
+
+// Per voxel: validity (as in the bank form), the mixture moments of z and the
+// cell key.  Mixture mean m_j = sum_c pi_c mu_cj and second moment
+// s_j = sum_c pi_c (sd_cj^2 + mu_cj^2); cell coordinate j is
+// floor(bins (exp(m_j) - lo_j) / (hi_j - lo_j)) clamped to [0, bins - 1]; the
+// key walks the grid in serpentine order: coordinate j runs backwards when
+// the key of the coordinates before it is odd.
+__global__ __launch_bounds__(256) void vpet_lb_summary_kernel(LbArgs A) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= A.V) return;
+    const int D = A.D;
+    const float* y = A.tacs + (size_t)v * A.F;
+    bool bad = false;
+    float ymax = -__builtin_inff();
+    for (int f = 0; f < A.F; ++f) {
+        bad = bad || !isfinite(y[f]);
+        ymax = fmaxf(ymax, y[f]);
+        if (A.weights) {
+            const float w = A.weights[(size_t)v * A.F + f];
+            bad = bad || !(w >= 0.0f) || !isfinite(w);
+        }
+    }
+    const float* o = A.prop + (size_t)v * kNetOut;
+    double mx = -1e300;
+    for (int c = 0; c < kMixC; ++c) mx = fmax(mx, (double)o[c]);
+    double pi[kMixC], se = 0.0;
+    for (int c = 0; c < kMixC; ++c) {
+        pi[c] = exp((double)o[c] - mx);
+        se += pi[c];
+    }
+    unsigned k = 0u;
+    double* zm = A.zmom + (size_t)v * 2 * D;
+    for (int j = 0; j < D; ++j) {
+        double m = 0.0, s2 = 0.0;
+        for (int c = 0; c < kMixC; ++c) {
+            const double mu = (double)o[kMixC + c * D + j];
+            const double lsd = kLS0 + (kLS1 - kLS0) / (1.0 + exp(-(double)o[kMixC + kMixC * D + c * D + j]));
+            const double p = pi[c] / se;
+            m = fma(p, mu, m);
+            s2 = fma(p, exp(2.0 * lsd) + mu * mu, s2);
+        }
+        zm[2 * j] = m;
+        zm[2 * j + 1] = s2;
+        bad = bad || !isfinite(m) || !isfinite(s2);
+        const double t = floor((double)A.bins * (exp(m) - (double)A.clo[j]) / (double)A.cwid[j]);
+        int b = (t >= (double)A.bins) ? A.bins - 1 : (t >= 0.0 ? (int)t : 0);
+        if (k & 1u) b = A.bins - 1 - b;
+        k = k * (unsigned)A.bins + (unsigned)b;
+    }
+    A.key[v] = (bad || !(ymax > 0.0f)) ? (unsigned)A.ncell : k;
+}
+
+// Counts of each key (ncell + 1 values) in each block of kLbBlock voxels.
+__global__ __launch_bounds__(256) void vpet_lb_hist_kernel(LbArgs A) {
+    __shared__ int h[kLbMaxCells + 1];
+    for (int c = threadIdx.x; c <= A.ncell; c += blockDim.x) h[c] = 0;
+    __syncthreads();
+    const long long v0 = (long long)blockIdx.x * kLbBlock;
+    for (int i = threadIdx.x; i < kLbBlock; i += blockDim.x)
+        if (v0 + i < A.V) atomicAdd(&h[A.key[v0 + i]], 1);
+    __syncthreads();
+    for (int c = threadIdx.x; c <= A.ncell; c += blockDim.x) A.hist[(size_t)blockIdx.x * (A.ncell + 1) + c] = h[c];
+}
+
+// Block counts -> first output position of each (block, key): keys in order,
+// blocks in order within a key (one block of 1024 threads).
+__global__ __launch_bounds__(1024) void vpet_lb_offsets_kernel(LbArgs A) {
+    __shared__ int tot[kLbMaxCells + 1];
+    const int nc = A.ncell + 1;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        int run = 0;
+        for (int b = 0; b < A.nb; ++b) {
+            int* hp = A.hist + (size_t)b * nc + c;
+            const int t = *hp;
+            *hp = run;
+            run += t;
+        }
+        tot[c] = run;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int c = 0; c < nc; ++c) {
+            const int t = tot[c];
+            tot[c] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        const int base = tot[c];
+        for (int b = 0; b < A.nb; ++b) A.hist[(size_t)b * nc + c] += base;
+    }
+}
+
+// Stable placement: one wavefront per block of kLbBlock voxels walks them in
+// index order, 64 at a time; a voxel's position is its key's next free slot
+// plus the number of earlier lanes of the same round with the same key.
+__global__ __launch_bounds__(64) void vpet_lb_scatter_kernel(LbArgs A) {
+    __shared__ int next[kLbMaxCells + 1];
+    const int nc = A.ncell + 1, lane = threadIdx.x;
+    for (int c = lane; c < nc; c += kWave) next[c] = A.hist[(size_t)blockIdx.x * nc + c];
+    wave_lds_sync();
+    const long long v0 = (long long)blockIdx.x * kLbBlock;
+    for (int r = 0; r < kLbBlock / kWave; ++r) {
+        const long long v = v0 + r * kWave + lane;
+        const unsigned k = v < A.V ? A.key[v] : 0xFFFFFFFFu;
+        int before = 0, after = 0;
+        for (int q = 0; q < kWave; ++q) {
+            const unsigned kq = (unsigned)__shfl((int)k, q, kWave);
+            if (kq == k) {
+                before += q < lane ? 1 : 0;
+                after += q > lane ? 1 : 0;
+            }
+        }
+        int base = 0;
+        if (v < A.V) base = next[k];
+        wave_lds_sync();
+        if (v < A.V) {
+            A.perm[base + before] = (int)v;
+            if (after == 0) next[k] = base + before + 1;
+        }
+        wave_lds_sync();
+    }
+}
+
+// Observed curves (and caller weights) in the grouped order; each voxel's group.
+__global__ __launch_bounds__(256) void vpet_lb_gather_kernel(LbArgs A) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.V) return;
+    const long long v = A.perm[p];
+    for (int f = 0; f < A.F; ++f) A.ys[(size_t)p * A.F + f] = A.tacs[(size_t)v * A.F + f];
+    if (A.weights)
+        for (int f = 0; f < A.F; ++f) A.ws[(size_t)p * A.F + f] = A.weights[(size_t)v * A.F + f];
+    if (A.out_group) A.out_group[v] = (int)(p / A.S);
+}
+
+// One block per group: the Gaussian of each parameter moment-matched to the
+// members' mixtures, mean mu_j = avg m_j, variance avg s_j - mu_j^2 (times
+// scale^2), in FP64 with a fixed summation order, stored in fp32.
+__global__ __launch_bounds__(256) void vpet_lb_fit_kernel(LbArgs A, LbGroup* groups, double scale) {
+    __shared__ double red[kRedStride * 4];
+    const long long g = blockIdx.x;
+    const long long p0 = g * A.S, p1 = min(A.V, p0 + A.S);
+    const int D = A.D;
+    double s[2 * kLbMaxDims + 1];
+#pragma unroll
+    for (int q = 0; q < 2 * kLbMaxDims + 1; ++q) s[q] = 0.0;
+    for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const long long v = A.perm[p];
+        if (A.key[v] >= (unsigned)A.ncell) continue;
+        const double* zm = A.zmom + (size_t)v * 2 * D;
+        for (int q = 0; q < 2 * D; ++q) s[q] += zm[q];
+        s[2 * kLbMaxDims] += 1.0;
+    }
+    block_sum<2 * kLbMaxDims + 1>(s, red, blockDim.x >> 6);
+    if (threadIdx.x == 0) {
+        LbGroup G;
+        const double cnt = s[2 * kLbMaxDims];
+        G.cnt = (int)cnt;
+        for (int j = 0; j < kLbMaxDims; ++j) {
+            G.mu[j] = 0.0f;
+            G.sd[j] = 1.0f;
+            if (j < D && cnt > 0.0) {
+                const double mu = s[2 * j] / cnt;
+                const double var = fmax(s[2 * j + 1] / cnt - mu * mu, 1e-12);
+                G.mu[j] = (float)mu;
+                G.sd[j] = (float)(sqrt(var) * scale);
+            }
+        }
+        groups[g] = G;
+    }
+}
+
+struct LbBank {
+    const LbGroup* groups;
+    long long g0;        // first group of this launch
+    long long first;     // added to the group index in the Philox counter
+    int D, dim_of[kMaxParams];  // head parameter of each model parameter, -1: drawn from the prior
+    double share, log_share, log_rest;
+    unsigned n_draws, rows_per_group, key0, key1;
+    float* theta;        // [groups][rows_per_group][8] (this launch's groups)
+    double* x;           // [groups][rows_per_group][ld]
+    double* logw;        // [groups][rows_per_group]
+    int ld;
+};
+
+struct NanOrBankSink {
+    double* row;  // bank row, or nullptr for a padding lane
+    bool valid;
+    __device__ __forceinline__ void operator()(int f, int n, const double (&X)[1]) {
+        if (row) row[f] = valid ? X[0] / (double)n : __builtin_nan("");
+    }
+};
+
+// Bank row i of model m (list position) of group g = g0 + blockIdx.y: Philox
+// stream 3, counters (i, first + g, 3, m << 16 | 0) and (i, first + g, 3,
+// m << 16 | 1).
+// u0 = ((w0 & 255) | (w1 & 255) << 8 | (w2 & 255) << 16) 2^-24 below the
+// share (or an empty group) draws every parameter uniformly from the box;
+// otherwise parameter p with a head parameter d gets z_p = mu_d + sd_d n_p,
+// theta_p = fp32(exp(z_p)) (invalid outside the box), and a parameter
+// without one (k4 under a four-parameter head) is uniform from u_6.  u_p =
+// (w_p >> 8) 2^-24 for p < 4, u_4, u_5, u_6 = (v0, v1, v2 >> 8) 2^-24 (the
+// second block is drawn for five-parameter models only); normals n_{2q},
+// n_{2q+1} = r cos, r sin (2 pi u_{2q+1}), r = sqrt(-2 ln(u_{2q} + 2^-24));
+// a uniform draw is theta_p = fp32(lo_p + u wid_p) with lo_p and wid_p = hi_p
+// - lo_p in fp32.  log w = -log(a + (1 - a) e^L), L = sum
+// over the head's parameters of log N(z_p; mu, sd) - z_p + log(hi_p - lo_p)
+// (z_p = log theta_p for a uniform draw); an invalid row has log w = -inf and
+// NaN curves.
+template <int KIND>
+__global__ __launch_bounds__(256) void vpet_lb_bank_kernel(LbBank B, ModelDev md, int m, Tab T, double C0, double h,
+                                                           int F, int k0) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < B.n_draws;
+    const unsigned ii = live ? i : B.n_draws - 1;
+    const long long g = B.g0 + blockIdx.y;
+    const LbGroup G = B.groups[g];
+    uint32_t w[4], v[4] = {0u, 0u, 0u, 0u};
+    const uint32_t gc = (uint32_t)(B.first + g);
+    philox10(ii, gc, 3u, (uint32_t)m << 16, B.key0, B.key1, w);
+    if (md.np > 4) philox10(ii, gc, 3u, ((uint32_t)m << 16) | 1u, B.key0, B.key1, v);
+    const double u0 = (double)((w[0] & 255u) | (w[1] & 255u) << 8 | (w[2] & 255u) << 16) * 0x1p-24;
+    double u[7];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = (double)(w[q] >> 8) * 0x1p-24;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) u[4 + q] = (double)(v[q] >> 8) * 0x1p-24;
+    const bool prior = G.cnt == 0 || u0 < B.share;
+    float th[kMaxParams];
+    double z[kMaxParams];
+    bool ok = true;
+    double L = 0.0;
+#pragma unroll
+    for (int p = 0; p < kMaxParams; ++p) {
+        th[p] = 0.0f;
+        z[p] = 0.0;
+    }
+    for (int p = 0; p < md.np; ++p) {
+        const double lo = (double)md.lo[p], wid = (double)md.wid[p];
+        const int d = B.dim_of[p];
+        if (prior || d < 0 || wid == 0.0) {
+            th[p] = (float)(lo + (prior || wid == 0.0 ? u[p] : u[6]) * wid);
+            z[p] = log((double)th[p]);
+        } else {
+            const int q = p >> 1;  // Box-Muller pair (u_{2q}, u_{2q+1})
+            const double r = sqrt(-2.0 * log_pos(u[2 * q] + 0x1p-24));
+            double sn, cs;
+            sincospi(2.0 * u[2 * q + 1], &sn, &cs);
+            const double nrm = (p & 1) ? r * sn : r * cs;
+            z[p] = (double)G.mu[d] + (double)G.sd[d] * nrm;
+            th[p] = (float)exp_series(z[p]);
+            ok = ok && th[p] >= md.lo[p] && (double)th[p] <= lo + wid;
+        }
+        if (d >= 0 && wid > 0.0 && G.cnt > 0) {
+            const double t = (z[p] - (double)G.mu[d]) / (double)G.sd[d];
+            L += -0.5 * t * t - log((double)G.sd[d]) - 0.9189385332046727 - z[p] + log(wid);
+        }
+    }
+    double lw = 0.0;
+    if (G.cnt > 0) {
+        if (!isfinite(L)) {
+            lw = L > 0.0 ? -__builtin_inf() : -B.log_share;  // q / p = 0: weight 1 / a
+        } else if (B.share == 0.0) {
+            lw = -L;
+        } else {
+            const double x = B.log_share, y = B.log_rest + L;  // -logaddexp(x, y)
+            const double mxy = fmax(x, y);
+            lw = -(mxy + log1p(exp(-fabs(x - y))));
+        }
+    }
+    if (!ok) lw = -__builtin_inf();
+    const size_t row = (size_t)blockIdx.y * B.rows_per_group + (size_t)m * B.n_draws + ii;
+    if (live) {
+        float* to = B.theta + row * VPET_PSTRIDE;
+        for (int q = 0; q < VPET_PSTRIDE; ++q) to[q] = __builtin_nanf("");
+        for (int q = 0; q < md.np; ++q) to[md.slot[q]] = th[q];
+        B.logw[row] = lw;
+        double* xr = B.x + row * (size_t)B.ld;
+        for (int f = F; f < B.ld; ++f) xr[f] = 0.0;
+    }
+    if (!ok) {  // an in-box stand-in keeps the recursion finite; the row's curve is NaN
+        for (int p = 0; p < md.np; ++p) th[p] = md.lo[p];
+        th[1] = md.lo[1] + md.wid[1];
+    }
+    NanOrBankSink sink{live ? B.x + row * (size_t)B.ld : nullptr, ok};
+    constexpr int NE = ModelTraits<KIND>::NE;
+    DrawState<NE, 1> s;
+    setup<KIND, NE, 1>(th, h, C0, s, 0);
+    simulate_draws<KIND, 1>(T, F, k0, s, sink);
 }
 
 // Table staging for the allocation-free entry point: 1 KB of table bytes per
@@ -2868,6 +3322,68 @@ int pow2_at_least(int x) {
 // ===========================================================================
 // C ABI.
 // ===========================================================================
+namespace {
+// BF16 hi/lo operands B_g = [x_g, x_g^2] of the first `rows` bank rows.
+void bank_bops(BankArgs A, unsigned rows, hipStream_t st, int ld) {
+    A.n_tot = rows;
+    const dim3 gb((rows + 255) / 256), b256(256);
+    switch (ld) {
+        case 8: hipLaunchKernelGGL((vpet_bank_bops_kernel<8>), gb, b256, 0, st, A); break;
+        case 16: hipLaunchKernelGGL((vpet_bank_bops_kernel<16>), gb, b256, 0, st, A); break;
+        case 24: hipLaunchKernelGGL((vpet_bank_bops_kernel<24>), gb, b256, 0, st, A); break;
+        case 32: hipLaunchKernelGGL((vpet_bank_bops_kernel<32>), gb, b256, 0, st, A); break;
+        case 40: hipLaunchKernelGGL((vpet_bank_bops_kernel<40>), gb, b256, 0, st, A); break;
+        default: hipLaunchKernelGGL((vpet_bank_bops_kernel<48>), gb, b256, 0, st, A); break;
+    }
+}
+
+// One voxel chunk of the bank form: reset, (BF16 voxel operands,) pilot,
+// scan, select and the exact fallback; mark(0) / mark(1) bracket the scan.
+template <class Mark>
+void bank_chunk(const BankArgs& Q, hipStream_t st, int ld, bool l1, bool mfma, size_t lds, size_t fb_lds,
+                int fb_waves, Mark& mark) {
+    const dim3 lanes((unsigned)((Q.V + 255) / 256)), b256(256), per_voxel((unsigned)Q.V), b64(64);
+    const dim3 mblocks((unsigned)((Q.V + kMfmaVox - 1) / kMfmaVox));
+    const dim3 fb_grid((unsigned)std::min<long long>(Q.V, 2048)), fb_block(64 * fb_waves), one(1);
+#define VPET_BANK_LAUNCH(LDV, L1V)                                                                        \
+    do {                                                                                                  \
+        hipLaunchKernelGGL(vpet_bank_reset_kernel, one, one, 0, st, Q);                                   \
+        if (mfma) {                                                                                       \
+            hipLaunchKernelGGL((vpet_bank_aops_kernel<LDV>), lanes, b256, 0, st, Q);                      \
+            launch_mfma<2 * LDV, true>(mblocks, st, Q);                                                   \
+            mark(0);                                                                                      \
+            launch_mfma<2 * LDV, false>(mblocks, st, Q);                                                  \
+            mark(1);                                                                                      \
+            hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, true>), per_voxel, b64, lds, st, Q);    \
+        } else {                                                                                          \
+            hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, true>), lanes, b256, 0, st, Q);           \
+            mark(0);                                                                                      \
+            hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, false>), lanes, b256, 0, st, Q);          \
+            mark(1);                                                                                      \
+            hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, false>), per_voxel, b64, lds, st, Q);   \
+        }                                                                                                 \
+        hipLaunchKernelGGL((vpet_bank_fallback_kernel<LDV, L1V>), fb_grid, fb_block, fb_lds, st, Q);      \
+    } while (0)
+    const int sel = (ld / 8) * 2 + (l1 ? 1 : 0);
+    switch (sel) {
+        case 2: VPET_BANK_LAUNCH(8, false); break;
+        case 3: VPET_BANK_LAUNCH(8, true); break;
+        case 4: VPET_BANK_LAUNCH(16, false); break;
+        case 5: VPET_BANK_LAUNCH(16, true); break;
+        case 6: VPET_BANK_LAUNCH(24, false); break;
+        case 7: VPET_BANK_LAUNCH(24, true); break;
+        case 8: VPET_BANK_LAUNCH(32, false); break;
+        case 9: VPET_BANK_LAUNCH(32, true); break;
+        case 10: VPET_BANK_LAUNCH(40, false); break;
+        case 11: VPET_BANK_LAUNCH(40, true); break;
+        case 12: VPET_BANK_LAUNCH(48, false); break;
+        default: VPET_BANK_LAUNCH(48, true); break;
+    }
+#undef VPET_BANK_LAUNCH
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* vpet_abc_last_error(void) { return g_err.c_str(); }
@@ -2980,8 +3496,8 @@ static int infer_entry(bool noalloc, const float* tacs, int64_t n_voxels, const 
         P.prop_logscale = std::log(scale);
         P.prop = o.proposal;
         P.out_ess = o.out_ess;
-    } else if (o.out_ess) {
-        return fail(VPET_E_ARG, "opts.out_ess needs opts.proposal");
+    } else if (o.out_ess || o.accept_below) {
+        return fail(VPET_E_ARG, "opts.out_ess and opts.accept_below need opts.proposal");
     }
     const double lambda = o.decay_lambda > 0.0 ? o.decay_lambda : std::log(2.0) / 109.8;
     HostTab T;
@@ -3049,6 +3565,7 @@ static int infer_entry(bool noalloc, const float* tacs, int64_t n_voxels, const 
         Q.out_thr = o.out_threshold ? o.out_threshold + base : nullptr;
         Q.prop = o.proposal ? o.proposal + (size_t)base * VPET_PROPOSAL_NOUT : nullptr;
         Q.out_ess = o.out_ess ? o.out_ess + base : nullptr;
+        Q.below = o.accept_below ? o.accept_below + base : nullptr;
         const dim3 grid((unsigned)Q.V), block(kWave * wpv);
         const int sel = o.proposal ? -1 - o.distance : (M == 1 ? kinds[0] : 0) * 2 + (o.distance == 1 ? 1 : 0);
         switch (sel) {
@@ -3190,6 +3707,8 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     if (o.bank_scan < 0 || o.bank_scan > 2) return fail(VPET_E_ARG, "opts.bank_scan must be 0, 1 or 2");
     if (o.bank_scan == 2 && o.distance == 1)
         return fail(VPET_E_ARG, "the bf16 contraction scan needs the L2 distance");
+    if (o.proposal || o.out_ess || o.accept_below)
+        return fail(VPET_E_ARG, "opts.proposal, opts.out_ess and opts.accept_below do not apply to a prior bank");
     const bool use_mfma = o.bank_scan == 2 || (o.bank_scan == 0 && o.distance == 0);
     int64_t n_acc = 0;
     int rc = vpet_abc_accept_count((int64_t)M * n_draws, accept_frac, &n_acc);
@@ -3309,15 +3828,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         if (me != hipSuccess && rc == VPET_OK) rc = hip_fail(me, "hipEventRecord");
     };
     if (mfma) {
-        const dim3 gb((unsigned)((n_tot + 255) / 256)), b256(256);
-        switch (ld) {
-            case 8: hipLaunchKernelGGL((vpet_bank_bops_kernel<8>), gb, b256, 0, st, A); break;
-            case 16: hipLaunchKernelGGL((vpet_bank_bops_kernel<16>), gb, b256, 0, st, A); break;
-            case 24: hipLaunchKernelGGL((vpet_bank_bops_kernel<24>), gb, b256, 0, st, A); break;
-            case 32: hipLaunchKernelGGL((vpet_bank_bops_kernel<32>), gb, b256, 0, st, A); break;
-            case 40: hipLaunchKernelGGL((vpet_bank_bops_kernel<40>), gb, b256, 0, st, A); break;
-            default: hipLaunchKernelGGL((vpet_bank_bops_kernel<48>), gb, b256, 0, st, A); break;
-        }
+        bank_bops(A, (unsigned)n_tot, st, ld);
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "bank operand launch");
     }
@@ -3331,44 +3842,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         Q.out_idx = o.out_accept_idx ? o.out_accept_idx + (size_t)base * n_acc : nullptr;
         Q.out_dist = o.out_accept_dist ? o.out_accept_dist + (size_t)base * n_acc : nullptr;
         Q.out_thr = o.out_threshold ? o.out_threshold + base : nullptr;
-        const dim3 lanes((unsigned)((Q.V + 255) / 256)), b256(256), per_voxel((unsigned)Q.V), b64(64);
-        const dim3 mblocks((unsigned)((Q.V + kMfmaVox - 1) / kMfmaVox));
-        const dim3 fb_grid((unsigned)std::min<long long>(Q.V, 2048)), fb_block(64 * fb_waves), one(1);
-#define VPET_BANK_LAUNCH(LDV, L1V)                                                                        \
-    do {                                                                                                  \
-        hipLaunchKernelGGL(vpet_bank_reset_kernel, one, one, 0, st, Q);                                   \
-        if (mfma) {                                                                                       \
-            hipLaunchKernelGGL((vpet_bank_aops_kernel<LDV>), lanes, b256, 0, st, Q);                      \
-            launch_mfma<2 * LDV, true>(mblocks, st, Q);                                                   \
-            mark(0);                                                                                      \
-            launch_mfma<2 * LDV, false>(mblocks, st, Q);                                                  \
-            mark(1);                                                                                      \
-            hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, true>), per_voxel, b64, lds, st, Q);    \
-        } else {                                                                                          \
-            hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, true>), lanes, b256, 0, st, Q);           \
-            mark(0);                                                                                      \
-            hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, false>), lanes, b256, 0, st, Q);          \
-            mark(1);                                                                                      \
-            hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, false>), per_voxel, b64, lds, st, Q);   \
-        }                                                                                                 \
-        hipLaunchKernelGGL((vpet_bank_fallback_kernel<LDV, L1V>), fb_grid, fb_block, fb_lds, st, Q);      \
-    } while (0)
-        const int sel = (ld / 8) * 2 + (o.distance == 1 ? 1 : 0);
-        switch (sel) {
-            case 2: VPET_BANK_LAUNCH(8, false); break;
-            case 3: VPET_BANK_LAUNCH(8, true); break;
-            case 4: VPET_BANK_LAUNCH(16, false); break;
-            case 5: VPET_BANK_LAUNCH(16, true); break;
-            case 6: VPET_BANK_LAUNCH(24, false); break;
-            case 7: VPET_BANK_LAUNCH(24, true); break;
-            case 8: VPET_BANK_LAUNCH(32, false); break;
-            case 9: VPET_BANK_LAUNCH(32, true); break;
-            case 10: VPET_BANK_LAUNCH(40, false); break;
-            case 11: VPET_BANK_LAUNCH(40, true); break;
-            case 12: VPET_BANK_LAUNCH(48, false); break;
-            default: VPET_BANK_LAUNCH(48, true); break;
-        }
-#undef VPET_BANK_LAUNCH
+        bank_chunk(Q, st, ld, o.distance == 1, mfma, lds, fb_lds, fb_waves, mark);
         e = hipGetLastError();
         if (e != hipSuccess) rc = hip_fail(e, "bank infer launch");
         if (o.out_fallback_voxels && rc == VPET_OK) {
@@ -3388,6 +3862,329 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     }
     for (hipEvent_t ev : tev)
         if (ev) (void)hipEventDestroy(ev);  // after the waits above: nothing pending
+    e = hipFreeAsync(work, st);
+    if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipFreeAsync");
+    e = hipEventRecord(ctx->ev[slot], st);
+    if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipEventRecord");
+    return rc;
+}
+
+
+int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float* frame_times, const float* input_fn,
+                                vpet_grid grid, uint32_t model_id, const double* prior_box, const float* proposal,
+                                const vpet_bank_groups* groups, int64_t n_draws, double accept_frac, uint64_t seed,
+                                float* out_moments, float* out_model_prob, const vpet_abc_opts* opts,
+                                void* hip_stream) {
+    int kinds[kMaxModels];
+    const int M = model_list(model_id, kinds);
+    if (M < 1 || (model_id & ~(uint32_t)(VPET_M_2TCM_IRR | VPET_M_2TCM_REV)) != 0u)
+        return fail(VPET_E_MODEL, "the learned bank runs the irreversible and reversible 2TCM (model_id 0x%x)", model_id);
+    if (n_voxels < 0) return fail(VPET_E_ARG, "n_voxels must be >= 0");
+    if (!prior_box || !groups) return fail(VPET_E_ARG, "prior_box and groups must not be NULL");
+    if (n_draws < 1) return fail(VPET_E_ARG, "n_draws must be >= 1");
+    const vpet_bank_groups gp = *groups;
+    if (gp.dims != 4 && gp.dims != 5) return fail(VPET_E_ARG, "groups->dims must be 4 or 5");
+    if (gp.bins < 1) return fail(VPET_E_ARG, "groups->bins must be >= 1");
+    double ncell_d = 1.0;
+    for (int j = 0; j < gp.dims; ++j) ncell_d *= gp.bins;
+    if (ncell_d > kLbMaxCells) return fail(VPET_E_LIMIT, "bins^dims must not exceed %d", kLbMaxCells);
+    if (gp.group_voxels < kLbVox || gp.group_voxels % kLbVox != 0)
+        return fail(VPET_E_ARG, "groups->group_voxels must be a positive multiple of %d", kLbVox);
+    if (!(gp.prior_share >= 0.0 && gp.prior_share <= 1.0)) return fail(VPET_E_ARG, "groups->prior_share must lie in [0, 1]");
+    const double scale = gp.sd_scale == 0.0 ? 1.0 : gp.sd_scale;
+    if (!(std::isfinite(scale) && scale > 0.0)) return fail(VPET_E_ARG, "groups->sd_scale must be > 0");
+    if (gp.first_group < 0 || (double)gp.first_group + (double)n_voxels / gp.group_voxels + 1.0 > 4294967296.0)
+        return fail(VPET_E_ARG, "group indices (first_group + g) must lie in [0, 2^32)");
+    vpet_abc_opts o{};
+    if (opts) o = *opts;
+    if (o.proposal || o.waves_per_voxel != 0 || o.voxel_offset != 0)
+        return fail(VPET_E_ARG, "opts.proposal, waves_per_voxel and voxel_offset do not apply to the learned bank");
+    if (o.distance != 0 && o.distance != 1) return fail(VPET_E_ARG, "opts.distance must be 0 (L2) or 1 (L1)");
+    if (!(std::isfinite(o.decay_lambda) && o.decay_lambda >= 0.0))
+        return fail(VPET_E_ARG, "opts.decay_lambda must be finite and >= 0");
+    if (!(std::isfinite(o.weight_floor_frac) && o.weight_floor_frac >= 0.0f))
+        return fail(VPET_E_ARG, "opts.weight_floor_frac must be finite and >= 0");
+    if (o.bank_pilot < 0) return fail(VPET_E_ARG, "opts.bank_pilot must be >= 0");
+    if (o.bank_scan < 0 || o.bank_scan > 2) return fail(VPET_E_ARG, "opts.bank_scan must be 0, 1 or 2");
+    if (o.bank_scan == 2 && o.distance == 1) return fail(VPET_E_ARG, "the bf16 contraction scan needs the L2 distance");
+    const bool mfma = o.bank_scan == 2 || (o.bank_scan == 0 && o.distance == 0);
+    if ((double)M * (double)n_draws > 4294967295.0) return fail(VPET_E_LIMIT, "M * n_draws must stay below 2^32");
+    const int64_t n_tot = (int64_t)M * n_draws;  // bank rows per group
+    int64_t n_acc = 0;
+    int rc = vpet_abc_accept_count(n_tot, accept_frac, &n_acc);
+    if (rc != VPET_OK) return rc;
+    if (n_acc > VPET_BANK_MAX_ACCEPT)
+        return fail(VPET_E_LIMIT, "n = %lld exceeds VPET_BANK_MAX_ACCEPT = %d", (long long)n_acc, VPET_BANK_MAX_ACCEPT);
+    ModelDev md[kMaxModels] = {};
+    for (int m = 0; m < M; ++m)
+        if ((rc = fill_model(kinds[m], prior_box + (size_t)m * VPET_PSTRIDE * 2, md[m])) != VPET_OK) return rc;
+    const double lambda = o.decay_lambda > 0.0 ? o.decay_lambda : std::log(2.0) / 109.8;
+    HostTab T;
+    if ((rc = make_tables(input_fn, frame_times, grid, lambda, T)) != VPET_OK) return rc;
+    const int F = T.F;
+    if (F > VPET_BANK_MAX_FRAMES) return fail(VPET_E_LIMIT, "the bank form supports up to %d frames", VPET_BANK_MAX_FRAMES);
+    std::vector<double> omega;
+    if ((rc = bank_omega(frame_times, grid, o.decay_lambda, omega)) != VPET_OK) return rc;
+    if (n_voxels == 0) return VPET_OK;
+    if (!tacs || !proposal || !out_moments || !out_model_prob)
+        return fail(VPET_E_ARG, "tacs, proposal and output pointers must not be NULL");
+    if (n_voxels > (int64_t)INT32_MAX) return fail(VPET_E_LIMIT, "at most 2^31 - 1 voxels per call");
+
+    // the head parameter of each model parameter (draw order K1, k2, k3, [k4,] vB)
+    LbBank LB{};
+    const int S = gp.group_voxels;
+    const int64_t G = (n_voxels + S - 1) / S;
+    const int ld = vpet_abc_bank_ld(F);
+    const int KB = 2 * ld;
+    // device scratch of the grouping (whole call) and of one voxel chunk; a
+    // chunk holds whole groups, its candidate list stays within 4 GiB and its
+    // banks within 4 GiB
+    const int cap = mfma ? std::max(512, std::min(4096, pow2_at_least(16 * (int)n_acc)))
+                         : std::max(256, pow2_at_least(8 * (int)n_acc));
+    const size_t row_bytes = sizeof(float) * VPET_PSTRIDE + sizeof(double) * (size_t)ld + sizeof(double) +
+                             (mfma ? 2 * sizeof(uint16_t) * (size_t)KB : 0);
+    long long cv = std::max<long long>(S, (1LL << 32) / ((long long)cap * (long long)sizeof(uint64_t)));
+    cv = std::max<long long>(S, std::min<long long>(cv, (long long)((1ULL << 32) / (row_bytes * (size_t)n_tot)) * S));
+    cv = std::max<long long>(S, (cv / S) * S);
+    cv = std::min<long long>(cv, ((n_voxels + S - 1) / S) * S);
+    const long long gpc = cv / S;  // groups per chunk
+    if ((double)gpc * (double)n_tot > 4294967295.0) return fail(VPET_E_LIMIT, "groups x bank rows must stay below 2^32");
+    const int D = gp.dims;
+    const int ncell = (int)ncell_d;
+    const long long V = n_voxels;
+    const int nb = (int)((V + kLbBlock - 1) / kLbBlock);
+    auto a256 = [](size_t b) { return align256(b); };
+    const size_t sz_key = a256(sizeof(unsigned) * V), sz_zm = a256(sizeof(double) * 2 * D * V),
+                 sz_hist = a256(sizeof(int) * (size_t)nb * (ncell + 1)), sz_perm = a256(sizeof(int) * V),
+                 sz_ys = a256(sizeof(float) * (size_t)F * V), sz_ws = o.weights ? sz_ys : 0,
+                 sz_grp = a256(sizeof(LbGroup) * G);
+    const size_t rows_c = (size_t)gpc * n_tot;
+    const size_t sz_bt = gp.out_bank_theta ? 0 : a256(sizeof(float) * VPET_PSTRIDE * rows_c),
+                 sz_bx = a256(sizeof(double) * (size_t)ld * rows_c),
+                 sz_bw = gp.out_bank_logw ? 0 : a256(sizeof(double) * rows_c),
+                 sz_b = mfma ? a256(sizeof(uint16_t) * (size_t)KB * rows_c) : 0;
+    const size_t sz_tau = a256(sizeof(float) * cv), sz_cnt = a256(sizeof(int) * cv),
+                 sz_fb = a256(sizeof(int) * cv) + 256, sz_cand = a256(sizeof(uint64_t) * (size_t)cap * cv),
+                 sz_a = mfma ? a256(sizeof(uint16_t) * (size_t)KB * cv) : 0, sz_c = mfma ? a256(sizeof(float) * cv) : 0,
+                 sz_av = mfma ? a256(sizeof(double) * cv) : 0;
+    const size_t total = sz_key + sz_zm + sz_hist + sz_perm + 2 * sz_ys + sz_ws + sz_grp + sz_bt + sz_bx + sz_bw +
+                         2 * sz_b + sz_tau + sz_cnt + sz_fb + sz_cand + 2 * sz_a + 3 * sz_c + sz_av;
+
+    DevCtx* ctx;
+    if ((rc = current_ctx(&ctx)) != VPET_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int slot;
+    Tab tab;
+    if ((rc = upload_tables(*ctx, T, st, tab, slot)) != VPET_OK) return rc;
+    // the weights' decay factors sit in the same slot, after the tables
+    const size_t off_om = align256(tab_layout(T).bytes);
+    if (off_om + sizeof(double) * F > kSlotBytes) {
+        (void)hipEventRecord(ctx->ev[slot], st);
+        return fail(VPET_E_LIMIT, "tables exceed a slot");
+    }
+    std::memcpy(ctx->hbuf + (size_t)slot * kSlotBytes + off_om, omega.data(), sizeof(double) * F);
+    double* d_omega = reinterpret_cast<double*>(ctx->dbuf + (size_t)slot * kSlotBytes + off_om);
+    hipError_t e = hipMemcpyAsync(d_omega, ctx->hbuf + (size_t)slot * kSlotBytes + off_om, sizeof(double) * F,
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "omega upload");
+    char* work = nullptr;
+    e = hipMallocAsync((void**)&work, total, st);
+    if (e != hipSuccess) {
+        (void)hipEventRecord(ctx->ev[slot], st);
+        return fail(VPET_E_NOMEM, "learned bank work: %s", hipGetErrorString(e));
+    }
+    char* q = work;
+    auto carve = [&](size_t b) {
+        char* r = q;
+        q += b;
+        return r;
+    };
+    LbArgs A{};
+    A.prop = proposal;
+    A.tacs = tacs;
+    A.weights = o.weights;
+    A.V = V;
+    A.F = F;
+    A.D = D;
+    A.bins = gp.bins;
+    A.ncell = ncell;
+    A.nb = nb;
+    A.S = S;
+    A.out_group = gp.out_group;
+    {
+        // cells over the box of the head's parameters (K1, k2, k3, [k4,] vB) of
+        // the last model listed (the reversible one when both are)
+        const double* box = prior_box + (size_t)(M - 1) * VPET_PSTRIDE * 2;
+        const int hs4[4] = {VPET_SLOT_K1, VPET_SLOT_K2, VPET_SLOT_K3, VPET_SLOT_VB};
+        const int hs5[5] = {VPET_SLOT_K1, VPET_SLOT_K2, VPET_SLOT_K3, VPET_SLOT_K4, VPET_SLOT_VB};
+        for (int j = 0; j < D; ++j) {
+            const int sl = D == 4 ? hs4[j] : hs5[j];
+            A.clo[j] = (float)box[2 * sl];
+            A.cwid[j] = (float)(box[2 * sl + 1] - box[2 * sl]);
+            if (!(A.cwid[j] > 0.0f)) A.cwid[j] = 1.0f;  // a fixed parameter: one cell
+        }
+    }
+    A.key = reinterpret_cast<unsigned*>(carve(sz_key));
+    A.zmom = reinterpret_cast<double*>(carve(sz_zm));
+    A.hist = reinterpret_cast<int*>(carve(sz_hist));
+    A.perm = reinterpret_cast<int*>(carve(sz_perm));
+    A.ys = reinterpret_cast<float*>(carve(sz_ys));
+    carve(sz_ys);  // reserved
+    A.ws = o.weights ? reinterpret_cast<float*>(carve(sz_ws)) : nullptr;
+    LbGroup* d_groups = reinterpret_cast<LbGroup*>(carve(sz_grp));
+    float* b_theta = gp.out_bank_theta ? nullptr : reinterpret_cast<float*>(carve(sz_bt));
+    double* b_x = reinterpret_cast<double*>(carve(sz_bx));
+    double* b_logw = gp.out_bank_logw ? nullptr : reinterpret_cast<double*>(carve(sz_bw));
+
+    BankArgs B{};
+    B.weights = A.ws;
+    B.omega = d_omega;
+    B.bank_x = b_x;
+    B.floor_frac = o.weight_floor_frac > 0.0f ? (double)o.weight_floor_frac : 0.01;
+    B.F = F;
+    B.ld = ld;
+    B.l1 = o.distance;
+    B.M = M;
+    B.cap = cap;
+    B.n_tot = (unsigned)n_tot;
+    B.n_draws = (unsigned)n_draws;
+    B.n_acc = (unsigned)n_acc;
+    int64_t pilot = o.bank_pilot > 0 ? o.bank_pilot
+                    : mfma           ? (11 * n_tot + 2 * n_acc - 1) / (2 * n_acc)
+                                     : (4 * n_tot + n_acc - 1) / n_acc;
+    B.n_pilot = (unsigned)std::min<int64_t>(pilot, n_tot);
+    for (int m = 0; m < M; ++m) B.kinds[m] = kinds[m];
+    B.K = KB;
+    if (mfma) {
+        B.bhi = reinterpret_cast<uint16_t*>(carve(sz_b));
+        B.blo = reinterpret_cast<uint16_t*>(carve(sz_b));
+    }
+    B.tau = reinterpret_cast<float*>(carve(sz_tau));
+    B.cnt = reinterpret_cast<int*>(carve(sz_cnt));
+    {
+        char* fb = carve(sz_fb);
+        B.fb_count = reinterpret_cast<unsigned*>(fb);
+        B.fb_list = reinterpret_cast<int*>(fb + 256);
+    }
+    B.cand = reinterpret_cast<uint64_t*>(carve(sz_cand));
+    if (mfma) {
+        B.ahi = reinterpret_cast<uint16_t*>(carve(sz_a));
+        B.alo = reinterpret_cast<uint16_t*>(carve(sz_a));
+        B.cthr = reinterpret_cast<float*>(carve(sz_c));
+        B.cthr1 = reinterpret_cast<float*>(carve(sz_c));
+        B.tau1 = reinterpret_cast<float*>(carve(sz_c));
+        B.aval = reinterpret_cast<double*>(carve(sz_av));
+    }
+    B.grp_vox = (unsigned)S;
+    B.grp_rows = (unsigned)n_tot;
+    B.out_row = A.perm;
+    B.out_mom = out_moments;
+    B.out_prob = out_model_prob;
+    B.out_idx = o.out_accept_idx;
+    B.out_dist = o.out_accept_dist;
+    B.out_thr = o.out_threshold;
+    B.out_ess = o.out_ess;
+    B.below = o.accept_below;
+
+    LB.groups = d_groups;
+    LB.D = D;
+    LB.share = gp.prior_share;
+    LB.log_share = std::log(gp.prior_share);
+    LB.log_rest = std::log1p(-gp.prior_share);
+    LB.n_draws = (unsigned)n_draws;
+    LB.rows_per_group = (unsigned)n_tot;
+    LB.key0 = (unsigned)(seed & 0xffffffffu);
+    LB.key1 = (unsigned)(seed >> 32);
+    LB.ld = ld;
+    LB.first = gp.first_group;
+
+    // grouping: cells, stable order, groups and their Gaussians
+    const dim3 b256(256);
+    hipLaunchKernelGGL(vpet_lb_summary_kernel, dim3((unsigned)((V + 255) / 256)), b256, 0, st, A);
+    hipLaunchKernelGGL(vpet_lb_hist_kernel, dim3((unsigned)nb), b256, 0, st, A);
+    hipLaunchKernelGGL(vpet_lb_offsets_kernel, dim3(1), dim3(1024), 0, st, A);
+    hipLaunchKernelGGL(vpet_lb_scatter_kernel, dim3((unsigned)nb), dim3(64), 0, st, A);
+    hipLaunchKernelGGL(vpet_lb_gather_kernel, dim3((unsigned)((V + 255) / 256)), b256, 0, st, A);
+    hipLaunchKernelGGL(vpet_lb_fit_kernel, dim3((unsigned)G), b256, 0, st, A, d_groups, scale);
+    e = hipGetLastError();
+    if (e != hipSuccess) rc = hip_fail(e, "grouping launch");
+
+    const size_t lds = sizeof(uint64_t) * cap + sizeof(double) * kRedStride * kMaxWpv;
+    const int fb_cap = pow2_at_least((int)n_acc + 2 * kWave);
+    int fb_waves = 8;
+    while (fb_waves > 1 && (size_t)fb_waves * fb_cap * sizeof(uint64_t) > 48 * 1024) fb_waves >>= 1;
+    const size_t fb_lds = sizeof(uint64_t) * (size_t)fb_waves * fb_cap + sizeof(double) * kRedStride * fb_waves;
+    B.fb_cap = fb_cap;
+    if (o.out_fallback_voxels) *o.out_fallback_voxels = 0;
+    hipEvent_t tev[2] = {nullptr, nullptr};
+    if (o.out_scan_ms) {
+        *o.out_scan_ms = 0.0f;
+        for (hipEvent_t& ev : tev) {
+            e = hipEventCreate(&ev);
+            if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipEventCreate");
+        }
+    }
+    auto mark = [&](int k) {
+        if (!tev[k]) return;
+        const hipError_t me = hipEventRecord(tev[k], st);
+        if (me != hipSuccess && rc == VPET_OK) rc = hip_fail(me, "hipEventRecord");
+    };
+    for (long long base = 0; base < V && rc == VPET_OK; base += cv) {
+        const long long nv = std::min<long long>(V - base, cv);
+        const long long g0 = base / S, ng = (nv + S - 1) / S;
+        // the chunk's banks
+        LB.g0 = g0;
+        LB.theta = gp.out_bank_theta ? gp.out_bank_theta + (size_t)g0 * n_tot * VPET_PSTRIDE : b_theta;
+        LB.logw = gp.out_bank_logw ? gp.out_bank_logw + (size_t)g0 * n_tot : b_logw;
+        LB.x = b_x;
+        for (int m = 0; m < M; ++m) {
+            for (int p = 0; p < kMaxParams; ++p) LB.dim_of[p] = -1;
+            // draw order K1, k2, k3, vB (irreversible) or K1, k2, k3, k4, vB
+            LB.dim_of[0] = 0;
+            LB.dim_of[1] = 1;
+            LB.dim_of[2] = 2;
+            if (kinds[m] == KIND_IRR) {
+                LB.dim_of[3] = D - 1;
+            } else {
+                LB.dim_of[3] = D == 5 ? 3 : -1;
+                LB.dim_of[4] = D - 1;
+            }
+            const dim3 bg((unsigned)((n_draws + 255) / 256), (unsigned)ng);
+            if (kinds[m] == KIND_IRR)
+                hipLaunchKernelGGL(vpet_lb_bank_kernel<KIND_IRR>, bg, b256, 0, st, LB, md[m], m, tab, T.C0, T.h, F, T.k0);
+            else
+                hipLaunchKernelGGL(vpet_lb_bank_kernel<KIND_REV>, bg, b256, 0, st, LB, md[m], m, tab, T.C0, T.h, F, T.k0);
+        }
+        BankArgs Q = B;
+        Q.bank_theta = LB.theta;
+        Q.bank_logw = LB.logw;
+        if (mfma) bank_bops(Q, (unsigned)(ng * n_tot), st, ld);
+        Q.V = nv;
+        Q.pos0 = base;
+        Q.g0 = g0;
+        Q.tacs = A.ys + (size_t)base * F;
+        Q.weights = A.ws ? A.ws + (size_t)base * F : nullptr;
+        bank_chunk(Q, st, ld, o.distance == 1, mfma, lds, fb_lds, fb_waves, mark);
+        e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_fail(e, "learned bank launch");
+        if (o.out_fallback_voxels && rc == VPET_OK) {
+            unsigned nfb = 0;
+            e = hipMemcpyAsync(&nfb, Q.fb_count, sizeof nfb, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) rc = hip_fail(e, "fallback count");
+            *o.out_fallback_voxels += nfb;
+        }
+        if (tev[0] && rc == VPET_OK) {
+            e = hipEventSynchronize(tev[1]);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, tev[0], tev[1]);
+            if (e != hipSuccess) rc = hip_fail(e, "scan timing");
+            *o.out_scan_ms += ms;
+        }
+    }
+    for (hipEvent_t ev : tev)
+        if (ev) (void)hipEventDestroy(ev);
     e = hipFreeAsync(work, st);
     if (e != hipSuccess && rc == VPET_OK) rc = hip_fail(e, "hipFreeAsync");
     e = hipEventRecord(ctx->ev[slot], st);
@@ -3526,12 +4323,12 @@ bool pwrite_all(int fd, const void* buf, size_t bytes, off_t off) {
     return true;
 }
 
-// The progress line names the run's shape so that a resume cannot continue
-// a different run.
-std::string progress_line(int64_t V, int F, int M, int64_t chunk, int64_t done) {
+// The progress line names the run's kind and shape so that a resume cannot
+// continue a different run.
+std::string progress_line(const char* kind, int64_t V, int F, int M, int64_t chunk, int64_t done) {
     char buf[192];
-    snprintf(buf, sizeof buf, "vpet_abc_stream v1 voxels=%lld frames=%d models=%d chunk=%lld done=%lld\n",
-             (long long)V, F, M, (long long)chunk, (long long)done);
+    snprintf(buf, sizeof buf, "%s v1 voxels=%lld frames=%d models=%d chunk=%lld done=%lld\n", kind, (long long)V, F,
+             M, (long long)chunk, (long long)done);
     return buf;
 }
 
@@ -3579,26 +4376,18 @@ struct StreamBuffers {
 
 extern "C" {
 
-int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* frame_times, vpet_grid grid,
-                         uint32_t model_id, int64_t n_draws, double accept_frac, const float* bank_theta,
-                         const double* bank_x, int64_t chunk_voxels, const char* out_prefix, int32_t resume,
-                         int64_t max_chunks, const vpet_abc_opts* opts, int64_t* out_done, void* hip_stream) {
-    if (out_done) *out_done = 0;
-    vpet_abc_opts o{};
-    if (opts) o = *opts;
-    if (o.weights || o.out_accept_idx || o.out_accept_dist || o.out_threshold || o.out_scan_ms ||
-        o.out_fallback_voxels)
-        return fail(VPET_E_ARG, "streaming takes no caller weights, debug outputs or reports");
-    // everything vpet_abc_infer_bank checks, without work (0 voxels)
-    int rc = vpet_abc_infer_bank(nullptr, 0, frame_times, grid, model_id, n_draws, accept_frac, bank_theta, bank_x,
-                                 nullptr, nullptr, &o, hip_stream);
-    if (rc != VPET_OK) return rc;
-    if (!tacs_path || !out_prefix) return fail(VPET_E_ARG, "tacs_path and out_prefix must not be NULL");
-    if (n_voxels < 0 || chunk_voxels < 1 || max_chunks < 0)
-        return fail(VPET_E_ARG, "need n_voxels >= 0, chunk_voxels >= 1, max_chunks >= 0");
-    if (!bank_theta || !bank_x) return fail(VPET_E_ARG, "bank pointers must not be NULL");
-    const int F = grid.n_frames;
-    const int M = __builtin_popcount(model_id);
+}  // extern "C"
+
+namespace {
+
+// Runs `run` (device input chunk -> device output chunk, enqueued on st) over
+// a volume in a file with two chunks in flight and resumable progress.
+using ChunkRun = std::function<int(const float* d_in, int64_t rows, float* d_mom, float* d_prob, int64_t chunk)>;
+
+int stream_driver(const char* kind, const char* tacs_path, int64_t n_voxels, int F, int M, int64_t chunk_voxels,
+                  const char* out_prefix, int32_t resume, int64_t max_chunks, int64_t* out_done, hipStream_t st,
+                  const ChunkRun& run) {
+    int rc = VPET_OK;
     const int64_t chunk = std::min<int64_t>(chunk_voxels, std::max<int64_t>(n_voxels, 1));
     const int64_t nchunks = (n_voxels + chunk - 1) / chunk;
     const size_t in_row = sizeof(float) * (size_t)F, mom_row = sizeof(float) * (size_t)M * VPET_PSTRIDE * 2,
@@ -3621,11 +4410,13 @@ int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* f
             ::close(fd);
             long long v = -1, c = -1, d = -1;
             int f = -1, m = -1;
-            if (r <= 0 || sscanf(buf, "vpet_abc_stream v1 voxels=%lld frames=%d models=%d chunk=%lld done=%lld", &v, &f,
-                                 &m, &c, &d) != 5)
+            char kbuf[64] = {0};
+            if (r <= 0 || sscanf(buf, "%63s v1 voxels=%lld frames=%d models=%d chunk=%lld done=%lld", kbuf, &v, &f, &m,
+                                 &c, &d) != 6)
                 return fail(VPET_E_IO, "unreadable progress file %s", prog_path.c_str());
-            if (v != n_voxels || f != F || m != M || c != chunk || d < 0 || d > nchunks)
-                return fail(VPET_E_ARG, "progress file %s belongs to a run of another shape", prog_path.c_str());
+            if (std::strcmp(kbuf, kind) != 0 || v != n_voxels || f != F || m != M || c != chunk || d < 0 ||
+                d > nchunks)
+                return fail(VPET_E_ARG, "progress file %s belongs to a run of another kind or shape", prog_path.c_str());
             done = d;
         }
     }
@@ -3637,14 +4428,13 @@ int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* f
         ::ftruncate(B.fds[2], (off_t)(prob_row * (size_t)n_voxels)) != 0)
         return fail(VPET_E_IO, "cannot size the output files %s.*", out_prefix);
     if (!resume || done == 0)
-        if ((rc = write_progress(prog_path, progress_line(n_voxels, F, M, chunk, 0))) != VPET_OK) return rc;
+        if ((rc = write_progress(prog_path, progress_line(kind, n_voxels, F, M, chunk, 0))) != VPET_OK) return rc;
     const int64_t last = max_chunks > 0 ? std::min<int64_t>(nchunks, done + max_chunks) : nchunks;
     if (done >= last) {
         if (out_done) *out_done = done;
         return VPET_OK;
     }
 
-    hipStream_t st = (hipStream_t)hip_stream;
     hipError_t e = hipStreamCreateWithFlags(&B.copy, hipStreamNonBlocking);
     for (int b = 0; b < 2 && e == hipSuccess; ++b) {
         e = hipHostMalloc((void**)&B.h_in[b], in_row * chunk, hipHostMallocDefault);
@@ -3680,7 +4470,7 @@ int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* f
             !pwrite_all(B.fds[2], B.h_prob[b], prob_row * n, (off_t)(prob_row * v0)) || ::fsync(B.fds[1]) != 0 ||
             ::fsync(B.fds[2]) != 0)
             return fail(VPET_E_IO, "write of %s.* failed at chunk %lld", out_prefix, (long long)c);
-        return write_progress(prog_path, progress_line(n_voxels, F, M, chunk, c + 1));
+        return write_progress(prog_path, progress_line(kind, n_voxels, F, M, chunk, c + 1));
     };
 
     if ((rc = load(done, 0)) != VPET_OK) return rc;
@@ -3688,9 +4478,7 @@ int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* f
         const int b = (int)((c - done) & 1);
         e = hipStreamWaitEvent(st, B.ev_in[b], 0);
         if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-        rc = vpet_abc_infer_bank(B.d_in[b], rows(c), frame_times, grid, model_id, n_draws, accept_frac, bank_theta,
-                                 bank_x, B.d_mom[b], B.d_prob[b], &o, hip_stream);
-        if (rc != VPET_OK) return rc;
+        if ((rc = run(B.d_in[b], rows(c), B.d_mom[b], B.d_prob[b], c)) != VPET_OK) return rc;
         e = hipMemcpyAsync(B.h_mom[b], B.d_mom[b], mom_row * (size_t)rows(c), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(B.h_prob[b], B.d_prob[b], prob_row * (size_t)rows(c), hipMemcpyDeviceToHost, st);
@@ -3703,6 +4491,86 @@ int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* f
     if ((rc = store(last - 1, (int)((last - 1 - done) & 1))) != VPET_OK) return rc;
     if (out_done) *out_done = last;
     return VPET_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vpet_abc_stream_bank(const char* tacs_path, int64_t n_voxels, const float* frame_times, vpet_grid grid,
+                         uint32_t model_id, int64_t n_draws, double accept_frac, const float* bank_theta,
+                         const double* bank_x, int64_t chunk_voxels, const char* out_prefix, int32_t resume,
+                         int64_t max_chunks, const vpet_abc_opts* opts, int64_t* out_done, void* hip_stream) {
+    if (out_done) *out_done = 0;
+    vpet_abc_opts o{};
+    if (opts) o = *opts;
+    if (o.weights || o.out_accept_idx || o.out_accept_dist || o.out_threshold || o.out_scan_ms ||
+        o.out_fallback_voxels)
+        return fail(VPET_E_ARG, "streaming takes no caller weights, debug outputs or reports");
+    // everything vpet_abc_infer_bank checks, without work (0 voxels)
+    int rc = vpet_abc_infer_bank(nullptr, 0, frame_times, grid, model_id, n_draws, accept_frac, bank_theta, bank_x,
+                                 nullptr, nullptr, &o, hip_stream);
+    if (rc != VPET_OK) return rc;
+    if (!tacs_path || !out_prefix) return fail(VPET_E_ARG, "tacs_path and out_prefix must not be NULL");
+    if (n_voxels < 0 || chunk_voxels < 1 || max_chunks < 0)
+        return fail(VPET_E_ARG, "need n_voxels >= 0, chunk_voxels >= 1, max_chunks >= 0");
+    if (!bank_theta || !bank_x) return fail(VPET_E_ARG, "bank pointers must not be NULL");
+    const int F = grid.n_frames, M = __builtin_popcount(model_id);
+    return stream_driver("vpet_abc_stream", tacs_path, n_voxels, F, M, chunk_voxels, out_prefix, resume, max_chunks,
+                         out_done, (hipStream_t)hip_stream,
+                         [&](const float* d_in, int64_t rows, float* d_mom, float* d_prob, int64_t) {
+                             return vpet_abc_infer_bank(d_in, rows, frame_times, grid, model_id, n_draws, accept_frac,
+                                                        bank_theta, bank_x, d_mom, d_prob, &o, hip_stream);
+                         });
+}
+
+int vpet_abc_stream_bank_learned(const char* tacs_path, int64_t n_voxels, const float* frame_times,
+                                 const float* input_fn, vpet_grid grid, uint32_t model_id, const double* prior_box,
+                                 const float* params, const vpet_bank_groups* groups, int64_t n_draws,
+                                 double accept_frac, uint64_t seed, int64_t chunk_voxels, const char* out_prefix,
+                                 int32_t resume, int64_t max_chunks, const vpet_abc_opts* opts, int64_t* out_done,
+                                 void* hip_stream) {
+    if (out_done) *out_done = 0;
+    vpet_abc_opts o{};
+    if (opts) o = *opts;
+    if (o.weights || o.out_accept_idx || o.out_accept_dist || o.out_threshold || o.out_scan_ms ||
+        o.out_fallback_voxels || o.out_ess || o.accept_below)
+        return fail(VPET_E_ARG, "streaming takes no caller weights, per-voxel inputs, debug outputs or reports");
+    if (!groups) return fail(VPET_E_ARG, "groups must not be NULL");
+    if (groups->out_group || groups->out_bank_theta || groups->out_bank_logw)
+        return fail(VPET_E_ARG, "streaming takes no bank outputs");
+    // everything vpet_abc_infer_bank_learned checks, without work (0 voxels)
+    int rc = vpet_abc_infer_bank_learned(nullptr, 0, frame_times, input_fn, grid, model_id, prior_box, nullptr, groups,
+                                         n_draws, accept_frac, seed, nullptr, nullptr, &o, hip_stream);
+    if (rc != VPET_OK) return rc;
+    if (!tacs_path || !out_prefix || !params)
+        return fail(VPET_E_ARG, "tacs_path, out_prefix and params must not be NULL");
+    if (grid.n_frames > 32) return fail(VPET_E_LIMIT, "the proposal network takes 1..32 frames");
+    if (n_voxels < 0 || chunk_voxels < 1 || max_chunks < 0)
+        return fail(VPET_E_ARG, "need n_voxels >= 0, chunk_voxels >= 1, max_chunks >= 0");
+    const int F = grid.n_frames, M = __builtin_popcount(model_id);
+    const int64_t chunk = std::min<int64_t>(chunk_voxels, std::max<int64_t>(n_voxels, 1));
+    float* d_prop = nullptr;
+    hipError_t e = hipMalloc((void**)&d_prop, sizeof(float) * VPET_PROPOSAL_NOUT * (size_t)chunk);
+    if (e != hipSuccess) return fail(VPET_E_NOMEM, "proposal outputs: %s", hipGetErrorString(e));
+    // chunk c's groups continue the numbering of the Philox counters
+    const int64_t groups_per_chunk = (chunk + groups->group_voxels - 1) / groups->group_voxels;
+    rc = stream_driver("vpet_abc_stream_learned", tacs_path, n_voxels, F, M, chunk_voxels, out_prefix, resume,
+                       max_chunks, out_done, (hipStream_t)hip_stream,
+                       [&](const float* d_in, int64_t rows, float* d_mom, float* d_prob, int64_t c) {
+                           int r = vpet_proposal_forward(params, d_in, rows, F, d_prop, hip_stream);
+                           if (r != VPET_OK) return r;
+                           vpet_bank_groups gc = *groups;
+                           gc.first_group = groups->first_group + c * groups_per_chunk;
+                           return vpet_abc_infer_bank_learned(d_in, rows, frame_times, input_fn, grid, model_id,
+                                                              prior_box, d_prop, &gc, n_draws, accept_frac, seed,
+                                                              d_mom, d_prob, &o, hip_stream);
+                       });
+    // every chunk's work is done (the driver waited for the last outputs) or
+    // the call failed; either way wait before freeing
+    (void)hipStreamSynchronize((hipStream_t)hip_stream);
+    (void)hipFree(d_prop);
+    return rc;
 }
 
 
@@ -3718,11 +4586,11 @@ __global__ __launch_bounds__(256) void vpet_fill_kernel(float* p, long long n, f
     if (i < n) p[i] = v;
 }
 
+template <int D>
 __global__ __launch_bounds__(256) void vpet_net_targets_kernel(const float* theta, long long n, float* Z) {
     const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
-    const int sl[kMixD] = {0, 1, 2, 4};
-    for (int j = 0; j < kMixD; ++j) Z[b * kMixD + j] = (float)log(fmax((double)theta[b * VPET_PSTRIDE + sl[j]], 1e-6));
+    for (int j = 0; j < D; ++j) Z[b * D + j] = (float)log(fmax((double)theta[b * VPET_PSTRIDE + head_slot<D>(j)], 1e-6));
 }
 
 // Activations of one batch of up to `rows` samples.
@@ -3735,7 +4603,7 @@ struct NetWork {
 constexpr int kSplitMax = 16;
 
 size_t net_work_bytes(long long rows) {
-    return sizeof(float) * ((size_t)rows * (kNetIn + 4 * kNetH + 2 * kNetOut + kMixD) +
+    return sizeof(float) * ((size_t)rows * (kNetIn + 4 * kNetH + 2 * kNetOut + kMixDMax) +
                             (size_t)kSplitMax * kNetH * kNetH) + 9 * 256;
 }
 
@@ -3753,7 +4621,7 @@ void net_work_carve(char* base, long long rows, NetWork& w) {
     w.dH2 = take((size_t)rows * kNetH);
     w.O = take((size_t)rows * kNetOut);
     w.dO = take((size_t)rows * kNetOut);
-    w.Z = take((size_t)rows * kMixD);
+    w.Z = take((size_t)rows * kMixDMax);
     w.part = take((size_t)kSplitMax * kNetH * kNetH);
 }
 
@@ -3857,9 +4725,10 @@ int vpet_proposal_forward(const float* params, const float* tacs, int64_t n, int
 }
 
 int vpet_proposal_loss_grad(const float* params, const float* tacs, const float* theta, int64_t n, int32_t n_frames,
-                            float* grad, float* loss, void* hip_stream) {
+                            int32_t dims, float* grad, float* loss, void* hip_stream) {
     int rc = check_frames(n_frames);
     if (rc != VPET_OK) return rc;
+    if (dims != 4 && dims != 5) return fail(VPET_E_ARG, "dims must be 4 or 5");
     if (n < 1 || n > (1LL << 20)) return fail(VPET_E_ARG, "n must lie in [1, 2^20]");
     if (!params || !tacs || !theta || !grad || !loss) return fail(VPET_E_ARG, "pointers must not be NULL");
     hipStream_t st = (hipStream_t)hip_stream;
@@ -3870,10 +4739,16 @@ int vpet_proposal_loss_grad(const float* params, const float* tacs, const float*
     net_work_carve(work, n, w);
     const unsigned blk = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(vpet_net_features_kernel, dim3(blk), dim3(256), 0, st, tacs, (long long)n, n_frames, w.X);
-    hipLaunchKernelGGL(vpet_net_targets_kernel, dim3(blk), dim3(256), 0, st, theta, (long long)n, w.Z);
+    if (dims == 4)
+        hipLaunchKernelGGL(vpet_net_targets_kernel<4>, dim3(blk), dim3(256), 0, st, theta, (long long)n, w.Z);
+    else
+        hipLaunchKernelGGL(vpet_net_targets_kernel<5>, dim3(blk), dim3(256), 0, st, theta, (long long)n, w.Z);
     hipLaunchKernelGGL(vpet_fill_kernel, dim3(1), dim3(256), 0, st, loss, 1LL, 0.0f);
     net_forward(st, params, w, (int)n);
-    hipLaunchKernelGGL(vpet_mix_loss_kernel, dim3(blk), dim3(256), 0, st, w.O, w.Z, (int)n, w.dO, loss);
+    if (dims == 4)
+        hipLaunchKernelGGL(vpet_mix_loss_kernel<4>, dim3(blk), dim3(256), 0, st, w.O, w.Z, (int)n, w.dO, loss);
+    else
+        hipLaunchKernelGGL(vpet_mix_loss_kernel<5>, dim3(blk), dim3(256), 0, st, w.O, w.Z, (int)n, w.dO, loss);
     net_backward(st, params, w, (int)n, grad);
     e = hipGetLastError();
     const hipError_t e2 = hipFreeAsync(work, st);
@@ -3882,12 +4757,13 @@ int vpet_proposal_loss_grad(const float* params, const float* tacs, const float*
 }
 
 int vpet_proposal_train(float* params, const float* bank_theta, const double* bank_x, int64_t n_bank,
-                        const float* frame_times, int32_t n_frames, double noise_level, double decay_lambda,
-                        int64_t steps, int32_t batch, float learning_rate, uint64_t seed, float* out_loss,
-                        void* hip_stream) {
+                        const float* frame_times, int32_t n_frames, int32_t dims, double noise_level,
+                        double decay_lambda, int64_t steps, int32_t batch, float learning_rate, uint64_t seed,
+                        float* out_loss, void* hip_stream) {
     const int F = n_frames;
     int rc = check_frames(F);
     if (rc != VPET_OK) return rc;
+    if (dims != 4 && dims != 5) return fail(VPET_E_ARG, "dims must be 4 or 5");
     if (!params || !bank_theta || !bank_x || !frame_times) return fail(VPET_E_ARG, "pointers must not be NULL");
     if (n_bank < 1 || n_bank > 4294967295LL || steps < 0 || batch < 1 || batch > (1 << 20))
         return fail(VPET_E_ARG, "need 1 <= n_bank < 2^32, steps >= 0, 1 <= batch <= 2^20");
@@ -3952,11 +4828,21 @@ int vpet_proposal_train(float* params, const float* bank_theta, const double* ba
             add = N > 1 ? (unsigned long long)c2 % N : 0;
         }
         const unsigned blk = (unsigned)((batch + 255) / 256);
-        hipLaunchKernelGGL(vpet_net_batch_kernel, dim3(blk), dim3(256), 0, st, bank_theta, bank_x, ld, (long long)n_bank,
-                           F, static_cast<const double*>(dfac), j % N, mul, add, (uint32_t)epoch, (int)batch, k0, k1,
-                           w.X, w.Z);
+        if (dims == 4)
+            hipLaunchKernelGGL(vpet_net_batch_kernel<4>, dim3(blk), dim3(256), 0, st, bank_theta, bank_x, ld,
+                               (long long)n_bank, F, static_cast<const double*>(dfac), j % N, mul, add, (uint32_t)epoch,
+                               (int)batch, k0, k1, w.X, w.Z);
+        else
+            hipLaunchKernelGGL(vpet_net_batch_kernel<5>, dim3(blk), dim3(256), 0, st, bank_theta, bank_x, ld,
+                               (long long)n_bank, F, static_cast<const double*>(dfac), j % N, mul, add, (uint32_t)epoch,
+                               (int)batch, k0, k1, w.X, w.Z);
         net_forward(st, params, w, batch);
-        hipLaunchKernelGGL(vpet_mix_loss_kernel, dim3(blk), dim3(256), 0, st, w.O, w.Z, (int)batch, w.dO, losses + t);
+        if (dims == 4)
+            hipLaunchKernelGGL(vpet_mix_loss_kernel<4>, dim3(blk), dim3(256), 0, st, w.O, w.Z, (int)batch, w.dO,
+                               losses + t);
+        else
+            hipLaunchKernelGGL(vpet_mix_loss_kernel<5>, dim3(blk), dim3(256), 0, st, w.O, w.Z, (int)batch, w.dO,
+                               losses + t);
         net_backward(st, params, w, batch, g);
         b1t *= 0.9;
         b2t *= 0.999;

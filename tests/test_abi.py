@@ -200,16 +200,19 @@ def test_proposal_validation_without_gpu(V):
     assert L.vpet_proposal_forward(fake, fake, -1, 30, fake, None) == V.E_ARG
     assert L.vpet_proposal_forward(fake, fake, 0, 30, fake, None) == V.OK  # nothing to do
     assert L.vpet_proposal_forward(None, fake, 4, 30, fake, None) == V.E_ARG
-    assert L.vpet_proposal_loss_grad(fake, fake, fake, 0, 30, fake, fake, None) == V.E_ARG
-    assert L.vpet_proposal_loss_grad(fake, fake, fake, (1 << 20) + 1, 30, fake, fake, None) == V.E_ARG
-    assert L.vpet_proposal_loss_grad(fake, fake, None, 8, 30, fake, fake, None) == V.E_ARG
-    assert L.vpet_proposal_loss_grad(fake, fake, fake, 8, 40, fake, fake, None) == V.E_LIMIT
+    assert L.vpet_proposal_loss_grad(fake, fake, fake, 0, 30, 4, fake, fake, None) == V.E_ARG
+    assert L.vpet_proposal_loss_grad(fake, fake, fake, (1 << 20) + 1, 30, 4, fake, fake, None) == V.E_ARG
+    assert L.vpet_proposal_loss_grad(fake, fake, None, 8, 30, 4, fake, fake, None) == V.E_ARG
+    assert L.vpet_proposal_loss_grad(fake, fake, fake, 8, 40, 4, fake, fake, None) == V.E_LIMIT
+    assert L.vpet_proposal_loss_grad(fake, fake, fake, 8, 30, 3, fake, fake, None) == V.E_ARG
     ft = W.frame_times(W.SCHED_30x50)
     ftp = ft.ctypes.data_as(ctypes.c_void_p)
 
-    def train(n_bank=1000, ft_=ftp, F=30, noise=0.1, lam=0.0, steps=5, batch=64, lr=1e-3):
-        return L.vpet_proposal_train(fake, fake, fake, n_bank, ft_, F, noise, lam, steps, batch, lr, 1, None, None)
+    def train(n_bank=1000, ft_=ftp, F=30, noise=0.1, lam=0.0, steps=5, batch=64, lr=1e-3, dims=4):
+        return L.vpet_proposal_train(fake, fake, fake, n_bank, ft_, F, dims, noise, lam, steps, batch, lr, 1, None,
+                                     None)
     assert train(n_bank=0) == V.E_ARG
+    assert train(dims=6) == V.E_ARG
     assert train(steps=-1) == V.E_ARG
     assert train(batch=0) == V.E_ARG
     assert train(lr=0.0) == V.E_ARG
@@ -236,3 +239,47 @@ def test_proposal_validation_without_gpu(V):
     o2 = V._binding.Opts()
     o2.out_ess = 0x1000
     assert _call_infer(V, V_=1, opts=o2)[0] == V.E_ARG
+
+
+def test_learned_bank_validation_without_gpu(V):
+    """vpet_abc_infer_bank_learned refuses bad requests before any device work."""
+    ft = W.frame_times(W.SCHED_30x50)
+    cp = W.grid(0.2, 50.0)[1]
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    g = V._binding.Grid(0.2, cp.size, ft.size - 1)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+    def lbank(model=2, dims=4, bins=4, gv=256, share=0.1, scale=1.0, n_draws=1000, p=0.05, V_=0, opts=None,
+              groups=True):
+        box = W.box_array([m for m in (1, 2, 4) if model & m] or [2])
+        gp = V._binding.BankGroups()
+        gp.dims, gp.bins, gp.group_voxels, gp.prior_share, gp.sd_scale = dims, bins, gv, share, scale
+        return V.lib.vpet_abc_infer_bank_learned(None, V_, P(ft), P(cp), g, model, P(box), None,
+                                                 ctypes.byref(gp) if groups else None, n_draws, p, 1, None, None,
+                                                 ctypes.byref(opts) if opts is not None else None, None)
+    assert lbank() == V.OK                                 # no voxels: nothing to do
+    assert lbank(model=2 | 4, dims=5) == V.OK
+    assert lbank(model=1) == V.E_MODEL                     # the 2TCMs only
+    assert lbank(model=8) == V.E_MODEL
+    assert lbank(groups=False) == V.E_ARG
+    assert lbank(dims=3) == V.E_ARG
+    assert lbank(bins=0) == V.E_ARG
+    assert lbank(bins=9) == V.E_LIMIT                      # 9^4 cells > 4096
+    assert lbank(gv=300) == V.E_ARG and lbank(gv=0) == V.E_ARG
+    assert lbank(share=1.5) == V.E_ARG and lbank(scale=-1.0) == V.E_ARG
+    assert lbank(p=0.9) == V.E_LIMIT                       # n = 900 > 512
+    o = V._binding.Opts()
+    o.proposal = 0x1000
+    assert lbank(opts=o) == V.E_ARG                        # the proposal is an argument of its own
+    o = V._binding.Opts()
+    o.bank_scan, o.distance = 2, 1
+    assert lbank(opts=o) == V.E_ARG                        # bf16 contraction is L2-only
+    assert lbank(V_=3) == V.E_ARG                          # NULL device pointers
+    # the prior bank form refuses the learned-proposal options
+    o = V._binding.Opts()
+    o.accept_below = 0x1000
+    assert V.lib.vpet_abc_infer_bank(None, 0, P(ft), g, 2, 1000, 0.05, None, None, None, None, ctypes.byref(o),
+                                     None) == V.E_ARG
+    assert V.lib.vpet_abc_infer(None, 0, P(ft), P(cp), g, 2, P(W.box_array([2])), 10, 0.5, 1, None, None,
+                                ctypes.byref(o), None) == V.E_ARG  # accept_below needs a proposal
+    del fake

@@ -89,3 +89,64 @@ def test_stream_matches_one_call_and_resumes(tmp_path):
     p_rev = np.asarray(prob2)[:, 1]
     ok = ~np.isnan(p_rev)
     assert p_rev[ok & rev].mean() > p_rev[ok & ~rev].mean()
+
+
+def test_stream_learned_matches_chunked_calls_resumes_and_matches_oracle(tmp_path):
+    """Streaming with a learned proposal: each chunk's outputs equal those of
+    one vpet_abc_infer_bank_learned call on that chunk (network outputs from
+    vpet_proposal_forward, groups numbered on from the previous chunks'),
+    across an interrupted and resumed run; streamed voxels on both sides of
+    the chunk boundaries against the oracle (with the same network outputs,
+    which the forward-pass parity tests check separately).  A progress file
+    of a prior-bank run is not resumed by a learned run."""
+    import oracle.learned_bank as lb
+    cfg = W.CFG_TBPET_SMALL
+    ft, cp = cfg.frame_times, cfg.input_fn()
+    models, boxes = list(cfg.models), cfg.box_array()
+    y, rev = _volume(cfg)
+    path = tmp_path / "volume.f32"
+    y.astype(np.float32).tofile(path)
+    params = V.proposal_init(3)
+    gk = dict(dims=5, bins=2, group_voxels=256, prior_share=0.2, sd_scale=1.5)
+    n_draws, p, seed, chunk = 2000, 0.01, 17, 1024
+    prefix = tmp_path / "learned"
+    args = (str(path), cfg.n_voxels, ft, cp, cfg.dt, models, boxes, params, n_draws, p, seed, str(prefix))
+    assert V.stream_bank_learned(*args, chunk_voxels=chunk, resume=False, max_chunks=2, **gk) == 2
+    assert V.stream_bank_learned(*args, chunk_voxels=chunk, resume=True, **gk) == 3
+    text = (tmp_path / "learned.progress").read_text()
+    assert text.startswith("vpet_abc_stream_learned") and "done=3" in text
+    mom, prob = V.load_stream_outputs(str(prefix), cfg.n_voxels, len(models))
+    y_d = torch.from_numpy(y).to(DEV)
+    outs = {}
+    for c in range(3):
+        sl = slice(c * chunk, min(cfg.n_voxels, (c + 1) * chunk))
+        o_c = V.proposal_forward(params, y_d[sl].contiguous())
+        r = V.infer_bank_learned(y_d[sl].contiguous(), ft, cp, cfg.dt, models, boxes, o_c, n_draws, p, seed,
+                                 debug=True, first_group=c * (chunk // 256), **gk)
+        torch.cuda.synchronize()
+        assert np.array_equal(np.asarray(mom[sl]).view(np.uint32), r["moments"].cpu().numpy().view(np.uint32))
+        assert np.array_equal(np.asarray(prob[sl]).view(np.uint32), r["model_prob"].cpu().numpy().view(np.uint32))
+        outs[c] = (o_c.cpu().numpy().astype(np.float64), r["accept_idx"].cpu().numpy())
+    assert np.isnan(prob[7]).all()
+    # oracle on voxels both sides of the chunk boundaries
+    for c, local in ((0, [0, 1, 1022, 1023]), (1, [0, 1, 1023]), (2, [0, 500, cfg.n_voxels - 2049])):
+        sl = slice(c * chunk, min(cfg.n_voxels, (c + 1) * chunk))
+        o_c, idx = outs[c]
+        ref = lb.infer_bank_learned(y[sl], ft, cp, cfg.dt, models, boxes, o_c, n_draws, p, seed, voxels=local,
+                                    first_group=c * (chunk // 256), **gk)
+        for k, v in enumerate(local):
+            a_g, a_o = set(idx[v].tolist()), set(ref["accept_idx"][k].tolist())
+            if a_g != a_o:
+                d, h = ref["distances"][k], ref["threshold"][k]
+                assert all(abs(d[q] - h) <= 1e-5 * h for q in a_g ^ a_o), (c, v)
+                continue
+            gm = np.asarray(mom[sl])[v].astype(np.float64)
+            ok = ~np.isnan(ref["moments"][k])
+            assert np.array_equal(np.isnan(gm), ~ok), (c, v)
+            assert np.allclose(gm[ok], ref["moments"][k][ok], rtol=1e-5, atol=1e-7), (c, v)
+            assert np.allclose(np.asarray(prob[sl])[v], ref["model_prob"][k], atol=1e-6), (c, v)
+    # a prior-bank run's progress is not continued by a learned run
+    (tmp_path / "learned.progress").write_text(
+        f"vpet_abc_stream v1 voxels={cfg.n_voxels} frames={ft.size - 1} models=2 chunk={chunk} done=1\n")
+    with pytest.raises(V.VpetError):
+        V.stream_bank_learned(*args, chunk_voxels=chunk, resume=True, **gk)

@@ -177,3 +177,70 @@ def test_sd_scale_widens_every_component():
     sd = np.exp(logsd[0, 0]) * 2.5
     lq = prop.log_density(o[None, :], z2[:1], sd_scale=2.5)[0]
     assert lq == pytest.approx(np.sum(stats.norm.logpdf(z2[0], loc=mu[0, 0], scale=sd)), rel=1e-9, abs=1e-9)
+
+
+def _is_setup(nv, seed):
+    import oracle as ora
+    cfg = W.CFG_LARGE
+    ft, cp = cfg.frame_times, cfg.input_fn()
+    box = W.box_array([W.M_2TCM_IRR])
+    rng = np.random.default_rng(seed)
+    th = W.true_params(rng, nv, W.M_2TCM_IRR, box[0])
+    y = W.add_noise(ora.simulate(W.M_2TCM_IRR, th, cp, cfg.dt, ft), ft, rng.standard_normal((nv, ft.size - 1)))
+    return cfg, ft, cp, box, th, y, rng
+
+
+def _centred_outputs(th_v, rng, sd=0.4):
+    o = np.zeros(prop.NOUT)
+    z0 = np.log(np.maximum(th_v[list(prop.FREE_SLOTS)], 1e-3))
+    o[prop.C:prop.C + prop.C * prop.D] = np.tile(z0, prop.C) + 0.2 * rng.standard_normal(prop.C * prop.D)
+    s = (math.log(sd) - prop.LS0) / (prop.LS1 - prop.LS0)
+    o[prop.C + prop.C * prop.D:] = math.log(s / (1.0 - s))
+    return o
+
+
+def test_given_threshold_is_the_prefix_of_the_fixed_fraction(ora):
+    """ABC at a given threshold h (the indicator form of Eq. (7)) keeps, of the
+    n closest draws, those at or below h.  With h the k-th smallest distance
+    (k < n) that is exactly the fixed-fraction result with k accepted draws;
+    with h = inf it is the fixed-fraction result itself."""
+    cfg, ft, cp, box, th, y, rng = _is_setup(3, 41)
+    for v in range(3):
+        o = _centred_outputs(th[v], rng)
+        kw = dict(prior_share=0.2, sd_scale=1.3)
+        order, mom, ess, d = prop.infer_is(y[v], ft, cp, cfg.dt, box[0], o, 4000, 0.05, 7, v, **kw)
+        k = 37
+        h = np.float32(d[order[k - 1]])
+        assert np.float32(d[order[k]]) > h  # distinct at the cut
+        _, mom_h, ess_h, _ = prop.infer_is(y[v], ft, cp, cfg.dt, box[0], o, 4000, 0.05, 7, v, accept_below=h, **kw)
+        _, mom_k, ess_k, _ = prop.infer_is(y[v], ft, cp, cfg.dt, box[0], o, 4000, k / 4000, 7, v, **kw)
+        assert np.array_equal(mom_h, mom_k, equal_nan=True) and ess_h == ess_k
+        _, mom_inf, ess_inf, _ = prop.infer_is(y[v], ft, cp, cfg.dt, box[0], o, 4000, 0.05, 7, v,
+                                               accept_below=np.float32(np.inf), **kw)
+        assert np.array_equal(mom_inf, mom, equal_nan=True) and ess_inf == ess
+        _, mom_0, ess_0, _ = prop.infer_is(y[v], ft, cp, cfg.dt, box[0], o, 4000, 0.05, 7, v,
+                                           accept_below=np.float32(0.5 * d[order[0]]), **kw)
+        assert np.isnan(mom_0).all() and np.isnan(ess_0)
+
+
+def test_importance_weighted_abc_at_plain_threshold_matches_plain_abc(ora):
+    """Plain prior ABC (Alg. 1) with 400k draws, 400 accepted, sets a threshold
+    h; importance-weighted ABC with 40k draws from a proposal centred near the
+    truth, restricted to the same h, targets the same distribution (the prior
+    on {d <= h}), so its weighted Ki mean agrees with plain ABC's within
+    Monte Carlo error.  Weighting the same draws by 1 instead misses (the
+    proposal favours the middle of the region)."""
+    cfg, ft, cp, box, th, y, rng = _is_setup(3, 42)
+    n_pl, p_pl, n_is, p_is = 400_000, 0.001, 100_000, 0.039
+    for v in range(3):
+        ref = ora.infer(y[v:v + 1], ft, cp, cfg.dt, [W.M_2TCM_IRR], box, n_pl, p_pl, 5, voxel_offset=v)
+        h = np.float32(ref["threshold"][0])
+        ki_pl, var_pl = ref["moments"][0, 0, 5]
+        o = _centred_outputs(th[v], rng, sd=0.3)
+        order, mom, ess, d = prop.infer_is(y[v], ft, cp, cfg.dt, box[0], o, n_is, p_is, 9, v, prior_share=0.1,
+                                           sd_scale=1.0, accept_below=h)
+        assert np.float32(d[order[-1]]) > h  # every draw below h was kept
+        ki_is, var_is = mom[5]
+        se = math.sqrt(var_is / ess + var_pl / 400.0)
+        print(f"voxel {v}: Ki plain {ki_pl:.5f} IS {ki_is:.5f} (SE {se:.2e}, ESS {ess:.0f})")
+        assert ess > 20 and abs(ki_is - ki_pl) <= 4.0 * se
