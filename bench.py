@@ -42,6 +42,20 @@ def flops_per_draw(n_steps: int, n_frames: int) -> int:
     return 2 * n_steps + 12 * n_frames + 40
 
 
+def host_cpu() -> str:
+    """The host's CPU model (as lscpu names it) and its logical core count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model} ({os.cpu_count()} logical cores visible)"
+
+
 def source_sha() -> str:
     with open(SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -124,7 +138,7 @@ def cpu_baseline(cfg, ft, cp, y, y_dev, budget_s: float):
     t0 = time.perf_counter()
     oracle.infer(y[:n1], ft, cp, cfg.dt, models, boxes, cfg.n_draws, cfg.accept_frac, cfg.infer_seed, nthreads=1)
     dt1 = time.perf_counter() - t0
-    base = {"value": nv / dt, "unit": "voxels/s", "cores": threads, "kind": "oracle",
+    base = {"value": nv / dt, "unit": "voxels/s", "cores": threads, "kind": "oracle", "cpu_model": host_cpu(),
             "sample": f"first {nv} voxels of the same volume, all {cfg.n_draws} draws each, FP64, "
                       f"OpenMP over voxels ({dt:.1f} s)",
             "value_1_thread": n1 / dt1, "sample_1_thread": f"first {n1} voxels, one thread ({dt1:.1f} s)"}
@@ -136,6 +150,7 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
     import torch
 
     import paper_2603_14859_amd as V
+    import workloads as W
     models, boxes = list(cfg.models), cfg.box_array()
     F = ft.size - 1
     n_nodes = cp.size
@@ -171,6 +186,12 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
     ms = (time.perf_counter() - t0) * 1e3 / steps
     call_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     kern_ms = float(np.mean(scan_ms))
+    ki_rmse = None
+    if models == [W.M_2TCM_IRR]:  # the posterior mean of Ki against the truth
+        th, _ = cfg.truth()
+        ki = th[:, 0].astype(np.float64) * th[:, 2] / (th[:, 1] + th[:, 2])
+        m = res["moments"][:, 0, 5, 0].cpu().numpy().astype(np.float64)
+        ki_rmse = float(np.sqrt(np.nanmean((m - ki) ** 2)))
     n = V.accept_count(M * cfg.n_draws, cfg.accept_frac)
     n_tot = M * cfg.n_draws
     pairs = cfg.n_voxels * n_tot
@@ -190,7 +211,7 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
         pilot = min(n_tot, -(-4 * n_tot // n))
     achieved = pairs * fpp / (kern_ms * 1e-3) / 1e12
     out = {"value": cfg.n_voxels / (ms * 1e-3), "unit": "voxels/s", "ms_per_step": round(ms, 3),
-           "call_ms_hip_events": round(call_ms, 3), "bank_build_ms": round(build_ms, 3),
+           "call_ms_hip_events": round(call_ms, 3), "bank_build_ms": round(build_ms, 3), "ki_rmse": ki_rmse,
            "dtype": "bf16x3 contraction + f64 re-rank" if scan == "bf16" else "f64",
            "config": {"bank_draws": n_tot, "draws": "one Philox4x32-10 bank (stream 1) for all voxels",
                       "n_accept": n, "pilot_rows": pilot, "scan": scan},
@@ -225,7 +246,7 @@ def bank_form(cfg, ft, cp, y_host, y_dev, steps: int, warmup: int, cpu: bool, bu
         ok[..., 1] = False
         rel = np.abs(mom[same] - ref["moments"][same])[ok[same]] / np.abs(ref["moments"][same][ok[same]])
         out["cpu_baseline"] = {"value": nv / (dt - bank_s) if dt > bank_s else None, "unit": "voxels/s",
-                               "cores": threads, "kind": "oracle",
+                               "cores": threads, "kind": "oracle", "cpu_model": host_cpu(),
                                "sample": f"first {nv} voxels against the same {M * cfg.n_draws}-row bank, FP64 "
                                          f"({dt:.1f} s incl. a {bank_s:.1f} s bank build, excluded)"}
         out["error_vs_oracle"] = {"voxels": int(nv), "identical_accepted_sets": int(same.sum()),
@@ -254,6 +275,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="large: skip the MRTM/lp-ntPET and total-body sub-objects")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); voxels are independent, so "
@@ -367,7 +390,22 @@ def main():
         lf = learned_form(cfg, ft, cp, y_host, y, args.steps, args.warmup, not args.no_cpu_baseline,
                           args.cpu_budget / 3, m_plain=m_plain)
         lf["comparison"]["plain_100k_voxels_per_s"] = out["value"]
+        ctx = lf.pop("_ctx")
         out["learned_proposal"] = lf
+        if not args.no_bank:
+            ctx["plain"] = {"per_voxel_100k": {"voxels_per_s": out["value"], "ki_rmse": lf["comparison"]["ki_rmse_plain_100k"]},
+                            "bank_100k": {"voxels_per_s": out["bank_form"]["value"],
+                                          "ki_rmse": out["bank_form"]["ki_rmse"]}}
+            out["learned_bank"] = learned_bank_form(cfg, ft, cp, y_host, y, args.steps, args.warmup, ctx,
+                                                    not args.no_cpu_baseline, args.cpu_budget / 3)
+        del ctx
+    if cfg.name == W.CFG_LARGE.name and not args.no_extra:
+        import torch
+        torch.cuda.empty_cache()
+        sub = max(1, min(args.steps, 3))
+        out["lpnt"] = reference_form(args, dev, sub, 1)
+        torch.cuda.empty_cache()
+        out["tbpet"] = tbpet_form(args, dev)
     print(json.dumps(out), flush=True)
 
 
@@ -460,7 +498,7 @@ def learned_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, cpu: bool, bud
     mj = rj["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
     ess_j = rj["ess"].cpu().numpy().astype(np.float64)
     covered = (rj["threshold"] > h1m).cpu().numpy()
-    del rj, h1m
+    del rj
     within_j = np.abs(mj[:, 0] - m1m[:, 0]) <= 3.0 * np.sqrt(mj[:, 1] / ess_j + m1m[:, 1] / n_acc)
     judge = {"voxels": sub, "plain_prior_draws": 1_000_000, "plain_accepted": n_acc, "learned_draws": n_is,
              "learned_kept": n_keep, "frac_covered": float(covered.mean()),
@@ -516,7 +554,9 @@ def learned_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, cpu: bool, bud
                "ki_rmse_plain_1M_subset": rmse(m1m, sub), "plain_1M_voxels_per_s": sub / t1m,
                "median_ess": float(np.nanmedian(ess))},
            "judge_common_threshold": judge,
-           "equal_error": equal_error}
+           "equal_error": equal_error,
+           "_ctx": {"params": params, "h1m": h1m, "m1m": m1m, "sub": sub, "t1m": t1m, "ki": ki, "share": share,
+                    "scale": scale}}
     if cpu:
         import oracle.proposal as prop
         rng = np.random.default_rng(0)
@@ -533,6 +573,7 @@ def learned_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, cpu: bool, bud
             done += 1
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": done / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+                               "cpu_model": host_cpu(),
                                "sample": f"first {done} voxels, {n_is} proposal draws each, FP64 numpy + C "
                                          f"(single thread, {dt:.1f} s)"}
     return out
@@ -557,6 +598,7 @@ def main_learned(args, dev):
     del r100
     lf = learned_form(cfg, ft, cp, y_host, y, args.steps, args.warmup, not args.no_cpu_baseline, args.cpu_budget,
                       m_plain=m100)
+    lf.pop("_ctx")
     lf["comparison"]["plain_100k_voxels_per_s"] = cfg.n_voxels / t100
     out = {"metric": METRIC, "value": lf["value"], "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": lf["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -573,10 +615,149 @@ def main_learned(args, dev):
     print(json.dumps(out), flush=True)
 
 
-def main_tbpet(args, dev):
+LB_SETTINGS = {"dims": 4, "bins": 8, "group_voxels": 1024, "prior_share": 0.1, "sd_scale": 1.0}
+
+
+def learned_bank_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, ctx, cpu: bool, budget_s: float):
+    """The shared bank drawn from the learned proposal on the same volume: the
+    network of the learned-proposal form groups the voxels (cells of its
+    posterior means, groups of 1024 voxels) and each group gets a bank of
+    n_bank rows from its Gaussian mixed with the prior (share 0.1); rows carry
+    prior / proposal weights; n = 100 accepted.  One step = network forward
+    pass + vpet_abc_infer_bank_learned.  A sweep over n_bank gives the Ki
+    error against the truth; the line's value is the 10k-row setting; plain
+    ABC (per voxel and shared bank, 100k prior draws; 1M prior draws on a
+    64k-voxel subset) is the comparison, and the judge compares Ki means with
+    plain ABC at 1M prior draws at plain ABC's own thresholds."""
+    import math
+
+    import torch
+
+    import paper_2603_14859_amd as V
+    import workloads as W
+    IRR = W.M_2TCM_IRR
+    box = cfg.box_array()
+    params, ki, n_acc = ctx["params"], ctx["ki"], 100
+    nv = cfg.n_voxels
+    F = ft.size - 1
+    stream = torch.cuda.current_stream()
+    res = {"moments": torch.empty((nv, 1, 8, 2), dtype=torch.float32, device=y.device),
+           "model_prob": torch.empty((nv, 1), dtype=torch.float32, device=y.device),
+           "ess": torch.empty((nv,), dtype=torch.float32, device=y.device)}
+    prop_out = torch.empty((nv, V.PROPOSAL_NOUT), dtype=torch.float32, device=y.device)
+
+    def run(n_bank, ys=y, out=res, po=prop_out, timed=False, **kw):
+        V.proposal_forward(params, ys, out=po)
+        return V.infer_bank_learned(ys, ft, cp, cfg.dt, [IRR], box, po, n_bank, n_acc / n_bank, cfg.infer_seed,
+                                    out=out, time_scan=timed, **LB_SETTINGS, **kw)
+
+    def rmse(m):
+        return float(math.sqrt(np.nanmean((m - ki) ** 2)))
+
+    sweep = []
+    for nb in (2500, 5000, 10_000, 20_000):
+        run(nb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(nb)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        m = res["moments"][:, 0, 5, 0].cpu().numpy().astype(np.float64)
+        sweep.append({"bank_rows_per_group": nb, "voxels_per_s": nv / dt, "ki_rmse": rmse(m),
+                      "median_ess": float(np.nanmedian(res["ess"].cpu().numpy()))})
+    n_bank = 10_000
+    for _ in range(warmup):
+        run(n_bank)
+    torch.cuda.synchronize()
+    scan_ms = []
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        r = run(n_bank, timed=True)
+        scan_ms.append(r["scan_ms"])
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    call_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    kern_ms = float(np.mean(scan_ms))
+    groups = -(-nv // LB_SETTINGS["group_voxels"])
+    fpp = 2 * 2 * F
+    achieved = nv * n_bank * fpp / (kern_ms * 1e-3) / 1e12
+    m_lb = res["moments"][:, 0, 5, 0].cpu().numpy().astype(np.float64)
+    # equal error: the fewest bank rows whose Ki error is at or below each plain point's
+    plain = dict(ctx["plain"])
+    plain["per_voxel_1M_subset"] = {"voxels_per_s": ctx["sub"] / ctx["t1m"],
+                                    "ki_rmse_subset": float(math.sqrt(np.nanmean((ctx["m1m"][:, 0] - ki[:ctx["sub"]]) ** 2)))}
+    equal = {}
+    for key in ("per_voxel_100k", "bank_100k"):
+        ok = [q for q in sweep if q["ki_rmse"] <= plain[key]["ki_rmse"]]
+        equal[f"speedup_vs_plain_{key}_at_its_error"] = (round(ok[0]["voxels_per_s"] / plain[key]["voxels_per_s"], 2)
+                                                          if ok else None)
+        equal[f"bank_rows_at_plain_{key}_error"] = ok[0]["bank_rows_per_group"] if ok else None
+    # the judge: at plain-1M's own per-voxel thresholds on the subset (500 kept)
+    sub = ctx["sub"]
+    ys = y[:sub].contiguous()
+    po = torch.empty((sub, V.PROPOSAL_NOUT), dtype=torch.float32, device=y.device)
+    V.proposal_forward(params, ys, out=po)
+    keep, nb_j = 500, 100_000
+    rj = V.infer_bank_learned(ys, ft, cp, cfg.dt, [IRR], box, po, nb_j, keep / nb_j, cfg.infer_seed, debug=True,
+                              accept_below=ctx["h1m"], **LB_SETTINGS)
+    mj = rj["moments"][:, 0, 5].cpu().numpy().astype(np.float64)
+    ess_j = rj["ess"].cpu().numpy().astype(np.float64)
+    covered = (rj["threshold"] > ctx["h1m"]).cpu().numpy()
+    del rj, po, ys
+    m1m = ctx["m1m"]
+    within = np.abs(mj[:, 0] - m1m[:, 0]) <= 3.0 * np.sqrt(mj[:, 1] / ess_j + m1m[:, 1] / n_acc)
+    judge = {"voxels": sub, "plain_prior_draws": 1_000_000, "plain_accepted": n_acc, "bank_rows_per_group": nb_j,
+             "kept": keep, "frac_covered": float(covered.mean()),
+             "median_ess_at_common_threshold": float(np.nanmedian(ess_j[covered])),
+             "frac_ki_within_3_mc_se": float(np.mean(within[covered])),
+             "note": "grouping made within the subset; h_v = plain ABC's 100th distance of 1M prior draws"}
+    out = {"value": nv / (ms * 1e-3), "unit": "voxels/s", "ms_per_step": round(ms, 3),
+           "call_ms_hip_events": round(call_ms, 3), "ki_rmse": rmse(m_lb),
+           "dtype": "bf16x3 contraction + f64 re-rank, f64 simulation, bf16x3 network",
+           "config": {"voxels": nv, "bank_rows_per_group": n_bank, "groups": groups, "n_accept": n_acc,
+                      **LB_SETTINGS, "models": ["2TCM-irreversible"],
+                      "step": "network forward pass + grouping + group banks (draw, simulate) + BF16 scan + "
+                              "select + weighted reduction"},
+           "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_BF16_MFMA_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
+                        "kernel": f"vpet_bank_mfma_kernel<{2 * int(V.lib.vpet_abc_bank_ld(F))}, false> (BF16 scan)",
+                        "kernel_ms": round(kern_ms, 3), "flops_per_pair": fpp},
+           "sweep": sweep, "plain": plain, "equal_error": equal, "judge_common_threshold": judge}
+    if cpu:
+        # the oracle of the learned bank on one group (the network outputs it
+        # groups are synthetic mixtures near the truths: its cost does not
+        # depend on them)
+        import oracle.learned_bank as olb
+        from oracle.proposal import C as NC
+        th, _ = cfg.truth(1024)
+        rng = np.random.default_rng(0)
+        o = np.zeros((1024, 96))
+        o[:, NC:NC + 32] = (np.tile(np.log(np.maximum(th[:, [0, 1, 2, 4]], 1e-3)), 8)
+                            + 0.2 * rng.standard_normal((1024, 32)))
+        o[:, NC + 32:NC + 64] = -1.0
+        t0 = time.perf_counter()
+        olb.infer_bank_learned(y_host[:1024], ft, cp, cfg.dt, [IRR], box, o, n_bank, n_acc / n_bank, cfg.infer_seed,
+                               **LB_SETTINGS)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1024 / dt, "unit": "voxels/s", "cores": 1, "kind": "oracle",
+                               "cpu_model": host_cpu(),
+                               "sample": f"one 1024-voxel group against its {n_bank}-row bank (built and counted), "
+                                         f"FP64 numpy + C (single thread, {dt:.1f} s)"}
+    return out
+
+
+def tbpet_form(args, dev):
     """Total-body scale: a 150 x 150 x 486 volume (irreversible / reversible
-    2TCM mixture) written to a file, then streamed through the shared-bank form
-    in 1M-voxel chunks (file -> GPU -> file, with resumable progress)."""
+    2TCM mixture) written to a file, then streamed in 1M-voxel chunks (file ->
+    GPU -> file, resumable): (a) against one shared prior bank of 1M draws
+    (500k per model), (b) with the learned proposal: a network with a
+    five-parameter head trained on reversible-2TCM simulations groups each
+    chunk's voxels, and every group gets a bank of 10k draws per model from its
+    proposal (weights prior / proposal).  Model selection and the Ki of the
+    preferred model are compared with the truth for both."""
     import torch
 
     import paper_2603_14859_amd as V
@@ -600,39 +781,91 @@ def main_tbpet(args, dev):
             W.add_noise(clean.cpu().numpy(), ft, eps[sl]).tofile(fh)
     prep_s = time.perf_counter() - t0
     del eps
+    ki_true = (th[:, 0].astype(np.float64) * th[:, 2] / (th[:, 1] + th[:, 2]))
+
+    def summary(wall):
+        mom, prob = V.load_stream_outputs(prefix, cfg.n_voxels, M)
+        p_rev = np.asarray(prob[:, 1])
+        ok = ~np.isnan(p_rev)
+        ki_post = np.where(p_rev > 0.5, mom[:, 1, 5, 0], mom[:, 0, 5, 0]).astype(np.float64)  # preferred model's Ki
+        rel = np.abs(ki_post - ki_true) / ki_true
+        return {"voxels_per_s": cfg.n_voxels / wall, "seconds": round(wall, 2),
+                "model_selection": {"mean_p_rev_reversible": float(p_rev[ok & rev].mean()),
+                                    "mean_p_rev_irreversible": float(p_rev[ok & ~rev].mean()),
+                                    "accuracy_p_rev_gt_half": float(np.mean((p_rev[ok] > 0.5) == rev[ok]))},
+                "ki_preferred_model": {"median_rel_err": float(np.nanmedian(rel)),
+                                       "rmse": float(np.sqrt(np.nanmean((ki_post - ki_true) ** 2)))}}
+
+    # (a) the prior bank
     thb, xb = V.bank_build(models, boxes, cfg.n_draws, cfg.infer_seed, cp, ft, cfg.dt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = V.stream_bank(path, cfg.n_voxels, ft, cfg.dt, cp.size, models, cfg.n_draws, cfg.accept_frac, thb, xb,
                          prefix, chunk_voxels=chunk, resume=False)
-    wall = time.perf_counter() - t0
-    mom, prob = V.load_stream_outputs(prefix, cfg.n_voxels, M)
-    p_rev = np.asarray(prob[:, 1])
-    ok = ~np.isnan(p_rev)
-    ki_true = (th[:, 0].astype(np.float64) * th[:, 2] / (th[:, 1] + th[:, 2]))
-    ki_post = np.where(p_rev > 0.5, mom[:, 1, 5, 0], mom[:, 0, 5, 0]).astype(np.float64)  # preferred model's Ki
-    rel = np.abs(ki_post - ki_true) / ki_true
-    n = V.accept_count(M * cfg.n_draws, cfg.accept_frac)
-    out = {"metric": METRIC, "value": cfg.n_voxels / wall, "unit": "voxels/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-           "ms_per_step": round(wall * 1e3, 1), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "bf16x3 contraction + f64 re-rank",
-           "data": "synthetic (seeded Feng input, uniform prior truths, half reversible, Gaussian frame noise); "
-                   "the value includes reading the volume from a file and writing the outputs (disk -> GPU -> disk)",
-           "config": {"workload": cfg.name, "voxels": cfg.n_voxels, "frames": F, "minutes": float(ft[-1]),
-                      "models": ["2TCM-irreversible", "2TCM-reversible"], "bank_draws_per_model": cfg.n_draws,
-                      "accept_frac": cfg.accept_frac, "n_accept": n, "chunk_voxels": chunk, "chunks": done,
-                      "input_file_gb": round(cfg.n_voxels * F * 4 / 1e9, 3), "input_prep_s": round(prep_s, 1),
-                      "parallelism": "single GPU"},
-           "model_selection": {"mean_p_rev_reversible": float(p_rev[ok & rev].mean()),
-                               "mean_p_rev_irreversible": float(p_rev[ok & ~rev].mean()),
-                               "median_rel_err_ki_preferred_model": float(np.nanmedian(rel))}}
-    print(json.dumps(out), flush=True)
+    plain = summary(time.perf_counter() - t0)
+    del thb, xb
+    torch.cuda.empty_cache()
+    # (b) the learned proposal
+    t0 = time.perf_counter()
+    thr, xr = V.bank_build([W.M_2TCM_REV], boxes[1:], 1_000_000, 17, cp, ft, cfg.dt)
+    params = V.proposal_init(2)
+    losses = V.proposal_train(params, thr, xr, ft, steps=5000, batch=2048, lr=5e-4, noise_level=0.05,
+                              decay_lambda=W.LAMBDA_F18, seed=9, dims=5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del thr, xr
+    torch.cuda.empty_cache()
+    n_acc = 100
+    lbk = {"dims": 5, "bins": 4, "group_voxels": 1024, "prior_share": 0.1, "sd_scale": 1.0}
+    sweep = []
+    for n_lb in (10_000, 30_000, 50_000, 100_000):
+        t0 = time.perf_counter()
+        done_l = V.stream_bank_learned(path, cfg.n_voxels, ft, cp, cfg.dt, models, boxes, params, n_lb,
+                                       n_acc / (M * n_lb), cfg.infer_seed, prefix, chunk_voxels=chunk, resume=False,
+                                       **lbk)
+        sweep.append({"bank_rows_per_model_per_group": n_lb, **summary(time.perf_counter() - t0)})
+    # the line's value: the fewest rows whose model-selection accuracy and Ki error of the preferred model are at
+    # least as good as the prior bank's (else the largest setting)
+    def as_good(q):
+        return (q["model_selection"]["accuracy_p_rev_gt_half"] >= plain["model_selection"]["accuracy_p_rev_gt_half"]
+                and q["ki_preferred_model"]["median_rel_err"] <= plain["ki_preferred_model"]["median_rel_err"])
+    eq = [q for q in sweep if as_good(q)]
+    learned = eq[0] if eq else sweep[-1]
+    n_lb = learned["bank_rows_per_model_per_group"]
     for f in (path, prefix + ".moments", prefix + ".prob", prefix + ".progress"):
         if os.path.exists(f):
             os.remove(f)
+    n = V.accept_count(M * cfg.n_draws, cfg.accept_frac)
+    return {"value": learned["voxels_per_s"], "unit": "voxels/s", "ms_per_step": round(learned["seconds"] * 1e3, 1),
+            "dtype": "bf16x3 contraction + f64 re-rank",
+            "data": "synthetic (seeded Feng input, uniform prior truths, half reversible, Gaussian frame noise); "
+                    "every rate includes reading the volume from a file and writing the outputs (disk -> GPU -> disk)",
+            "config": {"workload": cfg.name, "voxels": cfg.n_voxels, "frames": F, "minutes": float(ft[-1]),
+                       "models": ["2TCM-irreversible", "2TCM-reversible"], "chunk_voxels": chunk,
+                       "chunks": [done, done_l], "input_file_gb": round(cfg.n_voxels * F * 4 / 1e9, 3),
+                       "input_prep_s": round(prep_s, 1), "n_accept": n_acc,
+                       "value_is": "the learned-proposal stream"},
+            "prior_bank": {"bank_draws_per_model": cfg.n_draws, "accept_frac": cfg.accept_frac, "n_accept": n, **plain},
+            "learned_bank": {**lbk, "training_s": round(train_s, 2),
+                             "training_loss_last_100": float(losses[-100:].mean()), **learned, "sweep": sweep,
+                             "at_prior_bank_error": bool(eq)},
+            "speedup_learned_vs_prior_bank": round(learned["voxels_per_s"] / plain["voxels_per_s"], 2),
+            "speedup_note": "the learned stream's fewest rows per model per group at which both the model-selection "
+                            "accuracy and the median Ki error of the preferred model are at least as good as the prior "
+                            "bank's (at_prior_bank_error false: none of the sweep is; the largest setting is shown)"}
 
 
-def main_reference(args, dev):
+def main_tbpet(args, dev):
+    """The total-body workload as the line (see tbpet_form)."""
+    tb = tbpet_form(args, dev)
+    out = {"metric": METRIC, "value": tb["value"], "unit": "voxels/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": tb["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           **{k: v for k, v in tb.items() if k not in ("value", "unit", "ms_per_step")}}
+    out["config"]["parallelism"] = "single GPU"
+    print(json.dumps(out), flush=True)
+
+
+def reference_form(args, dev, steps, warmup):
     """MRTM vs lp-ntPET model selection on a reference-region input (the
     shared-bank form; the per-voxel path does not run these models)."""
     import torch
@@ -648,24 +881,23 @@ def main_reference(args, dev):
     clean[a] = V.simulate(W.M_LPNTPET, torch.from_numpy(th[a]).to(dev), cr, ft, cfg.dt).cpu().numpy()
     clean[z] = V.simulate(W.M_MRTM, torch.from_numpy(th[z]).to(dev), cr, ft, cfg.dt).cpu().numpy()
     y_host = W.add_noise(clean, ft, eps, lam=cfg.decay_lambda)
+    del clean
     y = torch.from_numpy(y_host).to(dev)
-    bank = bank_form(cfg, ft, cr, y_host, y, args.steps, args.warmup, not args.no_cpu_baseline, args.cpu_budget,
+    bank = bank_form(cfg, ft, cr, y_host, y, steps, warmup, not args.no_cpu_baseline, args.cpu_budget,
                      args.bank_scan)
     models = list(cfg.models)
     thb, xb = V.bank_build(models, cfg.box_array(), cfg.n_draws, cfg.infer_seed, cr, ft, cfg.dt)
     r = V.infer_bank(y, ft, cfg.dt, cr.size, models, cfg.n_draws, cfg.accept_frac, thb, xb,
                      decay_lambda=cfg.decay_lambda, bank_scan=args.bank_scan)
     p = r["model_prob"][:, 1].cpu().numpy()
-    out = {"metric": METRIC, "value": bank["value"], "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": bank["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": bank["dtype"],
+    del r, thb, xb, y
+    out = {"value": bank["value"], "unit": "voxels/s", "ms_per_step": bank["ms_per_step"], "dtype": bank["dtype"],
            "data": "synthetic (one-tissue reference TAC of the seeded Feng input, half the voxels activated, "
                    "Gaussian frame noise, 11C decay)",
            "config": {"workload": cfg.name, "voxels": cfg.n_voxels, "frames": F, "minutes": float(ft[-1]),
                       "grid_dt_min": cfg.dt, "models": ["MRTM", "lp-ntPET"], "bank_draws_per_model": cfg.n_draws,
                       "accept_frac": cfg.accept_frac, "n_accept": bank["config"]["n_accept"],
-                      "pilot_rows": bank["config"]["pilot_rows"], "scan": args.bank_scan,
-                      "parallelism": "single GPU"},
+                      "pilot_rows": bank["config"]["pilot_rows"], "scan": args.bank_scan, "steps": steps},
            "roofline": bank["roofline"],
            "model_selection": {"activated_voxels": int(active.sum()),
                                "mean_p_lpntpet_activated": float(p[active].mean()),
@@ -675,6 +907,16 @@ def main_reference(args, dev):
     for k in ("cpu_baseline", "error_vs_oracle"):
         if k in bank:
             out[k] = bank[k]
+    return out
+
+
+def main_reference(args, dev):
+    """The MRTM / lp-ntPET workload as the line (see reference_form)."""
+    rf = reference_form(args, dev, args.steps, args.warmup)
+    out = {"metric": METRIC, "value": rf["value"], "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": rf["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, **{k: v for k, v in rf.items() if k not in ("value", "unit", "ms_per_step")}}
+    out["config"]["parallelism"] = "single GPU"
     print(json.dumps(out), flush=True)
 
 

@@ -28,6 +28,11 @@
  *    caller's hipSetDevice); "host" pointers are ordinary host memory that the
  *    library reads before the call returns.  The caller owns every buffer; the
  *    library writes only the out_* buffers it is given.
+ *  - Device scratch that a call allocates in stream order comes from the
+ *    device's default memory pool (hipMallocAsync); on first use of a device
+ *    the library raises that pool's release threshold to 32 GiB, so that
+ *    freed scratch is kept for the next call instead of being unmapped and
+ *    mapped again.
  *  - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the null stream)
  *    and the call returns without waiting.  Outputs are valid once the stream
  *    has reached that point.  Calls on different streams may overlap.
@@ -400,9 +405,9 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
  *                 out_scan_ms, out_fallback_voxels, out_ess and accept_below
  *                 are honoured; proposal, voxel_offset and waves_per_voxel
  *                 must be unset.
- * Device scratch (the grouping, about 40 + 4 F bytes per voxel; the banks and
- * candidate lists of one chunk of whole groups, each within 4 GiB) is
- * allocated and freed in stream order.
+ * Device scratch (the grouping, about 40 + 4 F bytes per voxel; the banks of
+ * one chunk of whole groups within 16 GiB and its candidate lists within 4
+ * GiB) is allocated and freed in stream order.
  * Errors: VPET_E_ARG, VPET_E_MODEL, VPET_E_GRID, VPET_E_LIMIT (bins^dims >
  * 4096, n > VPET_BANK_MAX_ACCEPT, F > VPET_BANK_MAX_FRAMES, more than 2^31 - 1
  * voxels), VPET_E_NOMEM, VPET_E_HIP.

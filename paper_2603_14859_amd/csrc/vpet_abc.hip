@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -1072,6 +1073,7 @@ struct BankArgs {
     const float* bank_theta;
     double floor_frac;
     int F, ld, l1, M, cap, fb_cap;
+    int scap;               // keys the re-ranking select holds in LDS (a power of two)
     long long V;            // voxels in this launch
     unsigned n_tot, n_draws, n_acc, n_pilot;
     int kinds[kMaxModels];
@@ -1107,6 +1109,9 @@ struct BankArgs {
     const int* out_row;       // [positions] output row of each position, or nullptr (the launch row)
     float* out_ess;           // [V] effective sample size of the accepted weights (with bank_logw)
     const float* below;       // [V] given ABC thresholds (by output row), or nullptr
+    // [groups of the launch][ld] FP64 reference curve of each group (grouped
+    // banks), or nullptr: the BF16 screen works on y - r and x - r
+    const double* ref;
 };
 
 // First bank row of the bank that voxel `row` of the launch is screened against.
@@ -1185,6 +1190,55 @@ __device__ __forceinline__ double row_distance(const double* xr, const double (&
         } else {
             d0 = fma(Wt[f] * r0, r0, d0);
             d1 = fma(Wt[f + 1] * r1, r1, d1);
+        }
+    }
+    return d0 + d1;
+}
+
+// The voxel's curve and weights (as lane_curve computes them, padding frames
+// 0) written once to LDS by the first LD lanes of a wavefront; every lane then
+// reads them as broadcast operands.
+template <int LD, bool L1>
+__device__ __forceinline__ void wave_curve_lds(const BankArgs& P, long long row, double* Ys, double* Ws) {
+    const int f = lane_id();
+    const float* y = P.tacs + (size_t)row * P.F;
+    const float yy = (f < P.F) ? y[f] : 0.0f;
+    float ymax = (f < P.F) ? yy : -__builtin_inff();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ymax = fmaxf(ymax, __shfl_xor(ymax, off, kWave));
+    const double den_floor = P.floor_frac * (double)ymax;
+    double w = 0.0;
+    if (f < P.F) {
+        if (P.weights) {
+            w = (double)P.weights[(size_t)row * P.F + f];
+        } else {
+            const double Y = (double)yy;
+            w = P.omega[f] / (Y > den_floor ? Y : den_floor);
+        }
+        if (L1) w = sqrt(w);
+    }
+    if (f < LD) {
+        Ys[f] = (double)yy;
+        Ws[f] = w;
+    }
+    wave_lds_sync();
+}
+
+// row_distance with the voxel's curve and weights in LDS (the same operations
+// in the same order).
+template <int LD, bool L1>
+__device__ __forceinline__ double row_distance_lds(const double* xr, const double* Ys, const double* Ws) {
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int f = 0; f < LD; f += 2) {
+        const double r0 = Ys[f] - xr[f];
+        const double r1 = Ys[f + 1] - xr[f + 1];
+        if (L1) {
+            d0 = fma(Ws[f], fabs(r0), d0);
+            d1 = fma(Ws[f + 1], fabs(r1), d1);
+        } else {
+            d0 = fma(Ws[f] * r0, r0, d0);
+            d1 = fma(Ws[f + 1] * r1, r1, d1);
         }
     }
     return d0 + d1;
@@ -1430,7 +1484,9 @@ template <int LD, bool L1, bool RECOMPUTE>
 __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
     extern __shared__ __align__(16) unsigned char lds[];
     uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
-    double* red = reinterpret_cast<double*>(keys + P.cap);
+    double* red = reinterpret_cast<double*>(keys + (RECOMPUTE ? P.scap : P.cap));
+    double* Ys = red + kRedStride * kMaxWpv;  // RECOMPUTE: the voxel's curve and weights
+    double* Ws = Ys + LD;
     const long long row = blockIdx.x;
     if (row >= P.V) return;
     const int c = P.cnt[row];
@@ -1450,11 +1506,11 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
         // tighter test (computed S <= cthr1); if at least n of them lie at or
         // below tau1, the n smallest keys are among them.  Otherwise pass 2
         // adds the remaining candidates and the certificate is taken at tau.
-        double Y[LD], Wt[LD];
-        lane_curve<LD, L1>(P, row, Y, Wt);  // every lane holds the voxel
+        wave_curve_lds<LD, L1>(P, row, Ys, Ws);
         const uint64_t* src = P.cand + (size_t)row * P.cap;
         const float tau1 = P.tau1[row], cthr1 = P.cthr1[row];
         int below1 = 0;
+        bool overflow = false;  // more keys at or below tau than the LDS holds: exact fallback
         for (int pass = 0; pass < 2; ++pass) {
             for (int j0 = 0; j0 < c; j0 += kWave) {
                 const int j = j0 + lane_id();
@@ -1465,18 +1521,23 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
                     take = (__uint_as_float((uint32_t)(e >> 32)) <= cthr1) == (pass == 0);
                     if (take) {
                         const uint32_t g = (uint32_t)e;
-                        const float fd = key_dist(row_distance<LD, L1>(P.bank_x + (size_t)g * LD, Y, Wt));
+                        const float fd = key_dist(row_distance_lds<LD, L1>(P.bank_x + (size_t)g * LD, Ys, Ws));
                         key = ((uint64_t)__float_as_uint(fd) << 32) | g;
                     }
                 }
                 const float fd = __uint_as_float((uint32_t)(key >> 32));
                 const bool keep = take && fd <= tau;
                 const uint64_t b = __ballot(keep);
-                if (keep) keys[below + (int)mbcnt(b)] = key;
+                overflow = overflow || below + __popcll(b) > P.scap;
+                if (keep && !overflow) keys[below + (int)mbcnt(b)] = key;
                 below += __popcll(b);
                 below1 += __popcll(__ballot(take && fd <= tau1));
             }
             if (below1 >= (int)P.n_acc) break;  // certified at tau1
+        }
+        if (overflow) {
+            if (threadIdx.x == 0) P.fb_list[atomicAdd(P.fb_count, 1u)] = (int)row;
+            return;
         }
     } else {
         const uint64_t* src = P.cand + (size_t)row * P.cap;
@@ -1594,16 +1655,21 @@ __device__ __forceinline__ void store_words(uint16_t* dst, const uint32_t (&w)[L
     for (int q = 0; q < LD / 4; ++q) d[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
 }
 
-// Bank operands B_g = [x_g, x_g^2] as bf16 hi/lo parts.
+// Bank operands B_g = [x_g, x_g^2] as bf16 hi/lo parts (x_g - r and its
+// square with a group reference curve r: the distance is unchanged, since
+// d = sum w ((y - r) - (x - r))^2, while the screen's operands and hence its
+// error bound shrink to the size of the deviations from r).
 template <int LD>
 __global__ __launch_bounds__(256) void vpet_bank_bops_kernel(BankArgs P) {
     const unsigned g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= P.n_tot) return;
     const double* xr = P.bank_x + (size_t)g * LD;
+    const double* rr = P.ref ? P.ref + (size_t)(g / P.grp_rows) * LD : nullptr;
     uint32_t wh[LD], wl[LD];  // K = 2 LD bf16 values, two per word
 #pragma unroll
     for (int k = 0; k < 2 * LD; ++k) {
-        const double xv = xr[k < LD ? k : k - LD];
+        const int f = k < LD ? k : k - LD;
+        const double xv = rr ? xr[f] - rr[f] : xr[f];
         uint16_t hi, lo;
         split_bf16(k < LD ? xv : xv * xv, hi, lo);
         if (k & 1) {
@@ -1619,7 +1685,8 @@ __global__ __launch_bounds__(256) void vpet_bank_bops_kernel(BankArgs P) {
 }
 
 // Voxel operands A_v = [-2 w y, w] (bf16 hi/lo) and a_v = sum w y^2 (FP64),
-// so that d_vg = a_v + sum_k A_vk B_gk.  An invalid voxel gets zero operands,
+// so that d_vg = a_v + sum_k A_vk B_gk (with a group reference curve r, y - r
+// in place of y and x - r in place of x).  An invalid voxel gets zero operands,
 // a_v = NaN, threshold NaN and count -1.
 template <int LD>
 __global__ __launch_bounds__(256) void vpet_bank_aops_kernel(BankArgs P) {
@@ -1627,6 +1694,12 @@ __global__ __launch_bounds__(256) void vpet_bank_aops_kernel(BankArgs P) {
     if (row >= P.V) return;
     double Y[LD], Wt[LD];
     const bool valid = lane_curve<LD, false>(P, row, Y, Wt);
+    if (P.ref) {
+        const double* rr =
+            P.ref + (size_t)((unsigned long long)(P.pos0 + row) / P.grp_vox - (unsigned long long)P.g0) * LD;
+#pragma unroll
+        for (int f = 0; f < LD; ++f) Y[f] -= rr[f];
+    }
     uint16_t* ah = P.ahi + (size_t)row * 2 * LD;
     uint16_t* al = P.alo + (size_t)row * 2 * LD;
     uint32_t wh[LD], wl[LD];  // K = 2 LD bf16 values, two per word
@@ -2720,43 +2793,55 @@ __global__ __launch_bounds__(256) void vpet_lb_hist_kernel(LbArgs A) {
 }
 
 // Block counts -> first output position of each (block, key): keys in order,
-// blocks in order within a key (one block of 1024 threads).
-__global__ __launch_bounds__(1024) void vpet_lb_offsets_kernel(LbArgs A) {
-    __shared__ int tot[kLbMaxCells + 1];
+// blocks in order within a key.  Pass 1 (a thread per key): each key's
+// running count over the blocks and its total; pass 2 (one block): the
+// exclusive scan of the totals, which the scatter adds.
+__global__ __launch_bounds__(256) void vpet_lb_columns_kernel(LbArgs A, int* tot) {
     const int nc = A.ncell + 1;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int run = 0;
+    for (int b = 0; b < A.nb; ++b) {
+        int* hp = A.hist + (size_t)b * nc + c;
+        const int t = *hp;
+        *hp = run;
+        run += t;
+    }
+    tot[c] = run;
+}
+
+__global__ __launch_bounds__(1024) void vpet_lb_cellbase_kernel(LbArgs A, int* tot) {
+    __shared__ int part[1024];
+    const int nc = A.ncell + 1, t = threadIdx.x;
+    const int per = (nc + 1023) / 1024, c0 = t * per, c1 = min(nc, c0 + per);
+    int s = 0;
+    for (int c = c0; c < c1; ++c) s += tot[c];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {  // exclusive scan of the 1024 partial sums, in order
         int run = 0;
-        for (int b = 0; b < A.nb; ++b) {
-            int* hp = A.hist + (size_t)b * nc + c;
-            const int t = *hp;
-            *hp = run;
-            run += t;
+        for (int i = 0; i < 1024; ++i) {
+            const int v = part[i];
+            part[i] = run;
+            run += v;
         }
+    }
+    __syncthreads();
+    int run = part[t];
+    for (int c = c0; c < c1; ++c) {
+        const int v = tot[c];
         tot[c] = run;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int c = 0; c < nc; ++c) {
-            const int t = tot[c];
-            tot[c] = run;
-            run += t;
-        }
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        const int base = tot[c];
-        for (int b = 0; b < A.nb; ++b) A.hist[(size_t)b * nc + c] += base;
+        run += v;
     }
 }
 
 // Stable placement: one wavefront per block of kLbBlock voxels walks them in
 // index order, 64 at a time; a voxel's position is its key's next free slot
 // plus the number of earlier lanes of the same round with the same key.
-__global__ __launch_bounds__(64) void vpet_lb_scatter_kernel(LbArgs A) {
+__global__ __launch_bounds__(64) void vpet_lb_scatter_kernel(LbArgs A, const int* cellbase) {
     __shared__ int next[kLbMaxCells + 1];
     const int nc = A.ncell + 1, lane = threadIdx.x;
-    for (int c = lane; c < nc; c += kWave) next[c] = A.hist[(size_t)blockIdx.x * nc + c];
+    for (int c = lane; c < nc; c += kWave) next[c] = cellbase[c] + A.hist[(size_t)blockIdx.x * nc + c];
     wave_lds_sync();
     const long long v0 = (long long)blockIdx.x * kLbBlock;
     for (int r = 0; r < kLbBlock / kWave; ++r) {
@@ -2827,6 +2912,26 @@ __global__ __launch_bounds__(256) void vpet_lb_fit_kernel(LbArgs A, LbGroup* gro
         }
         groups[g] = G;
     }
+}
+
+// One block per group, a thread per frame: the mean observed curve of the
+// group's valid members (in the grouped order, FP64, a fixed order), the
+// reference that the BF16 screen subtracts (padding frames 0).
+__global__ __launch_bounds__(64) void vpet_lb_ref_kernel(LbArgs A, double* ref, int ld) {
+    const long long g = blockIdx.x;
+    const int f = threadIdx.x;
+    if (f >= ld) return;
+    const long long p0 = g * A.S, p1 = min(A.V, p0 + A.S);
+    double s = 0.0;
+    long long cnt = 0;
+    if (f < A.F) {
+        for (long long p = p0; p < p1; ++p) {
+            if (A.key[A.perm[p]] >= (unsigned)A.ncell) continue;
+            s += (double)A.ys[(size_t)p * A.F + f];
+            ++cnt;
+        }
+    }
+    ref[(size_t)g * ld + f] = cnt > 0 ? s / (double)cnt : 0.0;
 }
 
 struct LbBank {
@@ -3215,11 +3320,34 @@ int upload_blob(DevCtx& ctx, const void* data, size_t bytes, hipStream_t st, con
     return VPET_OK;
 }
 
+// Stream-ordered scratch comes from the device's default memory pool; once
+// per device the pool is told to keep up to 32 GiB of freed memory for reuse
+// (with the default threshold of 0 it returns freed memory to the system at
+// every synchronisation, and a call with banks of several GiB paid for mapping
+// them again each time).
+std::atomic<bool> g_pool_kept[64];
+
+void keep_pool(int dev) {
+    if (g_pool_kept[dev].exchange(true)) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = 32ull << 30;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+}
+
+int current_device(int* dev) {
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (*dev < 0 || *dev >= 64) return fail(VPET_E_HIP, "device ordinal %d out of range", *dev);
+    keep_pool(*dev);
+    return VPET_OK;
+}
+
 int current_ctx(DevCtx** out) {
     int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev < 0 || dev >= 64) return fail(VPET_E_HIP, "device ordinal %d out of range", dev);
+    const int rc = current_device(&dev);
+    if (rc != VPET_OK) return rc;
     *out = &g_ctx[dev];
     return VPET_OK;
 }
@@ -3804,7 +3932,11 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         q += sz_c;
         A.aval = reinterpret_cast<double*>(q);
     }
-    const size_t lds = sizeof(uint64_t) * cap + sizeof(double) * kRedStride * kMaxWpv;
+    // the re-ranking select keeps at most 8 n keys at or below tau in LDS
+    // (about 4 n are expected; more go to the exact fallback)
+    A.scap = std::min(cap, std::max(512, pow2_at_least(8 * (int)n_acc)));
+    const size_t lds = sizeof(uint64_t) * (use_mfma ? A.scap : cap) + sizeof(double) * kRedStride * kMaxWpv +
+                       (use_mfma ? 2 * sizeof(double) * (size_t)ld : 0);
     // fallback blocks: up to 8 wavefronts, each with its own pow2(n + 128)-key
     // top-n, within 48 KB of LDS
     const int fb_cap = pow2_at_least((int)n_acc + 2 * kWave);
@@ -3938,13 +4070,14 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
     const int KB = 2 * ld;
     // device scratch of the grouping (whole call) and of one voxel chunk; a
     // chunk holds whole groups, its candidate list stays within 4 GiB and its
-    // banks within 4 GiB
+    // banks within 16 GiB (large banks of many groups would otherwise cut the
+    // chunks below the size that fills the chip)
     const int cap = mfma ? std::max(512, std::min(4096, pow2_at_least(16 * (int)n_acc)))
                          : std::max(256, pow2_at_least(8 * (int)n_acc));
     const size_t row_bytes = sizeof(float) * VPET_PSTRIDE + sizeof(double) * (size_t)ld + sizeof(double) +
                              (mfma ? 2 * sizeof(uint16_t) * (size_t)KB : 0);
     long long cv = std::max<long long>(S, (1LL << 32) / ((long long)cap * (long long)sizeof(uint64_t)));
-    cv = std::max<long long>(S, std::min<long long>(cv, (long long)((1ULL << 32) / (row_bytes * (size_t)n_tot)) * S));
+    cv = std::max<long long>(S, std::min<long long>(cv, (long long)((1ULL << 34) / (row_bytes * (size_t)n_tot)) * S));
     cv = std::max<long long>(S, (cv / S) * S);
     cv = std::min<long long>(cv, ((n_voxels + S - 1) / S) * S);
     const long long gpc = cv / S;  // groups per chunk
@@ -3957,7 +4090,8 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
     const size_t sz_key = a256(sizeof(unsigned) * V), sz_zm = a256(sizeof(double) * 2 * D * V),
                  sz_hist = a256(sizeof(int) * (size_t)nb * (ncell + 1)), sz_perm = a256(sizeof(int) * V),
                  sz_ys = a256(sizeof(float) * (size_t)F * V), sz_ws = o.weights ? sz_ys : 0,
-                 sz_grp = a256(sizeof(LbGroup) * G);
+                 sz_grp = a256(sizeof(LbGroup) * G), sz_tot = a256(sizeof(int) * (ncell + 1)),
+                 sz_ref = mfma ? a256(sizeof(double) * (size_t)ld * G) : 0;
     const size_t rows_c = (size_t)gpc * n_tot;
     const size_t sz_bt = gp.out_bank_theta ? 0 : a256(sizeof(float) * VPET_PSTRIDE * rows_c),
                  sz_bx = a256(sizeof(double) * (size_t)ld * rows_c),
@@ -3967,7 +4101,8 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
                  sz_fb = a256(sizeof(int) * cv) + 256, sz_cand = a256(sizeof(uint64_t) * (size_t)cap * cv),
                  sz_a = mfma ? a256(sizeof(uint16_t) * (size_t)KB * cv) : 0, sz_c = mfma ? a256(sizeof(float) * cv) : 0,
                  sz_av = mfma ? a256(sizeof(double) * cv) : 0;
-    const size_t total = sz_key + sz_zm + sz_hist + sz_perm + 2 * sz_ys + sz_ws + sz_grp + sz_bt + sz_bx + sz_bw +
+    const size_t total = sz_key + sz_zm + sz_hist + sz_perm + sz_ys + sz_ws + sz_grp + sz_tot + sz_ref + sz_bt + sz_bx +
+                         sz_bw +
                          2 * sz_b + sz_tau + sz_cnt + sz_fb + sz_cand + 2 * sz_a + 3 * sz_c + sz_av;
 
     DevCtx* ctx;
@@ -4030,9 +4165,10 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
     A.hist = reinterpret_cast<int*>(carve(sz_hist));
     A.perm = reinterpret_cast<int*>(carve(sz_perm));
     A.ys = reinterpret_cast<float*>(carve(sz_ys));
-    carve(sz_ys);  // reserved
     A.ws = o.weights ? reinterpret_cast<float*>(carve(sz_ws)) : nullptr;
     LbGroup* d_groups = reinterpret_cast<LbGroup*>(carve(sz_grp));
+    int* d_tot = reinterpret_cast<int*>(carve(sz_tot));
+    double* d_ref = mfma ? reinterpret_cast<double*>(carve(sz_ref)) : nullptr;
     float* b_theta = gp.out_bank_theta ? nullptr : reinterpret_cast<float*>(carve(sz_bt));
     double* b_x = reinterpret_cast<double*>(carve(sz_bx));
     double* b_logw = gp.out_bank_logw ? nullptr : reinterpret_cast<double*>(carve(sz_bw));
@@ -4103,14 +4239,20 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
     const dim3 b256(256);
     hipLaunchKernelGGL(vpet_lb_summary_kernel, dim3((unsigned)((V + 255) / 256)), b256, 0, st, A);
     hipLaunchKernelGGL(vpet_lb_hist_kernel, dim3((unsigned)nb), b256, 0, st, A);
-    hipLaunchKernelGGL(vpet_lb_offsets_kernel, dim3(1), dim3(1024), 0, st, A);
-    hipLaunchKernelGGL(vpet_lb_scatter_kernel, dim3((unsigned)nb), dim3(64), 0, st, A);
+    hipLaunchKernelGGL(vpet_lb_columns_kernel, dim3((unsigned)((ncell + 1 + 255) / 256)), b256, 0, st, A, d_tot);
+    hipLaunchKernelGGL(vpet_lb_cellbase_kernel, dim3(1), dim3(1024), 0, st, A, d_tot);
+    hipLaunchKernelGGL(vpet_lb_scatter_kernel, dim3((unsigned)nb), dim3(64), 0, st, A, (const int*)d_tot);
     hipLaunchKernelGGL(vpet_lb_gather_kernel, dim3((unsigned)((V + 255) / 256)), b256, 0, st, A);
     hipLaunchKernelGGL(vpet_lb_fit_kernel, dim3((unsigned)G), b256, 0, st, A, d_groups, scale);
+    if (mfma) hipLaunchKernelGGL(vpet_lb_ref_kernel, dim3((unsigned)G), dim3(64), 0, st, A, d_ref, ld);
     e = hipGetLastError();
     if (e != hipSuccess) rc = hip_fail(e, "grouping launch");
 
-    const size_t lds = sizeof(uint64_t) * cap + sizeof(double) * kRedStride * kMaxWpv;
+    // the re-ranking select keeps at most 8 n keys at or below tau in LDS
+    // (about 4 n are expected; more go to the exact fallback)
+    B.scap = std::min(cap, std::max(512, pow2_at_least(8 * (int)n_acc)));
+    const size_t lds = sizeof(uint64_t) * (mfma ? B.scap : cap) + sizeof(double) * kRedStride * kMaxWpv +
+                       (mfma ? 2 * sizeof(double) * (size_t)ld : 0);
     const int fb_cap = pow2_at_least((int)n_acc + 2 * kWave);
     int fb_waves = 8;
     while (fb_waves > 1 && (size_t)fb_waves * fb_cap * sizeof(uint64_t) > 48 * 1024) fb_waves >>= 1;
@@ -4159,6 +4301,7 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
         BankArgs Q = B;
         Q.bank_theta = LB.theta;
         Q.bank_logw = LB.logw;
+        Q.ref = d_ref ? d_ref + (size_t)g0 * ld : nullptr;
         if (mfma) bank_bops(Q, (unsigned)(ng * n_tot), st, ld);
         Q.V = nv;
         Q.pos0 = base;
@@ -4703,6 +4846,8 @@ int vpet_proposal_forward(const float* params, const float* tacs, int64_t n, int
     if (n < 0) return fail(VPET_E_ARG, "n must be >= 0");
     if (n == 0) return VPET_OK;
     if (!params || !tacs || !out) return fail(VPET_E_ARG, "params, tacs and out must not be NULL");
+    int dev;
+    if ((rc = current_device(&dev)) != VPET_OK) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     const long long rows = std::min<long long>(n, 1LL << 17);
     char* work = nullptr;
@@ -4731,6 +4876,8 @@ int vpet_proposal_loss_grad(const float* params, const float* tacs, const float*
     if (dims != 4 && dims != 5) return fail(VPET_E_ARG, "dims must be 4 or 5");
     if (n < 1 || n > (1LL << 20)) return fail(VPET_E_ARG, "n must lie in [1, 2^20]");
     if (!params || !tacs || !theta || !grad || !loss) return fail(VPET_E_ARG, "pointers must not be NULL");
+    int dev;
+    if ((rc = current_device(&dev)) != VPET_OK) return rc;
     hipStream_t st = (hipStream_t)hip_stream;
     char* work = nullptr;
     hipError_t e = hipMallocAsync((void**)&work, net_work_bytes(n), st);
