@@ -2063,28 +2063,86 @@ __device__ __forceinline__ void split_bf16x8(const float (&x)[8], uint4& hi, uin
 // lo*hi (three MFMAs, FP32 accumulation), relative error about 3 * 2^-16 per
 // term instead of 2^-7 for a plain bf16 product.
 // Block = 4 wavefronts = a 64 x 64 tile of C (a 32 x 32 tile per wavefront).
+// K advances in chunks of 32: the block stages the chunk's 64 x 32 slices of A
+// and B into LDS, split into bf16 hi and lo once, with loads in which
+// consecutive lanes read consecutive addresses along whichever of the
+// operand's two strides is 1 (the transposed operands of the backward pass
+// included); the wavefronts then read their MFMA fragments from LDS.  Two
+// buffers: the loads of chunk c+1 are issued before chunk c is multiplied.
+// The products and their order per 16-wide k step are those of one MFMA
+// chain per output tile, so the result does not depend on the staging.
+constexpr int kGemmKC = 32;                  // k per staged chunk
+constexpr int kGemmRS = kGemmKC + 8;         // LDS row stride (bf16), padded against bank conflicts
 __global__ __launch_bounds__(256) void vpet_gemm_bf16x3_kernel(GemmArgs G) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * 64 + (wave >> 1) * 32, n0 = blockIdx.x * 64 + (wave & 1) * 32;
-    const int am = m0 + (lane & 31), bn = n0 + (lane & 31), kk = 8 * (lane >> 5);
+    __shared__ __align__(16) uint16_t sm[2][4][64 * kGemmRS];  // [buffer][A hi, A lo, B hi, B lo][row][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int bm0 = blockIdx.y * 64, bn0 = blockIdx.x * 64;
+    const int m0 = bm0 + (wave >> 1) * 32, n0 = bn0 + (wave & 1) * 32;
     const int kbeg = blockIdx.z * G.kchunk, kend = min(G.K, kbeg + G.kchunk);
-    f32x16_t acc = {};
-    for (int k0 = kbeg; k0 < kend; k0 += 16) {
-        float a[8], b[8];
+    // staging map: element e = tid + 256 q (q < 8) of a 64 x 32 slice, the
+    // fast index along the operand's unit stride
+    const bool a_kfast = G.sak == 1, b_kfast = G.sbk == 1;
+    float av[8], bv[8];
+    auto load = [&](int k0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = k0 + kk + e;
-            a[e] = (am < G.M && k < kend) ? G.A[am * G.sam + (long long)k * G.sak] : 0.0f;
-            b[e] = (bn < G.N && k < kend) ? G.B[(long long)k * G.sbk + bn * G.sbn] : 0.0f;
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;
+            {
+                const int r = a_kfast ? (e >> 5) : (e & 63), k = a_kfast ? (e & 31) : (e >> 6);
+                const int m = bm0 + r, kk = k0 + k;
+                av[q] = (m < G.M && kk < kend) ? G.A[(long long)m * G.sam + (long long)kk * G.sak] : 0.0f;
+            }
+            {
+                const int r = b_kfast ? (e >> 5) : (e & 63), k = b_kfast ? (e & 31) : (e >> 6);
+                const int n = bn0 + r, kk = k0 + k;
+                bv[q] = (n < G.N && kk < kend) ? G.B[(long long)kk * G.sbk + (long long)n * G.sbn] : 0.0f;
+            }
         }
-        uint4 ah, al, bh, bl;
-        split_bf16x8(a, ah, al);
-        split_bf16x8(b, bh, bl);
-        const bf16x8_t Ah = __builtin_bit_cast(bf16x8_t, ah), Al = __builtin_bit_cast(bf16x8_t, al);
-        const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, bh), Bl = __builtin_bit_cast(bf16x8_t, bl);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc, 0, 0, 0);
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;
+            {
+                const int r = a_kfast ? (e >> 5) : (e & 63), k = a_kfast ? (e & 31) : (e >> 6);
+                const uint32_t h = bf16_rn(av[q]);
+                sm[buf][0][r * kGemmRS + k] = (uint16_t)h;
+                sm[buf][1][r * kGemmRS + k] = (uint16_t)bf16_rn(av[q] - __uint_as_float(h << 16));
+            }
+            {
+                const int r = b_kfast ? (e >> 5) : (e & 63), k = b_kfast ? (e & 31) : (e >> 6);
+                const uint32_t h = bf16_rn(bv[q]);
+                sm[buf][2][r * kGemmRS + k] = (uint16_t)h;
+                sm[buf][3][r * kGemmRS + k] = (uint16_t)bf16_rn(bv[q] - __uint_as_float(h << 16));
+            }
+        }
+    };
+    f32x16_t acc = {};
+    const int nchunks = kend > kbeg ? (kend - kbeg + kGemmKC - 1) / kGemmKC : 0;
+    if (nchunks > 0) {
+        load(kbeg);
+        stash(0);
+        __syncthreads();
+    }
+    const int ar = (wave >> 1) * 32 + (lane & 31), br = (wave & 1) * 32 + (lane & 31), kk = 8 * (lane >> 5);
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunks) load(kbeg + (c + 1) * kGemmKC);  // in flight while this chunk is multiplied
+#pragma unroll
+        for (int ks = 0; ks < kGemmKC / 16; ++ks) {
+            const int off = ks * 16 + kk;
+            const bf16x8_t Ah = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(&sm[buf][0][ar * kGemmRS + off]));
+            const bf16x8_t Al = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(&sm[buf][1][ar * kGemmRS + off]));
+            const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(&sm[buf][2][br * kGemmRS + off]));
+            const bf16x8_t Bl = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(&sm[buf][3][br * kGemmRS + off]));
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc, 0, 0, 0);
+        }
+        if (c + 1 < nchunks) {
+            stash(buf ^ 1);  // the other buffer was last read before the previous barrier
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -2098,8 +2156,8 @@ __global__ __launch_bounds__(256) void vpet_gemm_bf16x3_kernel(GemmArgs G) {
         if (G.bias) v += G.bias[n];
         if (G.relu) v = fmaxf(v, 0.0f);
         if (G.mask && !(G.mask[(long long)m * G.ldm + n] > 0.0f)) v = 0.0f;
-        float* c = G.C + (long long)m * G.ldc + n;
-        *c = G.accumulate ? *c + v : v;
+        float* cptr = G.C + (long long)m * G.ldc + n;
+        *cptr = G.accumulate ? *cptr + v : v;
     }
 }
 
