@@ -1815,11 +1815,16 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
         const long long v = vbase + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         cth[r] = PILOT ? __builtin_inff() : (v < P.V ? P.cthr[v] : -__builtin_inff());
     }
-    // SCAN: candidates found so far for voxel (lane % 32) of this wavefront.
-    // A wavefront owns its 32 voxels, so the counts live in one register and
-    // are read with readlane and updated by lane (no atomics).
-    unsigned cntv = 0u;
-    uint64_t* wcand = P.cand + (size_t)(vbase + wave * 32) * P.cap;
+    // SCAN: candidates found so far for each of the wavefront's 32 voxels.  A
+    // wavefront owns its voxels, so the counts are wave-uniform values (scalar
+    // registers: every index below is a compile-time constant) updated from
+    // ballots, with no atomics.
+    unsigned cnt_s[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) cnt_s[i] = 0u;
+    // this lane's list base: the lanes of the upper half-wave append for the
+    // voxel four above the lower half's (result layout of the 32x32 tile)
+    uint64_t* wcand = P.cand + (size_t)(vbase + wave * 32 + 4 * (lane >> 5)) * P.cap;
     const uint32_t lt = (1u << (lane & 31)) - 1u;  // lanes below mine in my half-wave
 
     // PILOT: ceil(n_pilot / TR) tiles spread evenly over the bank (it is
@@ -1835,12 +1840,13 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
     // 64, so the array is the same for the whole wavefront), row, column
     const uint16_t* c_src[CPT];
     int c_row[CPT], c_dst[CPT];
-    bool c_has[CPT];
+    bool c_has[CPT], c_hi[CPT];
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
         const int c = tid + 512 * u;
         c_has[u] = c < 2 * CA;
         const int arr = __builtin_amdgcn_readfirstlane(c / CA), rem = c - arr * CA;
+        c_hi[u] = arr == 0;
         c_row[u] = rem / (K / 8);
         const int col = rem - c_row[u] * (K / 8);
         c_src[u] = (arr ? P.blo : P.bhi) + col * 8;
@@ -1851,7 +1857,9 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const unsigned g = tile_row0(t) + c_row[u];
-            pre[u] = make_uint4(0, 0, 0, 0);
+            // rows past the bank: NaN hi parts, so that their products never pass a test
+            const uint32_t pad = c_hi[u] ? 0x7FC07FC0u : 0u;
+            pre[u] = make_uint4(pad, pad, pad, pad);
             if (c_has[u] && g < n_rows) pre[u] = *reinterpret_cast<const uint4*>(c_src[u] + (size_t)(gb + g) * K);
         }
     };
@@ -1872,24 +1880,24 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
             }
             return;
         }
-        const uint64_t live = __builtin_amdgcn_ballot_w64(g < n_rows);
+        // (rows past the bank compute NaN and pass no test)
+        const unsigned grow = gb + g;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const uint64_t b = __builtin_amdgcn_ballot_w64(acc[r] <= cth[r]) & live;
+            const bool hit = acc[r] <= cth[r];
+            const uint64_t b = __builtin_amdgcn_ballot_w64(hit);
             if (b == 0ull) continue;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const uint32_t bits = (uint32_t)(b >> (32 * h));
-                if (bits == 0u) continue;
-                const int i = 8 * (r >> 2) + 4 * h + (r & 3);  // voxel of this (r, half) in the wave
-                const unsigned base = __builtin_amdgcn_readlane(cntv, i);
-                if ((lane >> 5) == h && ((bits >> (lane & 31)) & 1u)) {
-                    const unsigned pos = base + (unsigned)__popc(bits & lt);
-                    if (pos < (unsigned)P.cap)
-                        wcand[(unsigned)i * (unsigned)P.cap + pos] = ((uint64_t)__float_as_uint(acc[r]) << 32) | (gb + g);
-                }
-                cntv = lane == i ? base + (unsigned)__popc(bits) : cntv;
+            // voxels of result r: i0 (lower half-wave) and i0 + 4 (upper)
+            const int i0 = 8 * (r >> 2) + (r & 3);
+            const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+            if (hit) {
+                const unsigned base = lane < 32 ? cnt_s[i0] : cnt_s[i0 + 4];
+                const unsigned pos = base + (unsigned)__popc((lane < 32 ? b0 : b1) & lt);
+                if (pos < (unsigned)P.cap)
+                    wcand[(unsigned)i0 * (unsigned)P.cap + pos] = ((uint64_t)__float_as_uint(acc[r]) << 32) | grow;
             }
+            cnt_s[i0] += (unsigned)__popc(b0);
+            cnt_s[i0 + 4] += (unsigned)__popc(b1);
         }
     };
     fetch(0);
@@ -1972,9 +1980,12 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
                 P.cthr1[v] = test_of(tau1, a);
             }
         }
-    } else if (lane < 32) {
+    } else {
+        unsigned cntv = 0u;  // voxel (lane % 32)'s count
+#pragma unroll
+        for (int i = 0; i < 32; ++i) cntv = (lane & 31) == i ? cnt_s[i] : cntv;
         const long long v = vbase + wave * 32 + lane;
-        if (v < P.V && P.cthr[v] > -__builtin_inff()) P.cnt[v] = (int)cntv;
+        if (lane < 32 && v < P.V && P.cthr[v] > -__builtin_inff()) P.cnt[v] = (int)cntv;
     }
 }
 
