@@ -39,6 +39,7 @@
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -1079,7 +1080,8 @@ struct BankArgs {
     int kinds[kMaxModels];
     float* tau;             // [V] pilot threshold (fp32 distance), NaN for an invalid voxel
     int* cnt;               // [V] candidates found (may exceed cap)
-    uint64_t* cand;         // [V][cap] candidate keys (FP64 scan)
+    int* cnt_hi;            // [V] of them, in the second half of the list (the rest are at its start)
+    uint64_t* cand;         // [V][cap] candidate keys
     int* fb_list;           // [V] voxels whose candidate list cannot certify the top n
     unsigned* fb_count;     // [1] entries in fb_list
     // BF16 contraction (L2 only): d = a_v + sum_k A_vk B_gk with
@@ -1121,6 +1123,11 @@ __device__ __forceinline__ unsigned bank_row_base(const BankArgs& P, long long r
 }
 __device__ __forceinline__ long long bank_out_row(const BankArgs& P, long long row) {
     return P.out_row ? (long long)P.out_row[P.pos0 + row] : row;
+}
+// Position in a voxel's list of its j-th candidate (c0 of them at the start,
+// the rest from the middle on).
+__device__ __forceinline__ int cand_slot(const BankArgs& P, int j, int c0) {
+    return j < c0 ? j : (P.cap >> 1) + (j - c0);
 }
 
 // Per-lane observed curve and weights of voxel `row` (a lane per voxel).
@@ -1290,7 +1297,10 @@ __global__ __launch_bounds__(256) void vpet_bank_scan_kernel(BankArgs P) {
                 ++c;
             }
         }
-        if (live) P.cnt[row] = valid ? c : -1;
+        if (live) {
+            P.cnt[row] = valid ? c : -1;
+            P.cnt_hi[row] = 0;
+        }
     }
 }
 
@@ -1508,6 +1518,7 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
         // adds the remaining candidates and the certificate is taken at tau.
         wave_curve_lds<LD, L1>(P, row, Ys, Ws);
         const uint64_t* src = P.cand + (size_t)row * P.cap;
+        const int c0 = c - P.cnt_hi[row];
         const float tau1 = P.tau1[row], cthr1 = P.cthr1[row];
         int below1 = 0;
         bool overflow = false;  // more keys at or below tau than the LDS holds: exact fallback
@@ -1517,7 +1528,7 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
                 uint64_t key = kNoKey;
                 bool take = false;
                 if (j < c) {
-                    const uint64_t e = src[j];
+                    const uint64_t e = src[cand_slot(P, j, c0)];
                     take = (__uint_as_float((uint32_t)(e >> 32)) <= cthr1) == (pass == 0);
                     if (take) {
                         const uint32_t g = (uint32_t)e;
@@ -1541,7 +1552,8 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
         }
     } else {
         const uint64_t* src = P.cand + (size_t)row * P.cap;
-        for (int j = lane_id(); j < c; j += kWave) keys[j] = src[j];
+        const int c0 = c - P.cnt_hi[row];
+        for (int j = lane_id(); j < c; j += kWave) keys[j] = src[cand_slot(P, j, c0)];
         below = c;
     }
     if (below < (int)P.n_acc) {
@@ -1609,6 +1621,7 @@ __global__ __launch_bounds__(256) void vpet_bank_passall_kernel(BankArgs P) {
     const double a = P.aval[v];
     P.cthr[v] = a == a ? __builtin_inff() : -__builtin_inff();
     P.cnt[v] = a == a ? 0 : -1;
+    P.cnt_hi[v] = 0;
 }
 
 // vpet_abc_bank_screen: voxel `blockIdx.x`'s candidates (computed S, bank row)
@@ -1620,9 +1633,10 @@ __global__ __launch_bounds__(256) void vpet_bank_scatter_kernel(BankArgs P, floa
     if (threadIdx.x == 0) out_a[v] = P.aval[v];
     __syncthreads();
     const int c = P.cnt[v];
+    const int c0 = c - P.cnt_hi[v];
     const uint64_t* src = P.cand + (size_t)v * P.cap;
     for (int j = threadIdx.x; j < c && j < P.cap; j += blockDim.x) {
-        const uint64_t e = src[j];
+        const uint64_t e = src[cand_slot(P, j, c0)];
         const uint32_t g = (uint32_t)e;
         if (g < P.n_tot) dst[g] = __uint_as_float((uint32_t)(e >> 32));
     }
@@ -1756,17 +1770,21 @@ __host__ __device__ constexpr double contraction_rel_err() {
 // One block = 256 voxels (8 wavefronts, 32 each) against the bank, in tiles of
 // 64 rows staged in LDS (double-buffered; the global loads of tile t+2 are
 // issued while tile t is multiplied and land in LDS one tile later; two
-// independent 32-row accumulators per wavefront).  Per tile
-// and k-step a wavefront issues v_mfma_f32_32x32x16_bf16 on the hi/lo parts:
-// hi*hi + hi*lo + lo*hi gives S ~ sum_k A B.
+// independent 32-row accumulators per wavefront).  Per tile and k-step a
+// wavefront issues v_mfma_f32_32x32x16_bf16 on the hi/lo parts, the bank rows
+// as the first operand and its voxels as the second: hi*hi + hi*lo + lo*hi
+// gives S ~ sum_k A B.  Result r of lane l is then voxel l % 32 of the
+// wavefront against row 8 (r/4) + 4 (l/32) + r%4 of the 32-row half: a lane
+// serves one voxel, and its two half-wavefronts see 16 of every 32 rows each.
 //
 // PILOT (n_pilot rows, taken from tiles spread evenly over the bank, which is
-// ordered by model): lane l keeps, for each of its 16 voxels, the
-// minimum of S over the rows = l mod 32; the 16th smallest of a voxel's 32
-// column minima, plus a_v, is its threshold tau_v (rounded to fp32).  With
-// n_pilot = 5.5 N / n about 4 n bank rows fall below tau_v (order statistics of
-// the column minima); tau_v only steers the work -- the selection certifies or
-// falls back.  The candidate threshold is
+// ordered by model): for each of its 16 results a lane keeps the minimum of S
+// over that result's rows (one class of rows mod 32), so a voxel's 32 class
+// minima sit in lanes l and l + 32; the 16th smallest of them, plus a_v, is
+// its threshold tau_v (rounded to fp32).  With n_pilot = 5.5 N / n about 4 n
+// bank rows fall below tau_v (order statistics of the class minima); tau_v
+// only steers the work -- the selection certifies or falls back.  The
+// candidate threshold is
 //   cthr_v = tau_v - a_v + m E_tau + 1e-6 (a_v + |tau_v|),
 // m = contraction_rel_err, E_tau = 3 a_v + 4 sqrt(a_v tau_v) + tau_v: for any
 // pair with exact distance d <= tau_v, |x| <= |y| + |y - x| and Cauchy-Schwarz
@@ -1775,11 +1793,11 @@ __host__ __device__ constexpr double contraction_rel_err() {
 // roundings of tau_v, a_v and cthr_v.
 //
 // SCAN (every row): a (voxel, row) pair is a candidate when S <= cthr_v, so
-// every row whose exact distance is <= tau_v is a candidate; the bank rows are
-// appended to the voxel's list (LDS counters, at most cap stored, the full
-// count kept).
-// Lane layout (32x32x16): A row = lane % 32, B column = lane % 32,
-// k = 16 ks + 8 (lane / 32) + e; result r of a lane is row 8 (r/4) + 4 (lane/32) + r%4.
+// every row whose exact distance is <= tau_v is a candidate.  A voxel's list
+// has two halves of cap / 2 entries, one per half-wavefront: each lane appends
+// its voxel's candidates to its own half with a count in a register, so a
+// candidate costs no cross-lane work.  cnt = both halves' count (cap + 1 when
+// either half overflowed), cnt_hi = the second half's.
 template <int K, bool PILOT>
 __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
     constexpr int KS = K / 16;
@@ -1790,42 +1808,38 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
     static_assert(CA % 64 == 0 && CPT <= 3, "whole wavefronts per array, at most three chunks per thread");
     __shared__ __align__(16) unsigned char tile[2][2][TR * RS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned half = (unsigned)lane >> 5;
     const long long vbase = (long long)blockIdx.x * kMfmaVox;
     const unsigned gb = bank_row_base(P, vbase);  // the block's bank (groups hold whole 256-voxel tiles)
 
-    const long long arow = vbase + wave * 32 + (lane & 31);
+    // this lane's voxel; its operand is the second MFMA operand (k = 16 ks + 8 half + e)
+    const long long v = vbase + wave * 32 + (lane & 31);
     bf16x8_t ah[KS], al[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         uint4 h = make_uint4(0, 0, 0, 0), l = make_uint4(0, 0, 0, 0);
-        if (arow < P.V) {
-            const size_t off = (size_t)arow * K + ks * 16 + (lane >> 5) * 8;
+        if (v < P.V) {
+            const size_t off = (size_t)v * K + ks * 16 + half * 8;
             h = *reinterpret_cast<const uint4*>(P.ahi + off);
             l = *reinterpret_cast<const uint4*>(P.alo + off);
         }
         ah[ks] = __builtin_bit_cast(bf16x8_t, h);
         al[ks] = __builtin_bit_cast(bf16x8_t, l);
     }
-    // result r of this lane belongs to voxel 8 (r/4) + 4 (lane/32) + r%4 of the
-    // wavefront.  SCAN: that voxel's candidate threshold; PILOT: the running
-    // minimum of S over this lane's column.
-    float cth[16];
+    // SCAN: the voxel's candidate threshold.  PILOT: per result, the running
+    // minimum of S over its class of rows.
+    const float cth = PILOT ? 0.0f : (v < P.V ? P.cthr[v] : -__builtin_inff());
+    float cmin[PILOT ? 16 : 1];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const long long v = vbase + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        cth[r] = PILOT ? __builtin_inff() : (v < P.V ? P.cthr[v] : -__builtin_inff());
-    }
-    // SCAN: candidates found so far for each of the wavefront's 32 voxels.  A
-    // wavefront owns its voxels, so the counts are wave-uniform values (scalar
-    // registers: every index below is a compile-time constant) updated from
-    // ballots, with no atomics.
-    unsigned cnt_s[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) cnt_s[i] = 0u;
-    // this lane's list base: the lanes of the upper half-wave append for the
-    // voxel four above the lower half's (result layout of the 32x32 tile)
-    uint64_t* wcand = P.cand + (size_t)(vbase + wave * 32 + 4 * (lane >> 5)) * P.cap;
-    const uint32_t lt = (1u << (lane & 31)) - 1u;  // lanes below mine in my half-wave
+    for (int r = 0; r < (PILOT ? 16 : 1); ++r) cmin[r] = __builtin_inff();
+    // SCAN: this lane's half of its voxel's list, as byte offsets from the
+    // block's first list (256 lists of at most 8192 entries: 32 bits suffice):
+    // its start, its last entry and the next free entry
+    const unsigned hcap = (unsigned)P.cap >> 1;
+    unsigned char* blist = reinterpret_cast<unsigned char*>(P.cand + (size_t)vbase * (size_t)P.cap);
+    const unsigned loff = ((unsigned)(wave * 32 + (lane & 31)) * (unsigned)P.cap + half * hcap) * 8u;
+    const unsigned llast = loff + (hcap - 1u) * 8u;
+    unsigned lnext = loff;
 
     // PILOT: ceil(n_pilot / TR) tiles spread evenly over the bank (it is
     // ordered by model, so a prefix would see one model only)
@@ -1868,36 +1882,28 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
         for (int u = 0; u < CPT; ++u)
             if (c_has[u]) *reinterpret_cast<uint4*>(&tile[buf][0][0] + c_dst[u]) = pre[u];
     };
-    // screen one 32-row half: r-th results against the thresholds, passing
-    // rows appended to their voxel's list
-    // j0: position of the half's first row in the pilot sample (PILOT only)
+    // screen one 32-row half starting at bank row g0 (j0: its position in the
+    // pilot sample); result r is row g0 + 8 (r/4) + 4 half + r%4
     auto screen = [&](const f32x16_t& acc, unsigned g0, unsigned j0) {
-        const unsigned g = g0 + (lane & 31);
         if (PILOT) {
-            if (g < n_rows && j0 + (lane & 31) < P.n_pilot) {
+            // (rows past the bank compute NaN, which fminf ignores)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) cth[r] = fminf(cth[r], acc[r]);
+            for (int r = 0; r < 16; ++r) {
+                const unsigned o = 8u * (r >> 2) + 4u * half + (r & 3);
+                if (j0 + o < P.n_pilot) cmin[r] = fminf(cmin[r], acc[r]);
             }
             return;
         }
-        // (rows past the bank compute NaN and pass no test)
-        const unsigned grow = gb + g;
+        const unsigned grow = gb + g0 + 4u * half;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const bool hit = acc[r] <= cth[r];
-            const uint64_t b = __builtin_amdgcn_ballot_w64(hit);
-            if (b == 0ull) continue;
-            // voxels of result r: i0 (lower half-wave) and i0 + 4 (upper)
-            const int i0 = 8 * (r >> 2) + (r & 3);
-            const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-            if (hit) {
-                const unsigned base = lane < 32 ? cnt_s[i0] : cnt_s[i0 + 4];
-                const unsigned pos = base + (unsigned)__popc((lane < 32 ? b0 : b1) & lt);
-                if (pos < (unsigned)P.cap)
-                    wcand[(unsigned)i0 * (unsigned)P.cap + pos] = ((uint64_t)__float_as_uint(acc[r]) << 32) | grow;
+            if (acc[r] <= cth) {
+                // past the end of the half the last entry is overwritten: the
+                // count reports the overflow
+                *reinterpret_cast<uint64_t*>(blist + min(lnext, llast)) =
+                    ((uint64_t)__float_as_uint(acc[r]) << 32) | (grow + 8u * (r >> 2) + (r & 3));
+                lnext += 8u;
             }
-            cnt_s[i0] += (unsigned)__popc(b0);
-            cnt_s[i0 + 4] += (unsigned)__popc(b1);
         }
     };
     fetch(0);
@@ -1915,46 +1921,62 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
         f32x16_t acc0 = {}, acc1 = {};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const int off = (lane & 31) * RS + (ks * 16 + (lane >> 5) * 8) * 2;
+            const int off = (lane & 31) * RS + (ks * 16 + half * 8) * 2;
             const unsigned char* hi = &tile[buf][0][0];
             const unsigned char* lo = hi + TR * RS;
             const bf16x8_t bh0 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(hi + off));
             const bf16x8_t bl0 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(lo + off));
             const bf16x8_t bh1 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(hi + 32 * RS + off));
             const bf16x8_t bl1 = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const uint4*>(lo + 32 * RS + off));
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bh0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bh1, acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bl0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bl1, acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ks], bh0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ks], bh1, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh0, ah[ks], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh1, ah[ks], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl0, ah[ks], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl1, ah[ks], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh0, al[ks], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh1, al[ks], acc1, 0, 0, 0);
         }
         screen(acc0, tile_row0(t), t * TR);
         screen(acc1, tile_row0(t) + kMfmaRows, t * TR + kMfmaRows);
         __syncthreads();
     }
     if (PILOT) {
-        // ascending bitonic sort of each voxel's 32 column minima across the
-        // 32 lanes of its half-wavefront; lane 15 of the half then holds the
-        // 16th smallest
-        const int l = lane & 31;
+        // ascending bitonic sort of the lane's 16 class minima, in registers
 #pragma unroll
-        for (int k = 2; k <= 32; k <<= 1) {
+        for (int k = 2; k <= 16; k <<= 1) {
 #pragma unroll
             for (int j = k >> 1; j > 0; j >>= 1) {
-                const bool keep_min = ((l & j) == 0) == ((l & k) == 0);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const float o = __shfl_xor(cth[r], j, kWave);
-                    cth[r] = keep_min ? fminf(cth[r], o) : fmaxf(cth[r], o);
+                for (int i = 0; i < 16; ++i) {
+                    const int p = i ^ j;
+                    if (p > i) {
+                        const float x = cmin[i], y = cmin[p];
+                        const bool up = (i & k) == 0;
+                        cmin[i] = up ? fminf(x, y) : fmaxf(x, y);
+                        cmin[p] = up ? fmaxf(x, y) : fminf(x, y);
+                    }
                 }
             }
         }
-        // the 8th smallest (lane 7 of the half) gives the first threshold
-        float c8[16];
+        // the other half-wavefront's sorted minima of the same voxel; the k-th
+        // smallest of the two sorted lists a, b is the minimum over i of
+        // max(a[i-1], b[k-1-i]) (an empty side counting as -inf)
+        float pm[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) c8[r] = __shfl(cth[r], (lane & 32) + kBankTopK / 2 - 1, kWave);
-        if (l == kBankTopK - 1) {
+        for (int r = 0; r < 16; ++r) pm[r] = __shfl_xor(cmin[r], 32, kWave);
+        auto kth = [&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            float best = __builtin_inff();
+#pragma unroll
+            for (int i = 0; i <= k; ++i) {
+                const float x = i > 0 ? cmin[i > 0 ? i - 1 : 0] : -__builtin_inff();
+                const float y = i < k ? pm[i < k ? k - 1 - i : 0] : -__builtin_inff();
+                best = fminf(best, fmaxf(x, y));
+            }
+            return best;
+        };
+        const float c16 = kth(std::integral_constant<int, kBankTopK>{});
+        const float c8 = kth(std::integral_constant<int, kBankTopK / 2>{});
+        if (half == 0 && v < P.V) {
             constexpr double m = contraction_rel_err<K>();
             // candidate test of threshold t: t - a + m E_t, E_t = 3a + 4 sqrt(a t) + t
             auto test_of = [&](float t, double a) {
@@ -1962,18 +1984,12 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
                 const double e_t = 3.0 * a + 4.0 * sqrt(a * tp) + tp;
                 return (float)((double)t - a + m * e_t + 1e-6 * (a + fabs((double)t)));
             };
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const long long v = vbase + wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (v >= P.V) continue;
-                const double a = P.aval[v];
-                if (!(a == a)) continue;  // invalid voxel: marked by the operand kernel
-                if (a < 0.0) {            // negative weights: no bound, every row a candidate
-                    P.tau[v] = P.tau1[v] = __builtin_inff();
-                    P.cthr[v] = P.cthr1[v] = __builtin_inff();
-                    continue;
-                }
-                const float tau = (float)(a + (double)cth[r]), tau1 = (float)(a + (double)c8[r]);
+            const double a = P.aval[v];
+            if (a < 0.0) {  // negative weights: no bound, every row a candidate
+                P.tau[v] = P.tau1[v] = __builtin_inff();
+                P.cthr[v] = P.cthr1[v] = __builtin_inff();
+            } else if (a == a) {  // (NaN: invalid voxel, marked by the operand kernel)
+                const float tau = (float)(a + (double)c16), tau1 = (float)(a + (double)c8);
                 P.tau[v] = tau;
                 P.cthr[v] = test_of(tau, a);
                 P.tau1[v] = tau1;
@@ -1981,11 +1997,11 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
             }
         }
     } else {
-        unsigned cntv = 0u;  // voxel (lane % 32)'s count
-#pragma unroll
-        for (int i = 0; i < 32; ++i) cntv = (lane & 31) == i ? cnt_s[i] : cntv;
-        const long long v = vbase + wave * 32 + lane;
-        if (lane < 32 && v < P.V && P.cthr[v] > -__builtin_inff()) P.cnt[v] = (int)cntv;
+        const unsigned cnt = (lnext - loff) >> 3, other = __shfl_xor(cnt, 32, kWave);
+        if (half == 0 && v < P.V && cth > -__builtin_inff()) {
+            P.cnt[v] = (cnt > hcap || other > hcap) ? P.cap + 1 : (int)(cnt + other);
+            P.cnt_hi[v] = (int)other;
+        }
     }
 }
 
@@ -3965,7 +3981,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     const long long cv = std::min<long long>(n_voxels, chunk);
     const int KB = 2 * ld;  // contraction length: [x, x^2] per frame
     char* work = nullptr;
-    const size_t sz_tau = align256(sizeof(float) * cv), sz_cnt = align256(sizeof(int) * cv);
+    const size_t sz_tau = align256(sizeof(float) * cv), sz_cnt = align256(sizeof(int) * 2 * cv);
     const size_t sz_fb = align256(sizeof(int) * cv) + 256, sz_cand = align256(cand_bytes * (size_t)cap * cv);
     const size_t sz_b = use_mfma ? align256(sizeof(uint16_t) * (size_t)KB * n_tot) : 0;
     const size_t sz_a = use_mfma ? align256(sizeof(uint16_t) * (size_t)KB * cv) : 0;
@@ -3977,6 +3993,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     A.tau = reinterpret_cast<float*>(q);
     q += sz_tau;
     A.cnt = reinterpret_cast<int*>(q);
+    A.cnt_hi = A.cnt + cv;
     q += sz_cnt;
     A.fb_count = reinterpret_cast<unsigned*>(q);
     A.fb_list = reinterpret_cast<int*>(q + 256);
@@ -4166,7 +4183,7 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
                  sz_bx = a256(sizeof(double) * (size_t)ld * rows_c),
                  sz_bw = gp.out_bank_logw ? 0 : a256(sizeof(double) * rows_c),
                  sz_b = mfma ? a256(sizeof(uint16_t) * (size_t)KB * rows_c) : 0;
-    const size_t sz_tau = a256(sizeof(float) * cv), sz_cnt = a256(sizeof(int) * cv),
+    const size_t sz_tau = a256(sizeof(float) * cv), sz_cnt = a256(sizeof(int) * 2 * cv),
                  sz_fb = a256(sizeof(int) * cv) + 256, sz_cand = a256(sizeof(uint64_t) * (size_t)cap * cv),
                  sz_a = mfma ? a256(sizeof(uint16_t) * (size_t)KB * cv) : 0, sz_c = mfma ? a256(sizeof(float) * cv) : 0,
                  sz_av = mfma ? a256(sizeof(double) * cv) : 0;
@@ -4267,6 +4284,7 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
     }
     B.tau = reinterpret_cast<float*>(carve(sz_tau));
     B.cnt = reinterpret_cast<int*>(carve(sz_cnt));
+    B.cnt_hi = B.cnt + cv;
     {
         char* fb = carve(sz_fb);
         B.fb_count = reinterpret_cast<unsigned*>(fb);
@@ -4425,7 +4443,8 @@ int vpet_abc_bank_screen(const float* tacs, int64_t n_voxels, const float* frame
     if (n_voxels == 0) return VPET_OK;
     if (!tacs || !bank_x || !out_s || !out_a) return fail(VPET_E_ARG, "device pointers must not be NULL");
     const int F = grid.n_frames, ld = vpet_abc_bank_ld(F), KB = 2 * ld;
-    const int cap = pow2_at_least((int)n_rows);
+    // each half of a list can hold every row (the contraction scan fills both)
+    const int cap = 2 * pow2_at_least((int)n_rows);
     BankArgs A{};
     A.tacs = tacs;
     A.weights = o.weights;
@@ -4447,7 +4466,7 @@ int vpet_abc_bank_screen(const float* tacs, int64_t n_voxels, const float* frame
     if ((rc = upload_blob(*ctx, omega.data(), sizeof(double) * F, st, &dom, slot)) != VPET_OK) return rc;
     A.omega = static_cast<const double*>(dom);
     const size_t V = (size_t)n_voxels;
-    const size_t sz_cnt = align256(sizeof(int) * V), sz_cand = align256(sizeof(uint64_t) * (size_t)cap * V);
+    const size_t sz_cnt = align256(sizeof(int) * 2 * V), sz_cand = align256(sizeof(uint64_t) * (size_t)cap * V);
     const size_t sz_b = align256(sizeof(uint16_t) * (size_t)KB * (size_t)n_rows);
     const size_t sz_a = align256(sizeof(uint16_t) * (size_t)KB * V);
     const size_t sz_c = align256(sizeof(float) * V), sz_av = align256(sizeof(double) * V);
@@ -4456,6 +4475,7 @@ int vpet_abc_bank_screen(const float* tacs, int64_t n_voxels, const float* frame
     if (e != hipSuccess) return fail(VPET_E_NOMEM, "screen work: %s", hipGetErrorString(e));
     char* q = work;
     A.cnt = reinterpret_cast<int*>(q);
+    A.cnt_hi = A.cnt + V;
     q += sz_cnt;
     A.cand = reinterpret_cast<uint64_t*>(q);
     q += sz_cand;
