@@ -1167,54 +1167,53 @@ __device__ __forceinline__ bool lane_curve(const BankArgs& P, long long row, dou
     return !bad && ymax > 0.0f;
 }
 
-// Distance of one bank row to the lane's voxel; the row is wave-uniform, so
-// its values are scalar operands.
-template <int LD, bool L1>
-__device__ __forceinline__ double bank_distance(cdp xr, const double (&Y)[LD], const double (&Wt)[LD]) {
-    double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-    for (int f = 0; f < LD; f += 2) {
-        const double r0 = Y[f] - xr[f];
-        const double r1 = Y[f + 1] - xr[f + 1];
-        if (L1) {
-            d0 = fma(Wt[f], fabs(r0), d0);
-            d1 = fma(Wt[f + 1], fabs(r1), d1);
-        } else {
-            d0 = fma(Wt[f] * r0, r0, d0);
-            d1 = fma(Wt[f + 1] * r1, r1, d1);
-        }
-    }
-    return d0 + d1;
+// Exact distance of a bank row to a voxel, in one fixed order on every path:
+// four partial sums over consecutive quarters of the (padded) frames, each an
+// FMA chain in frame order, added as (p0 + p1) + (p2 + p3).  The re-ranking
+// select computes a quarter per lane (four lanes per row); the FP64 scan and
+// the exact fallback compute all four in one lane.  A row therefore has the
+// same FP64 distance whichever path ranks it.
+template <bool L1>
+__device__ __forceinline__ double dist_term(double y, double w, double x, double acc) {
+    const double r = y - x;
+    return L1 ? fma(w, fabs(r), acc) : fma(w * r, r, acc);
 }
 
-// The same distance from a per-lane row pointer (identical operation order, so
-// every path ranks a row with the same FP64 value).
+// The row is wave-uniform (FP64 scan), so its values are scalar operands.
+template <int LD, bool L1>
+__device__ __forceinline__ double bank_distance(cdp xr, const double (&Y)[LD], const double (&Wt)[LD]) {
+    constexpr int Q = LD / 4;
+    double p[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        p[t] = 0.0;
+#pragma unroll
+        for (int f = t * Q; f < (t + 1) * Q; ++f) p[t] = dist_term<L1>(Y[f], Wt[f], xr[f], p[t]);
+    }
+    return (p[0] + p[1]) + (p[2] + p[3]);
+}
+
+// The same from a per-lane row pointer (exact fallback).
 template <int LD, bool L1>
 __device__ __forceinline__ double row_distance(const double* xr, const double (&Y)[LD], const double (&Wt)[LD]) {
-    double d0 = 0.0, d1 = 0.0;
+    constexpr int Q = LD / 4;
+    double p[4];
 #pragma unroll
-    for (int f = 0; f < LD; f += 2) {
-        const double r0 = Y[f] - xr[f];
-        const double r1 = Y[f + 1] - xr[f + 1];
-        if (L1) {
-            d0 = fma(Wt[f], fabs(r0), d0);
-            d1 = fma(Wt[f + 1], fabs(r1), d1);
-        } else {
-            d0 = fma(Wt[f] * r0, r0, d0);
-            d1 = fma(Wt[f + 1] * r1, r1, d1);
-        }
+    for (int t = 0; t < 4; ++t) {
+        p[t] = 0.0;
+#pragma unroll
+        for (int f = t * Q; f < (t + 1) * Q; ++f) p[t] = dist_term<L1>(Y[f], Wt[f], xr[f], p[t]);
     }
-    return d0 + d1;
+    return (p[0] + p[1]) + (p[2] + p[3]);
 }
 
 // The voxel's curve and weights (as lane_curve computes them, padding frames
 // 0) written once to LDS by the first LD lanes of a wavefront; every lane then
 // reads them as broadcast operands.
 template <int LD, bool L1>
-__device__ __forceinline__ void wave_curve_lds(const BankArgs& P, long long row, double* Ys, double* Ws) {
-    const int f = lane_id();
-    const float* y = P.tacs + (size_t)row * P.F;
-    const float yy = (f < P.F) ? y[f] : 0.0f;
+__device__ __forceinline__ void wave_curve_lds(const BankArgs& P, long long row, float yy, double* Ys,
+                                               double* Ws) {
+    const int f = lane_id();  // yy: the TAC value of frame f (0 past the last frame)
     float ymax = (f < P.F) ? yy : -__builtin_inff();
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) ymax = fmaxf(ymax, __shfl_xor(ymax, off, kWave));
@@ -1234,26 +1233,6 @@ __device__ __forceinline__ void wave_curve_lds(const BankArgs& P, long long row,
         Ws[f] = w;
     }
     wave_lds_sync();
-}
-
-// row_distance with the voxel's curve and weights in LDS (the same operations
-// in the same order).
-template <int LD, bool L1>
-__device__ __forceinline__ double row_distance_lds(const double* xr, const double* Ys, const double* Ws) {
-    double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-    for (int f = 0; f < LD; f += 2) {
-        const double r0 = Ys[f] - xr[f];
-        const double r1 = Ys[f + 1] - xr[f + 1];
-        if (L1) {
-            d0 = fma(Ws[f], fabs(r0), d0);
-            d1 = fma(Ws[f + 1], fabs(r1), d1);
-        } else {
-            d0 = fma(Ws[f] * r0, r0, d0);
-            d1 = fma(Ws[f + 1] * r1, r1, d1);
-        }
-    }
-    return d0 + d1;
 }
 
 __device__ __forceinline__ float key_dist(double d) {
@@ -1330,6 +1309,7 @@ __device__ __forceinline__ void bank_slot_values(int kind, const float* t, doubl
 }
 
 __device__ double block_max(double v, double* red, int nw);
+constexpr int kOutCache = 2;  // accepted keys per thread whose values the output passes keep in registers
 
 // Weighted outputs (bank rows with log weights, the learned-proposal bank):
 // of the n accepted keys those at or below the voxel's given threshold (if
@@ -1347,14 +1327,32 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
         lw = P.bank_logw[(uint32_t)acc[j]];
         return lw > -__builtin_inf();
     };
+    // the first kOutCache keys of this thread keep their log weight, weight
+    // and values in registers across the passes (the same sums in the same
+    // order as reading them again)
+    double c_lw[kOutCache], c_w[kOutCache], c_val[kOutCache][8];
+    bool c_ok[kOutCache];
     double lmax = -__builtin_inf();
-    for (int j = tid; j < n; j += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < kOutCache; ++i) {
+        const int j = tid + i * (int)blockDim.x;
+        c_ok[i] = j < n && log_w(j, c_lw[i]);
+        if (c_ok[i]) lmax = fmax(lmax, c_lw[i]);
+    }
+    for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
         double lw;
         if (log_w(j, lw)) lmax = fmax(lmax, lw);
     }
     lmax = block_max(lmax, red, nw);
     double tot[2] = {0.0, 0.0};  // sum w, sum w^2 over every model
-    for (int j = tid; j < n; j += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < kOutCache; ++i) {
+        if (!c_ok[i]) continue;
+        c_w[i] = exp(c_lw[i] - lmax);
+        tot[0] += c_w[i];
+        tot[1] = fma(c_w[i], c_w[i], tot[1]);
+    }
+    for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
         double lw;
         if (!log_w(j, lw)) continue;
         const double w = exp(lw - lmax);
@@ -1367,8 +1365,19 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
         double s1[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) s1[q] = 0.0;
+        bool c_m[kOutCache];
+#pragma unroll
+        for (int i = 0; i < kOutCache; ++i) {
+            const int j = tid + i * (int)blockDim.x;
+            c_m[i] = c_ok[i] && ((uint32_t)acc[j] - gb) / P.n_draws == (uint32_t)m;
+            if (!c_m[i]) continue;
+            bank_slot_values(kind, P.bank_theta + (size_t)(uint32_t)acc[j] * VPET_PSTRIDE, c_val[i]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s1[q] = fma(c_w[i], c_val[i][q], s1[q]);
+            s1[8] += c_w[i];
+        }
         double val[8];
-        for (int j = tid; j < n; j += blockDim.x) {
+        for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
             double lw;
             const uint32_t g = (uint32_t)acc[j];
             if (!log_w(j, lw) || (g - gb) / P.n_draws != (uint32_t)m) continue;
@@ -1386,7 +1395,16 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
             mean[q] = s1[q] / sw;
             s2[q] = 0.0;
         }
-        for (int j = tid; j < n; j += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < kOutCache; ++i) {
+            if (!c_m[i]) continue;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double dv = c_val[i][q] - mean[q];
+                s2[q] = fma(c_w[i] * dv, dv, s2[q]);
+            }
+        }
+        for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
             double lw;
             const uint32_t g = (uint32_t)acc[j];
             if (!log_w(j, lw) || (g - gb) / P.n_draws != (uint32_t)m) continue;
@@ -1431,8 +1449,22 @@ __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* a
         double s1[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) s1[q] = 0.0;
+        // the first kOutCache keys of this thread keep their values in
+        // registers for the second pass (the same sums in the same order)
+        double c_val[kOutCache][8];
+        bool c_m[kOutCache];
+#pragma unroll
+        for (int i = 0; i < kOutCache; ++i) {
+            const int j = tid + i * (int)blockDim.x;
+            c_m[i] = j < n && ((uint32_t)acc[j] - gb) / P.n_draws == (uint32_t)m;
+            if (!c_m[i]) continue;
+            bank_slot_values(kind, P.bank_theta + (size_t)(uint32_t)acc[j] * VPET_PSTRIDE, c_val[i]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s1[q] += c_val[i][q];
+            s1[8] += 1.0;
+        }
         double val[8];
-        for (int j = tid; j < n; j += blockDim.x) {
+        for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
             const uint32_t g = (uint32_t)acc[j];
             if ((g - gb) / P.n_draws != (uint32_t)m) continue;
             bank_slot_values(kind, P.bank_theta + (size_t)g * VPET_PSTRIDE, val);
@@ -1448,7 +1480,16 @@ __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* a
             mean[q] = s1[q] / cnt;
             s2[q] = 0.0;
         }
-        for (int j = tid; j < n; j += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < kOutCache; ++i) {
+            if (!c_m[i]) continue;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double dv = c_val[i][q] - mean[q];
+                s2[q] = fma(dv, dv, s2[q]);
+            }
+        }
+        for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
             const uint32_t g = (uint32_t)acc[j];
             if ((g - gb) / P.n_draws != (uint32_t)m) continue;
             bank_slot_values(kind, P.bank_theta + (size_t)g * VPET_PSTRIDE, val);
@@ -1496,7 +1537,7 @@ __device__ void bank_invalid(const BankArgs& P, long long row) {
 // otherwise -- or when the buffer overflowed -- the voxel is marked for the
 // exact fallback.
 template <int LD, bool L1, bool RECOMPUTE>
-__global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vpet_bank_select_kernel(BankArgs P) {
     extern __shared__ __align__(16) unsigned char lds[];
     uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
     double* red = reinterpret_cast<double*>(keys + (RECOMPUTE ? P.scap : P.cap));
@@ -1504,7 +1545,13 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
     double* Ws = Ys + LD;
     const long long row = blockIdx.x;
     if (row >= P.V) return;
+    // the voxel's scalars and (RECOMPUTE) its TAC value of this lane's frame,
+    // loaded together: the kernel is bound by the latency of such round trips
     const int c = P.cnt[row];
+    const int c_hi = RECOMPUTE ? P.cnt_hi[row] : 0;
+    const float tau = P.tau[row];
+    const float tau1 = RECOMPUTE ? P.tau1[row] : 0.0f, cthr1 = RECOMPUTE ? P.cthr1[row] : 0.0f;
+    const float y_lane = (RECOMPUTE && lane_id() < P.F) ? P.tacs[(size_t)row * P.F + lane_id()] : 0.0f;
     if (c < 0) {
         bank_invalid(P, row);
         return;
@@ -1513,41 +1560,91 @@ __global__ __launch_bounds__(64) void vpet_bank_select_kernel(BankArgs P) {
         if (threadIdx.x == 0) P.fb_list[atomicAdd(P.fb_count, 1u)] = (int)row;
         return;
     }
-    const float tau = P.tau[row];
     int below = 0;
     if (RECOMPUTE) {
-        // exact FP64 distances of the candidate rows (a row per lane), keys up
-        // to tau packed to the front.  Pass 1 takes the rows that passed the
-        // tighter test (computed S <= cthr1); if at least n of them lie at or
-        // below tau1, the n smallest keys are among them.  Otherwise pass 2
-        // adds the remaining candidates and the certificate is taken at tau.
-        wave_curve_lds<LD, L1>(P, row, Ys, Ws);
+        // Exact FP64 distances of the candidate rows, keys up to tau packed to
+        // the front.  Pass 1 takes the rows that passed the tighter test
+        // (computed S <= cthr1); if at least n of them lie at or below tau1,
+        // the n smallest keys are among them.  Otherwise pass 2 adds the
+        // remaining candidates and the certificate is taken at tau.  Taken
+        // rows queue up in LDS; a batch of up to 64 is ranked 16 rows at a
+        // time, four lanes per row, each lane a quarter of the frames
+        // (16-byte loads of whole row segments).
+        wave_curve_lds<LD, L1>(P, row, y_lane, Ys, Ws);
+        uint32_t* queue = reinterpret_cast<uint32_t*>(Ws + LD);  // 2 x 64 rows
         const uint64_t* src = P.cand + (size_t)row * P.cap;
-        const int c0 = c - P.cnt_hi[row];
-        const float tau1 = P.tau1[row], cthr1 = P.cthr1[row];
-        int below1 = 0;
+        const int c0 = c - c_hi;
+        const int lane = lane_id(), part = lane & 3;
+        constexpr int Q = LD / 4;
+        double Yq[Q], Wq[Q];  // this lane's quarter of the curve and weights
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            Yq[q] = Ys[part * Q + q];
+            Wq[q] = Ws[part * Q + q];
+        }
+        int below1 = 0, queued = 0;
         bool overflow = false;  // more keys at or below tau than the LDS holds: exact fallback
+        auto rank = [&](int nb) {  // queue[0, nb), nb <= 64: 32 rows per round, their loads issued together
+            for (int i0 = 0; i0 < nb; i0 += 32) {
+                uint32_t g[2];
+                double xv[2][Q];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = i0 + 16 * h + (lane >> 2);
+                    g[h] = queue[i < nb ? i : 0];
+                    const double* xr = static_cast<const double*>(
+                        __builtin_assume_aligned(P.bank_x + (size_t)g[h] * LD + part * Q, 16));
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) xv[h][q] = xr[q];
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bool live = i0 + 16 * h + (lane >> 2) < nb;
+                    double pt = 0.0;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) pt = dist_term<L1>(Yq[q], Wq[q], xv[h][q], pt);
+                    pt += __shfl_xor(pt, 1, kWave);  // p0 + p1, p2 + p3
+                    pt += __shfl_xor(pt, 2, kWave);  // (p0 + p1) + (p2 + p3)
+                    const float fd = key_dist(pt);
+                    const bool mine = live && part == 0;
+                    const bool keep = mine && fd <= tau;
+                    const uint64_t b = __ballot(keep);
+                    overflow = overflow || below + __popcll(b) > P.scap;
+                    if (keep && !overflow) keys[below + (int)mbcnt(b)] = ((uint64_t)__float_as_uint(fd) << 32) | g[h];
+                    below += __popcll(b);
+                    below1 += __popcll(__ballot(mine && fd <= tau1));
+                }
+            }
+        };
         for (int pass = 0; pass < 2; ++pass) {
-            for (int j0 = 0; j0 < c; j0 += kWave) {
-                const int j = j0 + lane_id();
-                uint64_t key = kNoKey;
-                bool take = false;
-                if (j < c) {
-                    const uint64_t e = src[cand_slot(P, j, c0)];
-                    take = (__uint_as_float((uint32_t)(e >> 32)) <= cthr1) == (pass == 0);
-                    if (take) {
-                        const uint32_t g = (uint32_t)e;
-                        const float fd = key_dist(row_distance_lds<LD, L1>(P.bank_x + (size_t)g * LD, Ys, Ws));
-                        key = ((uint64_t)__float_as_uint(fd) << 32) | g;
+            for (int j0 = 0; j0 < c; j0 += 4 * kWave) {
+                uint64_t e[4];  // four list entries per lane, loaded together
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u * kWave + lane;
+                    e[u] = j < c ? src[cand_slot(P, j, c0)] : 0ull;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool take = j0 + u * kWave + lane < c &&
+                                      (__uint_as_float((uint32_t)(e[u] >> 32)) <= cthr1) == (pass == 0);
+                    const uint64_t b = __ballot(take);
+                    if (take) queue[queued + (int)mbcnt(b)] = (uint32_t)e[u];  // queued < 64 here
+                    queued += __popcll(b);
+                    wave_lds_sync();
+                    if (queued >= kWave) {
+                        rank(kWave);
+                        queued -= kWave;
+                        const uint32_t rest = lane < queued ? queue[kWave + lane] : 0u;
+                        wave_lds_sync();
+                        if (lane < queued) queue[lane] = rest;
+                        wave_lds_sync();
                     }
                 }
-                const float fd = __uint_as_float((uint32_t)(key >> 32));
-                const bool keep = take && fd <= tau;
-                const uint64_t b = __ballot(keep);
-                overflow = overflow || below + __popcll(b) > P.scap;
-                if (keep && !overflow) keys[below + (int)mbcnt(b)] = key;
-                below += __popcll(b);
-                below1 += __popcll(__ballot(take && fd <= tau1));
+            }
+            if (queued > 0) {
+                rank(queued);
+                queued = 0;
             }
             if (below1 >= (int)P.n_acc) break;  // certified at tau1
         }
@@ -4044,7 +4141,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
     // (about 4 n are expected; more go to the exact fallback)
     A.scap = std::min(cap, std::max(512, pow2_at_least(8 * (int)n_acc)));
     const size_t lds = sizeof(uint64_t) * (use_mfma ? A.scap : cap) + sizeof(double) * kRedStride * kMaxWpv +
-                       (use_mfma ? 2 * sizeof(double) * (size_t)ld : 0);
+                       (use_mfma ? 2 * sizeof(double) * (size_t)ld + sizeof(uint32_t) * 2 * kWave : 0);
     // fallback blocks: up to 8 wavefronts, each with its own pow2(n + 128)-key
     // top-n, within 48 KB of LDS
     const int fb_cap = pow2_at_least((int)n_acc + 2 * kWave);
@@ -4361,7 +4458,7 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
     // (about 4 n are expected; more go to the exact fallback)
     B.scap = std::min(cap, std::max(512, pow2_at_least(8 * (int)n_acc)));
     const size_t lds = sizeof(uint64_t) * (mfma ? B.scap : cap) + sizeof(double) * kRedStride * kMaxWpv +
-                       (mfma ? 2 * sizeof(double) * (size_t)ld : 0);
+                       (mfma ? 2 * sizeof(double) * (size_t)ld + sizeof(uint32_t) * 2 * kWave : 0);
     const int fb_cap = pow2_at_least((int)n_acc + 2 * kWave);
     int fb_waves = 8;
     while (fb_waves > 1 && (size_t)fb_waves * fb_cap * sizeof(uint64_t) > 48 * 1024) fb_waves >>= 1;
