@@ -543,7 +543,9 @@ def learned_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, cpu: bool, bud
            "config": {"voxels": nv, "proposal_draws_per_voxel": n_is, "n_accept": n_acc, "prior_share": share,
                       "sd_scale": scale, "models": ["2TCM-irreversible"]},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_F64_VECTOR_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_VECTOR_TFLOPS, 4), "traffic": None,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_VECTOR_TFLOPS, 4),
+                        "traffic": traffic_from_profiles(cfg.name.replace("100kdraws", "learned20k"),
+                                                         "vpet_infer_is_kernel"),
                         "kernel": "vpet_infer_is_kernel", "kernel_ms": round(kernel_ms, 3),
                         "flops_per_draw": flops_per_draw(n_steps, F)},
            "training": {**train, "samples": train["steps"] * train["batch"], "seconds": round(train_s, 2),
@@ -722,7 +724,9 @@ def learned_bank_form(cfg, ft, cp, y_host, y, steps: int, warmup: int, ctx, cpu:
                       "step": "network forward pass + grouping + group banks (draw, simulate) + BF16 scan + "
                               "select + weighted reduction"},
            "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_BF16_MFMA_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4), "traffic": None,
+                        "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_MFMA_TFLOPS, 4),
+                        "traffic": traffic_from_profiles(cfg.name.replace("100kdraws", "learnedbank10k"),
+                                                         "vpet_bank_mfma_kernel"),
                         "kernel": f"vpet_bank_mfma_kernel<{2 * int(V.lib.vpet_abc_bank_ld(F))}, false> (BF16 scan)",
                         "kernel_ms": round(kern_ms, 3), "flops_per_pair": fpp},
            "sweep": sweep, "plain": plain, "equal_error": equal, "judge_common_threshold": judge}

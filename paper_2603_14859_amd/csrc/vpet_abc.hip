@@ -1309,7 +1309,8 @@ __device__ __forceinline__ void bank_slot_values(int kind, const float* t, doubl
 }
 
 __device__ double block_max(double v, double* red, int nw);
-constexpr int kOutCache = 2;  // accepted keys per thread whose values the output passes keep in registers
+constexpr int kOutCache = 2;   // accepted keys per thread whose values the output passes keep in registers
+constexpr int kOutCacheW = 1;  // the same with importance weights
 
 // Weighted outputs (bank rows with log weights, the learned-proposal bank):
 // of the n accepted keys those at or below the voxel's given threshold (if
@@ -1327,32 +1328,33 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
         lw = P.bank_logw[(uint32_t)acc[j]];
         return lw > -__builtin_inf();
     };
-    // the first kOutCache keys of this thread keep their log weight, weight
+    // the first kOutCacheW keys of this thread keep their log weight, weight
     // and values in registers across the passes (the same sums in the same
-    // order as reading them again)
-    double c_lw[kOutCache], c_w[kOutCache], c_val[kOutCache][8];
-    bool c_ok[kOutCache];
+    // order as reading them again; one key, to stay within the registers of
+    // four wavefronts per SIMD)
+    double c_lw[kOutCacheW], c_w[kOutCacheW], c_val[kOutCacheW][8];
+    bool c_ok[kOutCacheW];
     double lmax = -__builtin_inf();
 #pragma unroll
-    for (int i = 0; i < kOutCache; ++i) {
+    for (int i = 0; i < kOutCacheW; ++i) {
         const int j = tid + i * (int)blockDim.x;
         c_ok[i] = j < n && log_w(j, c_lw[i]);
         if (c_ok[i]) lmax = fmax(lmax, c_lw[i]);
     }
-    for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
+    for (int j = tid + kOutCacheW * (int)blockDim.x; j < n; j += blockDim.x) {
         double lw;
         if (log_w(j, lw)) lmax = fmax(lmax, lw);
     }
     lmax = block_max(lmax, red, nw);
     double tot[2] = {0.0, 0.0};  // sum w, sum w^2 over every model
 #pragma unroll
-    for (int i = 0; i < kOutCache; ++i) {
+    for (int i = 0; i < kOutCacheW; ++i) {
         if (!c_ok[i]) continue;
         c_w[i] = exp(c_lw[i] - lmax);
         tot[0] += c_w[i];
         tot[1] = fma(c_w[i], c_w[i], tot[1]);
     }
-    for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
+    for (int j = tid + kOutCacheW * (int)blockDim.x; j < n; j += blockDim.x) {
         double lw;
         if (!log_w(j, lw)) continue;
         const double w = exp(lw - lmax);
@@ -1365,9 +1367,9 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
         double s1[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) s1[q] = 0.0;
-        bool c_m[kOutCache];
+        bool c_m[kOutCacheW];
 #pragma unroll
-        for (int i = 0; i < kOutCache; ++i) {
+        for (int i = 0; i < kOutCacheW; ++i) {
             const int j = tid + i * (int)blockDim.x;
             c_m[i] = c_ok[i] && ((uint32_t)acc[j] - gb) / P.n_draws == (uint32_t)m;
             if (!c_m[i]) continue;
@@ -1377,7 +1379,7 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
             s1[8] += c_w[i];
         }
         double val[8];
-        for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
+        for (int j = tid + kOutCacheW * (int)blockDim.x; j < n; j += blockDim.x) {
             double lw;
             const uint32_t g = (uint32_t)acc[j];
             if (!log_w(j, lw) || (g - gb) / P.n_draws != (uint32_t)m) continue;
@@ -1396,7 +1398,7 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
             s2[q] = 0.0;
         }
 #pragma unroll
-        for (int i = 0; i < kOutCache; ++i) {
+        for (int i = 0; i < kOutCacheW; ++i) {
             if (!c_m[i]) continue;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -1404,7 +1406,7 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
                 s2[q] = fma(c_w[i] * dv, dv, s2[q]);
             }
         }
-        for (int j = tid + kOutCache * (int)blockDim.x; j < n; j += blockDim.x) {
+        for (int j = tid + kOutCacheW * (int)blockDim.x; j < n; j += blockDim.x) {
             double lw;
             const uint32_t g = (uint32_t)acc[j];
             if (!log_w(j, lw) || (g - gb) / P.n_draws != (uint32_t)m) continue;
@@ -1428,8 +1430,12 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
     if (P.out_ess && tid == 0) P.out_ess[orow] = tot[0] > 0.0 ? (float)(tot[0] * tot[0] / tot[1]) : __builtin_nanf("");
 }
 
-// Outputs of one voxel from its n accepted keys (sorted, in LDS).
-__device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* acc, double* red) {
+// Outputs of one voxel from its n accepted keys (sorted, in LDS).  MODE 0:
+// unit row weights, 1: the bank's importance weights, 2: whichever the launch
+// has (one instance per mode keeps the select kernels' registers to what
+// their path needs).
+template <int MODE>
+__device__ void bank_outputs_m(const BankArgs& P, long long row, const uint64_t* acc, double* red) {
     const int n = (int)P.n_acc;
     const int tid = threadIdx.x;
     const long long orow = bank_out_row(P, row);
@@ -1440,7 +1446,7 @@ __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* a
         for (int j = tid; j < n; j += blockDim.x)
             P.out_dist[(size_t)orow * n + j] = __uint_as_float((uint32_t)(acc[j] >> 32));
     if (P.out_thr && tid == 0) P.out_thr[orow] = __uint_as_float((uint32_t)(acc[n - 1] >> 32));
-    if (P.bank_logw) {
+    if (MODE == 1 || (MODE == 2 && P.bank_logw)) {
         bank_outputs_weighted(P, row, orow, acc, red);
         return;
     }
@@ -1515,6 +1521,10 @@ __device__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* a
     }
 }
 
+__device__ __forceinline__ void bank_outputs(const BankArgs& P, long long row, const uint64_t* acc, double* red) {
+    bank_outputs_m<2>(P, row, acc, red);
+}
+
 __device__ void bank_invalid(const BankArgs& P, long long row) {
     const int n = (int)P.n_acc;
     const float qnan = __builtin_nanf("");
@@ -1536,7 +1546,7 @@ __device__ void bank_invalid(const BankArgs& P, long long row) {
 // the threshold is a candidate, so the n smallest keys are among them);
 // otherwise -- or when the buffer overflowed -- the voxel is marked for the
 // exact fallback.
-template <int LD, bool L1, bool RECOMPUTE>
+template <int LD, bool L1, bool RECOMPUTE, bool WEIGHTED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vpet_bank_select_kernel(BankArgs P) {
     extern __shared__ __align__(16) unsigned char lds[];
     uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
@@ -1666,7 +1676,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vp
     for (int j = below + lane_id(); j < len; j += kWave) keys[j] = kNoKey;
     wave_lds_sync();
     wave_bitonic_sort(keys, len);
-    bank_outputs(P, row, keys, red);
+    bank_outputs_m<WEIGHTED ? 1 : 0>(P, row, keys, red);
 }
 
 // Exact fallback: one block per listed voxel streams every bank row; each
@@ -3686,13 +3696,19 @@ void bank_chunk(const BankArgs& Q, hipStream_t st, int ld, bool l1, bool mfma, s
             mark(0);                                                                                      \
             launch_mfma<2 * LDV, false>(mblocks, st, Q);                                                  \
             mark(1);                                                                                      \
-            hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, true>), per_voxel, b64, lds, st, Q);    \
+            if (Q.bank_logw)                                                                              \
+                hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, true, true>), per_voxel, b64, lds, st, Q); \
+            else                                                                                          \
+                hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, true, false>), per_voxel, b64, lds, st, Q); \
         } else {                                                                                          \
             hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, true>), lanes, b256, 0, st, Q);           \
             mark(0);                                                                                      \
             hipLaunchKernelGGL((vpet_bank_scan_kernel<LDV, L1V, false>), lanes, b256, 0, st, Q);          \
             mark(1);                                                                                      \
-            hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, false>), per_voxel, b64, lds, st, Q);   \
+            if (Q.bank_logw)                                                                              \
+                hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, false, true>), per_voxel, b64, lds, st, Q); \
+            else                                                                                          \
+                hipLaunchKernelGGL((vpet_bank_select_kernel<LDV, L1V, false, false>), per_voxel, b64, lds, st, Q); \
         }                                                                                                 \
         hipLaunchKernelGGL((vpet_bank_fallback_kernel<LDV, L1V>), fb_grid, fb_block, fb_lds, st, Q);      \
     } while (0)
