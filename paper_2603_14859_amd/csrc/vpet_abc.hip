@@ -1430,12 +1430,98 @@ __device__ void bank_outputs_weighted(const BankArgs& P, long long row, long lon
     if (P.out_ess && tid == 0) P.out_ess[orow] = tot[0] > 0.0 ? (float)(tot[0] * tot[0] / tot[1]) : __builtin_nanf("");
 }
 
+// bank_outputs_weighted with each accepted key's log weight, weight and bank
+// values gathered once into LDS (spare: 5 n free 8-byte slots after the n
+// keys): one gather and one exp per key instead of one per pass, the same
+// sums in the same order.  A weight of 0 marks a key that takes no part.
+__device__ void bank_outputs_weighted_lds(const BankArgs& P, long long row, long long orow, const uint64_t* acc,
+                                          double* red, uint64_t* spare) {
+    const int n = (int)P.n_acc;
+    const int tid = threadIdx.x, nw = blockDim.x >> 6;
+    const unsigned gb = bank_row_base(P, row);
+    const float h_v = P.below ? P.below[orow] : __builtin_inff();
+    double* cw = reinterpret_cast<double*>(spare);    // [n] log weight, then weight
+    float* ct = reinterpret_cast<float*>(spare + n);  // [n][8] bank values (16-byte aligned)
+    double lmax = -__builtin_inf();
+    for (int j = tid; j < n; j += blockDim.x) {
+        const uint64_t k = acc[j];
+        double lw = -__builtin_inf();
+        if (k != kNoKey && __uint_as_float((uint32_t)(k >> 32)) <= h_v) {
+            const uint32_t g = (uint32_t)k;
+            lw = P.bank_logw[g];
+            const float4* src = reinterpret_cast<const float4*>(P.bank_theta + (size_t)g * VPET_PSTRIDE);
+            float4* dst = reinterpret_cast<float4*>(ct + (size_t)j * VPET_PSTRIDE);
+            dst[0] = src[0];
+            dst[1] = src[1];
+        }
+        cw[j] = lw;
+        if (lw > -__builtin_inf()) lmax = fmax(lmax, lw);
+    }
+    lmax = block_max(lmax, red, nw);
+    double tot[2] = {0.0, 0.0};  // sum w, sum w^2 over every model
+    for (int j = tid; j < n; j += blockDim.x) {
+        const double lw = cw[j];
+        double w = 0.0;
+        if (lw > -__builtin_inf()) {
+            w = exp(lw - lmax);
+            tot[0] += w;
+            tot[1] = fma(w, w, tot[1]);
+        }
+        cw[j] = w;
+    }
+    block_sum<2>(tot, red, nw);
+    for (int m = 0; m < P.M; ++m) {
+        const int kind = P.kinds[m];
+        double s1[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s1[q] = 0.0;
+        double val[8];
+        for (int j = tid; j < n; j += blockDim.x) {
+            const double w = cw[j];
+            if (w == 0.0 || ((uint32_t)acc[j] - gb) / P.n_draws != (uint32_t)m) continue;
+            bank_slot_values(kind, ct + (size_t)j * VPET_PSTRIDE, val);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s1[q] = fma(w, val[q], s1[q]);
+            s1[8] += w;
+        }
+        block_sum<9>(s1, red, nw);
+        const double sw = s1[8];
+        double mean[8], s2[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            mean[q] = s1[q] / sw;
+            s2[q] = 0.0;
+        }
+        for (int j = tid; j < n; j += blockDim.x) {
+            const double w = cw[j];
+            if (w == 0.0 || ((uint32_t)acc[j] - gb) / P.n_draws != (uint32_t)m) continue;
+            bank_slot_values(kind, ct + (size_t)j * VPET_PSTRIDE, val);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double dv = val[q] - mean[q];
+                s2[q] = fma(w * dv, dv, s2[q]);
+            }
+        }
+        block_sum<8>(s2, red, nw);
+        if (tid < 16) {
+            const int q = tid >> 1;
+            float outv = __builtin_nanf("");
+            if (bank_slot_used(kind, q) && sw > 0.0) outv = (tid & 1) == 0 ? (float)mean[q] : (float)(s2[q] / sw);
+            P.out_mom[((size_t)orow * P.M + m) * 16 + tid] = outv;
+        }
+        if (tid == 0) P.out_prob[(size_t)orow * P.M + m] = tot[0] > 0.0 ? (float)(sw / tot[0]) : __builtin_nanf("");
+    }
+    if (P.out_ess && tid == 0) P.out_ess[orow] = tot[0] > 0.0 ? (float)(tot[0] * tot[0] / tot[1]) : __builtin_nanf("");
+}
+
 // Outputs of one voxel from its n accepted keys (sorted, in LDS).  MODE 0:
 // unit row weights, 1: the bank's importance weights, 2: whichever the launch
 // has (one instance per mode keeps the select kernels' registers to what
 // their path needs).
+// spare (MODE 1): LDS past the keys for bank_outputs_weighted_lds.
 template <int MODE>
-__device__ void bank_outputs_m(const BankArgs& P, long long row, const uint64_t* acc, double* red) {
+__device__ void bank_outputs_m(const BankArgs& P, long long row, const uint64_t* acc, double* red,
+                               uint64_t* spare = nullptr) {
     const int n = (int)P.n_acc;
     const int tid = threadIdx.x;
     const long long orow = bank_out_row(P, row);
@@ -1446,7 +1532,11 @@ __device__ void bank_outputs_m(const BankArgs& P, long long row, const uint64_t*
         for (int j = tid; j < n; j += blockDim.x)
             P.out_dist[(size_t)orow * n + j] = __uint_as_float((uint32_t)(acc[j] >> 32));
     if (P.out_thr && tid == 0) P.out_thr[orow] = __uint_as_float((uint32_t)(acc[n - 1] >> 32));
-    if (MODE == 1 || (MODE == 2 && P.bank_logw)) {
+    if (MODE == 1) {
+        bank_outputs_weighted_lds(P, row, orow, acc, red, spare);
+        return;
+    }
+    if (MODE == 2 && P.bank_logw) {
         bank_outputs_weighted(P, row, orow, acc, red);
         return;
     }
@@ -1676,7 +1766,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vp
     for (int j = below + lane_id(); j < len; j += kWave) keys[j] = kNoKey;
     wave_lds_sync();
     wave_bitonic_sort(keys, len);
-    bank_outputs_m<WEIGHTED ? 1 : 0>(P, row, keys, red);
+    // with importance weights the keys' values are staged in the LDS past the
+    // n accepted keys (the host makes scap >= 6 n)
+    bank_outputs_m<WEIGHTED ? 1 : 0>(P, row, keys, red, keys + P.n_acc);
 }
 
 // Exact fallback: one block per listed voxel streams every bank row; each
@@ -4473,6 +4565,8 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
     // the re-ranking select keeps at most 8 n keys at or below tau in LDS
     // (about 4 n are expected; more go to the exact fallback)
     B.scap = std::min(cap, std::max(512, pow2_at_least(8 * (int)n_acc)));
+    // (n <= VPET_BANK_MAX_ACCEPT = 512 makes this pow2(8 n) >= 8 n: the
+    // weighted select stages 5 n values past the n accepted keys)
     const size_t lds = sizeof(uint64_t) * (mfma ? B.scap : cap) + sizeof(double) * kRedStride * kMaxWpv +
                        (mfma ? 2 * sizeof(double) * (size_t)ld + sizeof(uint32_t) * 2 * kWave : 0);
     const int fb_cap = pow2_at_least((int)n_acc + 2 * kWave);
