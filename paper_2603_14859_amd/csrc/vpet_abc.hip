@@ -1878,28 +1878,31 @@ __device__ __forceinline__ void store_words(uint16_t* dst, const uint32_t (&w)[L
 // d = sum w ((y - r) - (x - r))^2, while the screen's operands and hence its
 // error bound shrink to the size of the deviations from r).
 template <int LD>
+// A thread per pair of frames of a row (coalesced 16-byte reads, 4-byte
+// writes of bf16 pairs).
 __global__ __launch_bounds__(256) void vpet_bank_bops_kernel(BankArgs P) {
-    const unsigned g = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long t = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned long long g = t / (LD / 2);
     if (g >= P.n_tot) return;
-    const double* xr = P.bank_x + (size_t)g * LD;
-    const double* rr = P.ref ? P.ref + (size_t)(g / P.grp_rows) * LD : nullptr;
-    uint32_t wh[LD], wl[LD];  // K = 2 LD bf16 values, two per word
-#pragma unroll
-    for (int k = 0; k < 2 * LD; ++k) {
-        const int f = k < LD ? k : k - LD;
-        const double xv = rr ? xr[f] - rr[f] : xr[f];
-        uint16_t hi, lo;
-        split_bf16(k < LD ? xv : xv * xv, hi, lo);
-        if (k & 1) {
-            wh[k >> 1] |= (uint32_t)hi << 16;
-            wl[k >> 1] |= (uint32_t)lo << 16;
-        } else {
-            wh[k >> 1] = hi;
-            wl[k >> 1] = lo;
-        }
+    const int f = 2 * (int)(t - g * (LD / 2));
+    const double2 x2 = *reinterpret_cast<const double2*>(P.bank_x + g * LD + f);
+    double x0 = x2.x, x1 = x2.y;
+    if (P.ref) {
+        const double* rr = P.ref + (size_t)(g / P.grp_rows) * LD + f;
+        x0 -= rr[0];
+        x1 -= rr[1];
     }
-    store_words<LD>(P.bhi + (size_t)g * 2 * LD, wh);
-    store_words<LD>(P.blo + (size_t)g * 2 * LD, wl);
+    uint16_t h0, l0, h1, l1, hq0, lq0, hq1, lq1;
+    split_bf16(x0, h0, l0);
+    split_bf16(x1, h1, l1);
+    split_bf16(x0 * x0, hq0, lq0);
+    split_bf16(x1 * x1, hq1, lq1);
+    uint32_t* bh = reinterpret_cast<uint32_t*>(P.bhi + g * 2 * LD);
+    uint32_t* bl = reinterpret_cast<uint32_t*>(P.blo + g * 2 * LD);
+    bh[f / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+    bl[f / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    bh[(LD + f) / 2] = (uint32_t)hq0 | ((uint32_t)hq1 << 16);
+    bl[(LD + f) / 2] = (uint32_t)lq0 | ((uint32_t)lq1 << 16);
 }
 
 // Voxel operands A_v = [-2 w y, w] (bf16 hi/lo) and a_v = sum w y^2 (FP64),
@@ -3041,33 +3044,57 @@ struct LbGroup {
 // floor(bins (exp(m_j) - lo_j) / (hi_j - lo_j)) clamped to [0, bins - 1]; the
 // key walks the grid in serpentine order: coordinate j runs backwards when
 // the key of the coordinates before it is odd.
-__global__ __launch_bounds__(256) void vpet_lb_summary_kernel(LbArgs A) {
-    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= A.V) return;
-    const int D = A.D;
-    const float* y = A.tacs + (size_t)v * A.F;
+// The voxel's whole network-output row and its TAC row are loaded before use
+// (independent loads in flight together: the kernel is bound by their
+// latency); D is a template parameter so that every index into them is a
+// constant.
+template <int D>
+__device__ __forceinline__ void lb_summary(const LbArgs& A, long long v) {
+    const float* yr = A.tacs + (size_t)v * A.F;
     bool bad = false;
     float ymax = -__builtin_inff();
-    for (int f = 0; f < A.F; ++f) {
-        bad = bad || !isfinite(y[f]);
-        ymax = fmaxf(ymax, y[f]);
-        if (A.weights) {
+    for (int f0 = 0; f0 < A.F; f0 += 16) {  // sixteen frames' loads in flight at a time
+        float y[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) y[i] = f0 + i < A.F ? yr[f0 + i] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (f0 + i >= A.F) break;
+            bad = bad || !isfinite(y[i]);
+            ymax = fmaxf(ymax, y[i]);
+        }
+    }
+    float o[kNetOut];
+    const float4* o4 = reinterpret_cast<const float4*>(A.prop + (size_t)v * kNetOut);
+#pragma unroll
+    for (int i = 0; i < kNetOut / 4; ++i) {
+        const float4 q = o4[i];
+        o[4 * i] = q.x;
+        o[4 * i + 1] = q.y;
+        o[4 * i + 2] = q.z;
+        o[4 * i + 3] = q.w;
+    }
+    if (A.weights) {
+        for (int f = 0; f < A.F; ++f) {
             const float w = A.weights[(size_t)v * A.F + f];
             bad = bad || !(w >= 0.0f) || !isfinite(w);
         }
     }
-    const float* o = A.prop + (size_t)v * kNetOut;
     double mx = -1e300;
+#pragma unroll
     for (int c = 0; c < kMixC; ++c) mx = fmax(mx, (double)o[c]);
     double pi[kMixC], se = 0.0;
+#pragma unroll
     for (int c = 0; c < kMixC; ++c) {
         pi[c] = exp((double)o[c] - mx);
         se += pi[c];
     }
     unsigned k = 0u;
     double* zm = A.zmom + (size_t)v * 2 * D;
+#pragma unroll
     for (int j = 0; j < D; ++j) {
         double m = 0.0, s2 = 0.0;
+#pragma unroll
         for (int c = 0; c < kMixC; ++c) {
             const double mu = (double)o[kMixC + c * D + j];
             const double lsd = kLS0 + (kLS1 - kLS0) / (1.0 + exp(-(double)o[kMixC + kMixC * D + c * D + j]));
@@ -3084,6 +3111,15 @@ __global__ __launch_bounds__(256) void vpet_lb_summary_kernel(LbArgs A) {
         k = k * (unsigned)A.bins + (unsigned)b;
     }
     A.key[v] = (bad || !(ymax > 0.0f)) ? (unsigned)A.ncell : k;
+}
+
+__global__ __launch_bounds__(256) void vpet_lb_summary_kernel(LbArgs A) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= A.V) return;
+    if (A.D == 4)
+        lb_summary<4>(A, v);
+    else
+        lb_summary<5>(A, v);
 }
 
 // Counts of each key (ncell + 1 values) in each block of kLbBlock voxels.
@@ -3174,13 +3210,15 @@ __global__ __launch_bounds__(64) void vpet_lb_scatter_kernel(LbArgs A, const int
 
 // Observed curves (and caller weights) in the grouped order; each voxel's group.
 __global__ __launch_bounds__(256) void vpet_lb_gather_kernel(LbArgs A) {
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // a thread per (position, frame): coalesced writes, row-contiguous reads
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long p = t / A.F;
     if (p >= A.V) return;
+    const int f = (int)(t - p * A.F);
     const long long v = A.perm[p];
-    for (int f = 0; f < A.F; ++f) A.ys[(size_t)p * A.F + f] = A.tacs[(size_t)v * A.F + f];
-    if (A.weights)
-        for (int f = 0; f < A.F; ++f) A.ws[(size_t)p * A.F + f] = A.weights[(size_t)v * A.F + f];
-    if (A.out_group) A.out_group[v] = (int)(p / A.S);
+    A.ys[t] = A.tacs[(size_t)v * A.F + f];
+    if (A.weights) A.ws[t] = A.weights[(size_t)v * A.F + f];
+    if (f == 0 && A.out_group) A.out_group[v] = (int)(p / A.S);
 }
 
 // One block per group: the Gaussian of each parameter moment-matched to the
@@ -3220,24 +3258,45 @@ __global__ __launch_bounds__(256) void vpet_lb_fit_kernel(LbArgs A, LbGroup* gro
     }
 }
 
-// One block per group, a thread per frame: the mean observed curve of the
-// group's valid members (in the grouped order, FP64, a fixed order), the
-// reference that the BF16 screen subtracts (padding frames 0).
-__global__ __launch_bounds__(64) void vpet_lb_ref_kernel(LbArgs A, double* ref, int ld) {
+// One block per group, four wavefronts, a lane per frame: the mean observed
+// curve of the group's valid members (in the grouped order, FP64), the
+// reference that the BF16 screen subtracts (padding frames 0).  Wavefront q
+// sums the q-th quarter of the members in order, eight members' loads in
+// flight at a time; the quarters are added in order.
+__global__ __launch_bounds__(256) void vpet_lb_ref_kernel(LbArgs A, double* ref, int ld) {
+    __shared__ double part[4][kWave];
+    __shared__ long long pcnt[4];
     const long long g = blockIdx.x;
-    const int f = threadIdx.x;
-    if (f >= ld) return;
-    const long long p0 = g * A.S, p1 = min(A.V, p0 + A.S);
+    const int f = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const long long p0 = g * A.S, p1 = min(A.V, p0 + A.S), len = p1 - p0;
+    const long long a = p0 + len * q / 4, b = p0 + len * (q + 1) / 4;
     double s = 0.0;
     long long cnt = 0;
     if (f < A.F) {
-        for (long long p = p0; p < p1; ++p) {
-            if (A.key[A.perm[p]] >= (unsigned)A.ncell) continue;
-            s += (double)A.ys[(size_t)p * A.F + f];
-            ++cnt;
+        for (long long p = a; p < b; p += 8) {
+            bool ok[8];
+            float yv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                ok[i] = p + i < b && A.key[A.perm[p + i]] < (unsigned)A.ncell;
+                yv[i] = ok[i] ? A.ys[(size_t)(p + i) * A.F + f] : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (!ok[i]) continue;
+                s += (double)yv[i];
+                ++cnt;
+            }
         }
     }
-    ref[(size_t)g * ld + f] = cnt > 0 ? s / (double)cnt : 0.0;
+    part[q][f] = s;
+    if (f == 0) pcnt[q] = cnt;
+    __syncthreads();
+    if (q == 0 && f < ld) {
+        const double t = ((part[0][f] + part[1][f]) + part[2][f]) + part[3][f];
+        const long long c = f < A.F ? pcnt[0] + pcnt[1] + pcnt[2] + pcnt[3] : 0;
+        ref[(size_t)g * ld + f] = c > 0 ? t / (double)c : 0.0;
+    }
 }
 
 struct LbBank {
@@ -3760,7 +3819,7 @@ namespace {
 // BF16 hi/lo operands B_g = [x_g, x_g^2] of the first `rows` bank rows.
 void bank_bops(BankArgs A, unsigned rows, hipStream_t st, int ld) {
     A.n_tot = rows;
-    const dim3 gb((rows + 255) / 256), b256(256);
+    const dim3 gb((unsigned)(((unsigned long long)rows * (unsigned)(ld / 2) + 255) / 256)), b256(256);
     switch (ld) {
         case 8: hipLaunchKernelGGL((vpet_bank_bops_kernel<8>), gb, b256, 0, st, A); break;
         case 16: hipLaunchKernelGGL((vpet_bank_bops_kernel<16>), gb, b256, 0, st, A); break;
@@ -4556,9 +4615,9 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
     hipLaunchKernelGGL(vpet_lb_columns_kernel, dim3((unsigned)((ncell + 1 + 255) / 256)), b256, 0, st, A, d_tot);
     hipLaunchKernelGGL(vpet_lb_cellbase_kernel, dim3(1), dim3(1024), 0, st, A, d_tot);
     hipLaunchKernelGGL(vpet_lb_scatter_kernel, dim3((unsigned)nb), dim3(64), 0, st, A, (const int*)d_tot);
-    hipLaunchKernelGGL(vpet_lb_gather_kernel, dim3((unsigned)((V + 255) / 256)), b256, 0, st, A);
+    hipLaunchKernelGGL(vpet_lb_gather_kernel, dim3((unsigned)((V * F + 255) / 256)), b256, 0, st, A);
     hipLaunchKernelGGL(vpet_lb_fit_kernel, dim3((unsigned)G), b256, 0, st, A, d_groups, scale);
-    if (mfma) hipLaunchKernelGGL(vpet_lb_ref_kernel, dim3((unsigned)G), dim3(64), 0, st, A, d_ref, ld);
+    if (mfma) hipLaunchKernelGGL(vpet_lb_ref_kernel, dim3((unsigned)G), b256, 0, st, A, d_ref, ld);
     e = hipGetLastError();
     if (e != hipSuccess) rc = hip_fail(e, "grouping launch");
 
@@ -4725,7 +4784,7 @@ int vpet_abc_bank_screen(const float* tacs, int64_t n_voxels, const float* frame
     A.tau1 = reinterpret_cast<float*>(q);
     q += sz_c;
     A.aval = reinterpret_cast<double*>(q);
-    const dim3 b256(256), rows((unsigned)((n_rows + 255) / 256)), lanes((unsigned)((V + 255) / 256));
+    const dim3 b256(256), rows((unsigned)((n_rows * (ld / 2) + 255) / 256)), lanes((unsigned)((V + 255) / 256));
     const dim3 mblocks((unsigned)((V + kMfmaVox - 1) / kMfmaVox)), per_voxel((unsigned)V);
 #define VPET_SCREEN(LDV)                                                                   \
     do {                                                                                   \
