@@ -711,6 +711,40 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// FP64 lane exchange by a DPP pattern within rows of 16 lanes (two 32-bit
+// moves; no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// FP64 wavefront sum, the same value in every lane: pairs, quads, halves and
+// whole rows of 16 by DPP (each step adds the mirror lane's partial, so the
+// lanes of a row agree), then (row0 + row1) + (row2 + row3).
+template <>
+__device__ __forceinline__ double wave_sum<double>(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
+}
+
 // Sum of NV values over the block; every thread gets the totals.
 template <int NV>
 __device__ void block_sum(double (&v)[NV], double* red, int wpv) {
@@ -2818,8 +2852,7 @@ __device__ __forceinline__ void tile_keys_is(const InferArgs& P, const MixTab& m
 }
 
 __device__ double block_max(double v, double* red, int nw) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    v = wave_max(v);
     if (lane_id() == 0) red[(threadIdx.x >> 6) * kRedStride] = v;
     __syncthreads();
     double m = -__builtin_inf();
