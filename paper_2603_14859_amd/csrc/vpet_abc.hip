@@ -2151,12 +2151,6 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
     stash(0);
     if (ntiles > 1) fetch(1);
     __syncthreads();
-    // Waves 4-7 screen each tile one iteration late, after the barrier and
-    // before their products of the next tile: of the two wavefronts of a block
-    // on one SIMD (waves w and w + 4), one then screens while the other's
-    // products run on the matrix core.
-    const bool lag = __builtin_amdgcn_readfirstlane(wave) >= 4;
-    f32x16_t acc0 = {}, acc1 = {};
     for (unsigned t = 0; t < ntiles; ++t) {
         const int buf = t & 1;
         if (t + 1 < ntiles) {
@@ -2165,12 +2159,7 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
             stash(buf ^ 1);
             if (t + 2 < ntiles) fetch(t + 2);
         }
-        if (lag && t > 0) {
-            screen(acc0, tile_row0(t - 1), (t - 1) * TR);
-            screen(acc1, tile_row0(t - 1) + kMfmaRows, (t - 1) * TR + kMfmaRows);
-        }
-        acc0 = f32x16_t{};
-        acc1 = f32x16_t{};
+        f32x16_t acc0 = {}, acc1 = {};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int off = (lane & 31) * RS + (ks * 16 + half * 8) * 2;
@@ -2187,15 +2176,9 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh0, al[ks], acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh1, al[ks], acc1, 0, 0, 0);
         }
-        if (!lag) {
-            screen(acc0, tile_row0(t), t * TR);
-            screen(acc1, tile_row0(t) + kMfmaRows, t * TR + kMfmaRows);
-        }
+        screen(acc0, tile_row0(t), t * TR);
+        screen(acc1, tile_row0(t) + kMfmaRows, t * TR + kMfmaRows);
         __syncthreads();
-    }
-    if (lag && ntiles > 0) {
-        screen(acc0, tile_row0(ntiles - 1), (ntiles - 1) * TR);
-        screen(acc1, tile_row0(ntiles - 1) + kMfmaRows, (ntiles - 1) * TR + kMfmaRows);
     }
     if (PILOT) {
         // ascending bitonic sort of the lane's 16 class minima, in registers
