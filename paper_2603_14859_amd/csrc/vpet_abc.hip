@@ -1737,8 +1737,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vp
                     double pt = 0.0;
 #pragma unroll
                     for (int q = 0; q < Q; ++q) pt = dist_term<L1>(Yq[q], Wq[q], xv[h][q], pt);
-                    pt += __shfl_xor(pt, 1, kWave);  // p0 + p1, p2 + p3
-                    pt += __shfl_xor(pt, 2, kWave);  // (p0 + p1) + (p2 + p3)
+                    pt += dpp_f64<0xB1>(pt);  // p0 + p1, p2 + p3 (quad_perm [1,0,3,2])
+                    pt += dpp_f64<0x4E>(pt);  // (p0 + p1) + (p2 + p3) (quad_perm [2,3,0,1])
                     const float fd = key_dist(pt);
                     const bool mine = live && part == 0;
                     const bool keep = mine && fd <= tau;
