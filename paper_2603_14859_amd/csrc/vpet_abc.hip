@@ -1786,6 +1786,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vp
             if (threadIdx.x == 0) P.fb_list[atomicAdd(P.fb_count, 1u)] = (int)row;
             return;
         }
+        if (below1 >= (int)P.n_acc) {
+            // certified at tau1: only the keys at or below tau1 can be among
+            // the n smallest, so they alone are moved to the front and sorted
+            // (each chunk is read before it is written, at lower indices)
+            int m = 0;
+            for (int j0 = 0; j0 < below; j0 += kWave) {
+                const int j = j0 + lane;
+                const uint64_t k = j < below ? keys[j] : kNoKey;
+                const bool in = j < below && __uint_as_float((uint32_t)(k >> 32)) <= tau1;
+                const uint64_t b = __ballot(in);
+                wave_lds_sync();
+                if (in) keys[m + (int)mbcnt(b)] = k;
+                m += __popcll(b);
+                wave_lds_sync();
+            }
+            below = m;
+        }
     } else {
         const uint64_t* src = P.cand + (size_t)row * P.cap;
         const int c0 = c - P.cnt_hi[row];
@@ -3159,11 +3176,16 @@ __global__ __launch_bounds__(256) void vpet_lb_columns_kernel(LbArgs A, int* tot
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     int run = 0;
-    for (int b = 0; b < A.nb; ++b) {
-        int* hp = A.hist + (size_t)b * nc + c;
-        const int t = *hp;
-        *hp = run;
-        run += t;
+    for (int b0 = 0; b0 < A.nb; b0 += 8) {  // eight blocks' counts loaded together
+        int t[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) t[i] = b0 + i < A.nb ? A.hist[(size_t)(b0 + i) * nc + c] : 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (b0 + i >= A.nb) break;
+            A.hist[(size_t)(b0 + i) * nc + c] = run;
+            run += t[i];
+        }
     }
     tot[c] = run;
 }
