@@ -1663,6 +1663,62 @@ __device__ void bank_invalid(const BankArgs& P, long long row) {
     if (P.out_ess && threadIdx.x == 0) P.out_ess[orow] = qnan;
 }
 
+// Ascending sort of one 64-bit value per lane across the wavefront (bitonic;
+// lane l ends with the l-th smallest).
+__device__ __forceinline__ uint64_t wave_sort_lanes(uint64_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, j, kWave);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), j, kWave);
+            const uint64_t y = ((uint64_t)hi << 32) | lo;
+            const bool lower = (lane & j) == 0, up = (lane & k) == 0;
+            x = (lower == up) ? (x < y ? x : y) : (x < y ? y : x);
+        }
+    }
+    return x;
+}
+
+// Moves the m <= below smallest of the wavefront's `below` distinct keys in
+// LDS to the front and returns m, with n <= m: a pivot taken from 64 evenly
+// spaced keys, at about 1.25 n of them below it, is checked by counting and
+// raised until at least n keys lie at or below it (else every key stays).
+// The n smallest keys are then among the first m, in fewer to sort.
+__device__ __forceinline__ int keep_smallest(uint64_t* keys, int below, int n) {
+    const int lane = lane_id();
+    wave_lds_sync();
+    const uint64_t smp = wave_sort_lanes(keys[(int)(((long long)lane * below) / kWave)]);
+    int q = (int)min(63LL, (64LL * (n + n / 4) + below - 1) / below);
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        const uint64_t piv = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(smp >> 32), q) << 32) |
+                             (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)smp, q);
+        int cnt = 0;
+        for (int j0 = 0; j0 < below; j0 += kWave) {
+            const int j = j0 + lane;
+            cnt += __popcll(__ballot(j < below && keys[j] <= piv));
+        }
+        if (cnt >= n) {
+            int m = 0;  // each chunk is read before it is written, at lower indices
+            for (int j0 = 0; j0 < below; j0 += kWave) {
+                const int j = j0 + lane;
+                const uint64_t k = j < below ? keys[j] : kNoKey;
+                const bool in = j < below && k <= piv;
+                const uint64_t b = __ballot(in);
+                wave_lds_sync();
+                if (in) keys[m + (int)mbcnt(b)] = k;
+                m += __popcll(b);
+                wave_lds_sync();
+            }
+            return m;
+        }
+        if (q == kWave - 1) break;
+        q = min(kWave - 1, q + (8 << attempt));
+    }
+    return below;
+}
+
 // One wavefront per voxel: sort the candidates, keep the n smallest.  With
 // RECOMPUTE the candidates carry only their bank row and the exact FP64
 // distance is computed here.  The result is certified when at least n
@@ -1813,6 +1869,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vp
         if (threadIdx.x == 0) P.fb_list[atomicAdd(P.fb_count, 1u)] = (int)row;
         return;
     }
+    if (below > 2 * (int)P.n_acc) below = keep_smallest(keys, below, (int)P.n_acc);
     const int len = below <= 1 ? 2 : (1 << (32 - __clz(below - 1)));
     for (int j = below + lane_id(); j < len; j += kWave) keys[j] = kNoKey;
     wave_lds_sync();
