@@ -1548,11 +1548,72 @@ __device__ void bank_outputs_weighted_lds(const BankArgs& P, long long row, long
     if (P.out_ess && tid == 0) P.out_ess[orow] = tot[0] > 0.0 ? (float)(tot[0] * tot[0] / tot[1]) : __builtin_nanf("");
 }
 
+// Unit-weight outputs with each accepted key's bank values gathered once
+// into LDS (spare: 4 n free 8-byte slots after the n keys, 16-byte aligned
+// from the second): one gather per key for both moment passes, the same sums
+// in the same order.
+__device__ void bank_outputs_unit_lds(const BankArgs& P, long long orow, unsigned gb, const uint64_t* acc,
+                                      double* red, uint64_t* spare) {
+    const int n = (int)P.n_acc;
+    const int tid = threadIdx.x;
+    float* ct = reinterpret_cast<float*>(spare + (n & 1));  // [n][8] bank values
+    for (int j = tid; j < n; j += blockDim.x) {
+        const float4* src = reinterpret_cast<const float4*>(P.bank_theta + (size_t)(uint32_t)acc[j] * VPET_PSTRIDE);
+        float4* dst = reinterpret_cast<float4*>(ct + (size_t)j * VPET_PSTRIDE);
+        dst[0] = src[0];
+        dst[1] = src[1];
+    }
+    for (int m = 0; m < P.M; ++m) {
+        const int kind = P.kinds[m];
+        double s1[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s1[q] = 0.0;
+        double val[8];
+        for (int j = tid; j < n; j += blockDim.x) {
+            if (((uint32_t)acc[j] - gb) / P.n_draws != (uint32_t)m) continue;
+            bank_slot_values(kind, ct + (size_t)j * VPET_PSTRIDE, val);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s1[q] += val[q];
+            s1[8] += 1.0;
+        }
+        block_sum<9>(s1, red, blockDim.x >> 6);
+        const double cnt = s1[8];
+        double mean[8], s2[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            mean[q] = s1[q] / cnt;
+            s2[q] = 0.0;
+        }
+        for (int j = tid; j < n; j += blockDim.x) {
+            if (((uint32_t)acc[j] - gb) / P.n_draws != (uint32_t)m) continue;
+            bank_slot_values(kind, ct + (size_t)j * VPET_PSTRIDE, val);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const double dv = val[q] - mean[q];
+                s2[q] = fma(dv, dv, s2[q]);
+            }
+        }
+        block_sum<8>(s2, red, blockDim.x >> 6);
+        if (tid < 16) {
+            const int q = tid >> 1;
+            float outv = __builtin_nanf("");
+            if (bank_slot_used(kind, q) && cnt > 0.0) {
+                if ((tid & 1) == 0)
+                    outv = (float)mean[q];
+                else
+                    outv = (cnt > 1.0) ? (float)(s2[q] / (cnt - 1.0)) : 0.0f;
+            }
+            P.out_mom[((size_t)orow * P.M + m) * 16 + tid] = outv;
+        }
+        if (tid == 0) P.out_prob[(size_t)orow * P.M + m] = (float)(cnt / (double)n);
+    }
+}
+
 // Outputs of one voxel from its n accepted keys (sorted, in LDS).  MODE 0:
 // unit row weights, 1: the bank's importance weights, 2: whichever the launch
 // has (one instance per mode keeps the select kernels' registers to what
 // their path needs).
-// spare (MODE 1): LDS past the keys for bank_outputs_weighted_lds.
+// spare (MODES 0, 1): LDS past the keys for the staged outputs.
 template <int MODE>
 __device__ void bank_outputs_m(const BankArgs& P, long long row, const uint64_t* acc, double* red,
                                uint64_t* spare = nullptr) {
@@ -1572,6 +1633,10 @@ __device__ void bank_outputs_m(const BankArgs& P, long long row, const uint64_t*
     }
     if (MODE == 2 && P.bank_logw) {
         bank_outputs_weighted(P, row, orow, acc, red);
+        return;
+    }
+    if (MODE == 0) {
+        bank_outputs_unit_lds(P, orow, gb, acc, red, spare);
         return;
     }
     for (int m = 0; m < P.M; ++m) {
@@ -1874,8 +1939,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vp
     for (int j = below + lane_id(); j < len; j += kWave) keys[j] = kNoKey;
     wave_lds_sync();
     wave_bitonic_sort(keys, len);
-    // with importance weights the keys' values are staged in the LDS past the
-    // n accepted keys (the host makes scap >= 6 n)
+    // the accepted keys' values (and weights) are staged in the LDS past the n
+    // accepted keys (n <= 512 makes scap >= 8 n)
     bank_outputs_m<WEIGHTED ? 1 : 0>(P, row, keys, red, keys + P.n_acc);
 }
 
