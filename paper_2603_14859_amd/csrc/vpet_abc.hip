@@ -3470,13 +3470,19 @@ struct LbBank {
     double* x;           // [groups][rows_per_group][ld]
     double* logw;        // [groups][rows_per_group]
     int ld;
+    // BF16 screen operands of the rows (bank_bops' layout) and the launch's
+    // group reference curves [groups][ld]; null without the contraction screen
+    uint16_t* bhi;
+    uint16_t* blo;
+    const double* ref;
 };
 
-struct NanOrBankSink {
-    double* row;  // bank row, or nullptr for a padding lane
+// A lane's curve staged in LDS (NaN for an invalid row).
+struct StagedRowSink {
+    double* s;
     bool valid;
     __device__ __forceinline__ void operator()(int f, int n, const double (&X)[1]) {
-        if (row) row[f] = valid ? X[0] / (double)n : __builtin_nan("");
+        s[f] = valid ? X[0] / (double)n : __builtin_nan("");
     }
 };
 
@@ -3496,10 +3502,18 @@ struct NanOrBankSink {
 // over the head's parameters of log N(z_p; mu, sd) - z_p + log(hi_p - lo_p)
 // (z_p = log theta_p for a uniform draw); an invalid row has log w = -inf and
 // NaN curves.
+// A wavefront draws 64 consecutive rows, a lane each, and stages its
+// parameter row and then its curve in LDS, so that all of its global writes
+// are runs of consecutive elements (a lane writing its own row would send one
+// memory request per lane per frame).  With the contraction screen the kernel
+// also writes the rows' BF16 operands from the staged curves, as
+// bank_bops_kernel would from the stored ones.
 template <int KIND>
-__global__ __launch_bounds__(256) void vpet_lb_bank_kernel(LbBank B, ModelDev md, int m, Tab T, double C0, double h,
-                                                           int F, int k0) {
-    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kWave) void vpet_lb_bank_kernel(LbBank B, ModelDev md, int m, Tab T, double C0, double h,
+                                                             int F, int k0) {
+    extern __shared__ double stage[];  // [kWave][ld + 1]: the wavefront's rows
+    const int lane = threadIdx.x;
+    const unsigned i = blockIdx.x * kWave + lane;
     const bool live = i < B.n_draws;
     const unsigned ii = live ? i : B.n_draws - 1;
     const long long g = B.g0 + blockIdx.y;
@@ -3558,24 +3572,82 @@ __global__ __launch_bounds__(256) void vpet_lb_bank_kernel(LbBank B, ModelDev md
         }
     }
     if (!ok) lw = -__builtin_inf();
-    const size_t row = (size_t)blockIdx.y * B.rows_per_group + (size_t)m * B.n_draws + ii;
-    if (live) {
-        float* to = B.theta + row * VPET_PSTRIDE;
-        for (int q = 0; q < VPET_PSTRIDE; ++q) to[q] = __builtin_nanf("");
-        for (int q = 0; q < md.np; ++q) to[md.slot[q]] = th[q];
-        B.logw[row] = lw;
-        double* xr = B.x + row * (size_t)B.ld;
-        for (int f = F; f < B.ld; ++f) xr[f] = 0.0;
+    // the wavefront's rows are consecutive: row0 + r for r < nlive
+    const int ld = B.ld;
+    const int nlive = (int)min(B.n_draws - blockIdx.x * kWave, (unsigned)kWave);
+    const size_t row0 = (size_t)blockIdx.y * B.rows_per_group + (size_t)m * B.n_draws + blockIdx.x * kWave;
+    if (live) B.logw[row0 + lane] = lw;
+    {  // parameter rows through LDS, written out as consecutive floats
+        float* tf = reinterpret_cast<float*>(stage);
+#pragma unroll
+        for (int j = 0; j < VPET_PSTRIDE; ++j) tf[lane * VPET_PSTRIDE + j] = __builtin_nanf("");
+        for (int q = 0; q < md.np; ++q) tf[lane * VPET_PSTRIDE + md.slot[q]] = th[q];
+        __syncthreads();
+        float* to = B.theta + row0 * VPET_PSTRIDE;
+#pragma unroll
+        for (int k = 0; k < VPET_PSTRIDE; ++k) {
+            const int e = k * kWave + lane;
+            if (e < nlive * VPET_PSTRIDE) to[e] = tf[e];
+        }
+        __syncthreads();
     }
     if (!ok) {  // an in-box stand-in keeps the recursion finite; the row's curve is NaN
         for (int p = 0; p < md.np; ++p) th[p] = md.lo[p];
         th[1] = md.lo[1] + md.wid[1];
     }
-    NanOrBankSink sink{live ? B.x + row * (size_t)B.ld : nullptr, ok};
+    double* mine = stage + lane * (ld + 1);
+    for (int f = F; f < ld; ++f) mine[f] = 0.0;
+    StagedRowSink sink{mine, ok};
     constexpr int NE = ModelTraits<KIND>::NE;
     DrawState<NE, 1> s;
     setup<KIND, NE, 1>(th, h, C0, s, 0);
     simulate_draws<KIND, 1>(T, F, k0, s, sink);
+    __syncthreads();
+    // the rows leave as consecutive elements: lane + 64 k of the wavefront's
+    // kWave x ld block, (r, f) advanced by (64 / ld, 64 % ld) per step
+    {
+        double* xo = B.x + row0 * (size_t)ld;
+        const int dr = kWave / ld, df = kWave % ld;
+        int r = lane / ld, f = lane % ld;
+        for (int k = 0; k < ld; ++k) {
+            if (r < nlive) xo[(size_t)k * kWave + lane] = stage[r * (ld + 1) + f];
+            r += dr;
+            f += df;
+            if (f >= ld) {
+                f -= ld;
+                ++r;
+            }
+        }
+    }
+    if (B.bhi) {  // the screen operands of bank_bops, pairs of frames per lane
+        const int hp = ld >> 1, dr = kWave / hp, df = kWave % hp;
+        const double* rr = B.ref + (size_t)blockIdx.y * ld;
+        uint32_t* bh = reinterpret_cast<uint32_t*>(B.bhi) + row0 * (size_t)ld;
+        uint32_t* bl = reinterpret_cast<uint32_t*>(B.blo) + row0 * (size_t)ld;
+        int r = lane / hp, pr = lane % hp;
+        for (int k = 0; k < hp; ++k) {
+            if (r < nlive) {
+                const double x0 = stage[r * (ld + 1) + 2 * pr] - rr[2 * pr];
+                const double x1 = stage[r * (ld + 1) + 2 * pr + 1] - rr[2 * pr + 1];
+                uint16_t h0, l0, h1, l1, hq0, lq0, hq1, lq1;
+                split_bf16(x0, h0, l0);
+                split_bf16(x1, h1, l1);
+                split_bf16(x0 * x0, hq0, lq0);
+                split_bf16(x1 * x1, hq1, lq1);
+                const size_t o = (size_t)r * ld + pr;
+                bh[o] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                bl[o] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+                bh[o + hp] = (uint32_t)hq0 | ((uint32_t)hq1 << 16);
+                bl[o + hp] = (uint32_t)lq0 | ((uint32_t)lq1 << 16);
+            }
+            r += dr;
+            pr += df;
+            if (pr >= hp) {
+                pr -= hp;
+                ++r;
+            }
+        }
+    }
 }
 
 // Table staging for the allocation-free entry point: 1 KB of table bytes per
@@ -4815,6 +4887,11 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
         LB.theta = gp.out_bank_theta ? gp.out_bank_theta + (size_t)g0 * n_tot * VPET_PSTRIDE : b_theta;
         LB.logw = gp.out_bank_logw ? gp.out_bank_logw + (size_t)g0 * n_tot : b_logw;
         LB.x = b_x;
+        // with the contraction screen the bank kernel also writes the rows'
+        // BF16 operands (bank_bops' output) from its staged curves
+        LB.bhi = mfma ? B.bhi : nullptr;
+        LB.blo = mfma ? B.blo : nullptr;
+        LB.ref = d_ref ? d_ref + (size_t)g0 * ld : nullptr;
         for (int m = 0; m < M; ++m) {
             for (int p = 0; p < kMaxParams; ++p) LB.dim_of[p] = -1;
             // draw order K1, k2, k3, vB (irreversible) or K1, k2, k3, k4, vB
@@ -4827,17 +4904,20 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
                 LB.dim_of[3] = D == 5 ? 3 : -1;
                 LB.dim_of[4] = D - 1;
             }
-            const dim3 bg((unsigned)((n_draws + 255) / 256), (unsigned)ng);
+            // a wavefront per 64 rows, its curves staged in LDS
+            const dim3 bg((unsigned)((n_draws + kWave - 1) / kWave), (unsigned)ng), bw(kWave);
+            const size_t stage = sizeof(double) * kWave * (size_t)(ld + 1);
             if (kinds[m] == KIND_IRR)
-                hipLaunchKernelGGL(vpet_lb_bank_kernel<KIND_IRR>, bg, b256, 0, st, LB, md[m], m, tab, T.C0, T.h, F, T.k0);
+                hipLaunchKernelGGL(vpet_lb_bank_kernel<KIND_IRR>, bg, bw, stage, st, LB, md[m], m, tab, T.C0, T.h, F,
+                                   T.k0);
             else
-                hipLaunchKernelGGL(vpet_lb_bank_kernel<KIND_REV>, bg, b256, 0, st, LB, md[m], m, tab, T.C0, T.h, F, T.k0);
+                hipLaunchKernelGGL(vpet_lb_bank_kernel<KIND_REV>, bg, bw, stage, st, LB, md[m], m, tab, T.C0, T.h, F,
+                                   T.k0);
         }
         BankArgs Q = B;
         Q.bank_theta = LB.theta;
         Q.bank_logw = LB.logw;
         Q.ref = d_ref ? d_ref + (size_t)g0 * ld : nullptr;
-        if (mfma) bank_bops(Q, (unsigned)(ng * n_tot), st, ld);
         Q.V = nv;
         Q.pos0 = base;
         Q.g0 = g0;
