@@ -3538,25 +3538,48 @@ __global__ __launch_bounds__(kWave) void vpet_lb_bank_kernel(LbBank B, ModelDev 
         th[p] = 0.0f;
         z[p] = 0.0;
     }
-    for (int p = 0; p < md.np; ++p) {
+    // the Box-Muller normals, once per pair (u_{2q}, u_{2q+1})
+    double nrm[2 * 3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        nrm[2 * q] = nrm[2 * q + 1] = 0.0;
+        if (2 * q < md.np) {
+            const double r = sqrt(-2.0 * log_pos(u[2 * q] + 0x1p-24));
+            double sn, cs;
+            sincospi(2.0 * u[2 * q + 1], &sn, &cs);
+            nrm[2 * q] = r * cs;
+            nrm[2 * q + 1] = r * sn;
+        }
+    }
+    // log wid_p (lanes 0-7) and log sd_d (lanes 8-15), one logarithm per
+    // lane, read back per parameter
+    double lgv;
+    {
+        float a = 1.0f;
+#pragma unroll
+        for (int p = 0; p < kMaxParams; ++p)
+            if (lane == p) a = md.wid[p];
+#pragma unroll
+        for (int d = 0; d < kLbMaxDims; ++d)
+            if (lane == 8 + d) a = G.sd[d];
+        lgv = log((double)a);
+    }
+#pragma unroll
+    for (int p = 0; p < kMaxParams; ++p) {
+        if (p >= md.np) break;
         const double lo = (double)md.lo[p], wid = (double)md.wid[p];
         const int d = B.dim_of[p];
         if (prior || d < 0 || wid == 0.0) {
             th[p] = (float)(lo + (prior || wid == 0.0 ? u[p] : u[6]) * wid);
             z[p] = log((double)th[p]);
         } else {
-            const int q = p >> 1;  // Box-Muller pair (u_{2q}, u_{2q+1})
-            const double r = sqrt(-2.0 * log_pos(u[2 * q] + 0x1p-24));
-            double sn, cs;
-            sincospi(2.0 * u[2 * q + 1], &sn, &cs);
-            const double nrm = (p & 1) ? r * sn : r * cs;
-            z[p] = (double)G.mu[d] + (double)G.sd[d] * nrm;
+            z[p] = (double)G.mu[d] + (double)G.sd[d] * nrm[p];
             th[p] = (float)exp_series(z[p]);
             ok = ok && th[p] >= md.lo[p] && (double)th[p] <= lo + wid;
         }
         if (d >= 0 && wid > 0.0 && G.cnt > 0) {
             const double t = (z[p] - (double)G.mu[d]) / (double)G.sd[d];
-            L += -0.5 * t * t - log((double)G.sd[d]) - 0.9189385332046727 - z[p] + log(wid);
+            L += -0.5 * t * t - lane_f64(lgv, 8 + d) - 0.9189385332046727 - z[p] + lane_f64(lgv, p);
         }
     }
     double lw = 0.0;
