@@ -2038,6 +2038,21 @@ __device__ __forceinline__ void split_bf16(double v, uint16_t& hi, uint16_t& lo)
     lo = bf16_rn((float)(v - (double)bf16_to_f(hi)));
 }
 
+// split_bf16 of two values at once, packed (first value in the low half), with
+// gfx950's paired conversion (v_cvt_pk_bf16_f32, round to nearest even: the
+// same bits as bf16_rn for every non-NaN value).
+typedef float vpet_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 vpet_bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16x2_rn(float a, float b) {
+    const vpet_f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, vpet_bf16x2));
+}
+__device__ __forceinline__ void split_bf16x2(double v0, double v1, uint32_t& hi, uint32_t& lo) {
+    hi = bf16x2_rn((float)v0, (float)v1);
+    lo = bf16x2_rn((float)(v0 - (double)__uint_as_float(hi << 16)),
+                   (float)(v1 - (double)__uint_as_float(hi & 0xFFFF0000u)));
+}
+
 // A row of 2 LD bf16 values (LD words) written as 16-byte stores.
 template <int LD>
 __device__ __forceinline__ void store_words(uint16_t* dst, const uint32_t (&w)[LD]) {
@@ -2065,17 +2080,10 @@ __global__ __launch_bounds__(256) void vpet_bank_bops_kernel(BankArgs P) {
         x0 -= rr[0];
         x1 -= rr[1];
     }
-    uint16_t h0, l0, h1, l1, hq0, lq0, hq1, lq1;
-    split_bf16(x0, h0, l0);
-    split_bf16(x1, h1, l1);
-    split_bf16(x0 * x0, hq0, lq0);
-    split_bf16(x1 * x1, hq1, lq1);
     uint32_t* bh = reinterpret_cast<uint32_t*>(P.bhi + g * 2 * LD);
     uint32_t* bl = reinterpret_cast<uint32_t*>(P.blo + g * 2 * LD);
-    bh[f / 2] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-    bl[f / 2] = (uint32_t)l0 | ((uint32_t)l1 << 16);
-    bh[(LD + f) / 2] = (uint32_t)hq0 | ((uint32_t)hq1 << 16);
-    bl[(LD + f) / 2] = (uint32_t)lq0 | ((uint32_t)lq1 << 16);
+    split_bf16x2(x0, x1, bh[f / 2], bl[f / 2]);
+    split_bf16x2(x0 * x0, x1 * x1, bh[(LD + f) / 2], bl[(LD + f) / 2]);
 }
 
 // Voxel operands A_v = [-2 w y, w] (bf16 hi/lo) and a_v = sum w y^2 (FP64),
@@ -3511,7 +3519,7 @@ struct StagedRowSink {
 template <int KIND>
 __global__ __launch_bounds__(kWave) void vpet_lb_bank_kernel(LbBank B, ModelDev md, int m, Tab T, double C0, double h,
                                                              int F, int k0) {
-    extern __shared__ double stage[];  // [kWave][ld + 1]: the wavefront's rows
+    extern __shared__ double stage[];  // [kWave][ld + 1]: the wavefront's rows, then the reference curve
     const int lane = threadIdx.x;
     const unsigned i = blockIdx.x * kWave + lane;
     const bool live = i < B.n_draws;
@@ -3600,6 +3608,7 @@ __global__ __launch_bounds__(kWave) void vpet_lb_bank_kernel(LbBank B, ModelDev 
     const int nlive = (int)min(B.n_draws - blockIdx.x * kWave, (unsigned)kWave);
     const size_t row0 = (size_t)blockIdx.y * B.rows_per_group + (size_t)m * B.n_draws + blockIdx.x * kWave;
     if (live) B.logw[row0 + lane] = lw;
+    if (B.bhi && lane < ld) stage[kWave * (ld + 1) + lane] = B.ref[(size_t)blockIdx.y * ld + lane];
     {  // parameter rows through LDS, written out as consecutive floats
         float* tf = reinterpret_cast<float*>(stage);
 #pragma unroll
@@ -3627,47 +3636,59 @@ __global__ __launch_bounds__(kWave) void vpet_lb_bank_kernel(LbBank B, ModelDev 
     simulate_draws<KIND, 1>(T, F, k0, s, sink);
     __syncthreads();
     // the rows leave as consecutive elements: lane + 64 k of the wavefront's
-    // kWave x ld block, (r, f) advanced by (64 / ld, 64 % ld) per step
+    // kWave x ld block, (r, f) advanced by (64 / ld, 64 % ld) per step; ld is
+    // a multiple of 8 and r stays below kWave
     {
         double* xo = B.x + row0 * (size_t)ld;
         const int dr = kWave / ld, df = kWave % ld;
         int r = lane / ld, f = lane % ld;
-        for (int k = 0; k < ld; ++k) {
-            if (r < nlive) xo[(size_t)k * kWave + lane] = stage[r * (ld + 1) + f];
-            r += dr;
-            f += df;
-            if (f >= ld) {
-                f -= ld;
-                ++r;
+        for (int k = 0; k < ld; k += 4) {
+            double v[4];
+            bool w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                w[j] = r < nlive;
+                v[j] = stage[r * (ld + 1) + f];
+                r += dr;
+                f += df;
+                if (f >= ld) {
+                    f -= ld;
+                    ++r;
+                }
             }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (w[j]) xo[(size_t)(k + j) * kWave + lane] = v[j];
         }
     }
     if (B.bhi) {  // the screen operands of bank_bops, pairs of frames per lane
         const int hp = ld >> 1, dr = kWave / hp, df = kWave % hp;
-        const double* rr = B.ref + (size_t)blockIdx.y * ld;
+        const double* rs = stage + kWave * (ld + 1);  // the group's reference curve
         uint32_t* bh = reinterpret_cast<uint32_t*>(B.bhi) + row0 * (size_t)ld;
         uint32_t* bl = reinterpret_cast<uint32_t*>(B.blo) + row0 * (size_t)ld;
         int r = lane / hp, pr = lane % hp;
-        for (int k = 0; k < hp; ++k) {
-            if (r < nlive) {
-                const double x0 = stage[r * (ld + 1) + 2 * pr] - rr[2 * pr];
-                const double x1 = stage[r * (ld + 1) + 2 * pr + 1] - rr[2 * pr + 1];
-                uint16_t h0, l0, h1, l1, hq0, lq0, hq1, lq1;
-                split_bf16(x0, h0, l0);
-                split_bf16(x1, h1, l1);
-                split_bf16(x0 * x0, hq0, lq0);
-                split_bf16(x1 * x1, hq1, lq1);
-                const size_t o = (size_t)r * ld + pr;
-                bh[o] = (uint32_t)h0 | ((uint32_t)h1 << 16);
-                bl[o] = (uint32_t)l0 | ((uint32_t)l1 << 16);
-                bh[o + hp] = (uint32_t)hq0 | ((uint32_t)hq1 << 16);
-                bl[o + hp] = (uint32_t)lq0 | ((uint32_t)lq1 << 16);
+        for (int k = 0; k < hp; k += 4) {
+            double x0[4], x1[4];
+            int o[4];
+            bool w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                w[j] = r < nlive;
+                o[j] = r * ld + pr;
+                x0[j] = stage[r * (ld + 1) + 2 * pr] - rs[2 * pr];
+                x1[j] = stage[r * (ld + 1) + 2 * pr + 1] - rs[2 * pr + 1];
+                r += dr;
+                pr += df;
+                if (pr >= hp) {
+                    pr -= hp;
+                    ++r;
+                }
             }
-            r += dr;
-            pr += df;
-            if (pr >= hp) {
-                pr -= hp;
-                ++r;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (!w[j]) continue;
+                split_bf16x2(x0[j], x1[j], bh[o[j]], bl[o[j]]);
+                split_bf16x2(x0[j] * x0[j], x1[j] * x1[j], bh[o[j] + hp], bl[o[j] + hp]);
             }
         }
     }
@@ -4929,7 +4950,7 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
             }
             // a wavefront per 64 rows, its curves staged in LDS
             const dim3 bg((unsigned)((n_draws + kWave - 1) / kWave), (unsigned)ng), bw(kWave);
-            const size_t stage = sizeof(double) * kWave * (size_t)(ld + 1);
+            const size_t stage = sizeof(double) * ((size_t)kWave * (ld + 1) + ld);
             if (kinds[m] == KIND_IRR)
                 hipLaunchKernelGGL(vpet_lb_bank_kernel<KIND_IRR>, bg, bw, stage, st, LB, md[m], m, tab, T.C0, T.h, F,
                                    T.k0);
