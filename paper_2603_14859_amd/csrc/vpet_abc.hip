@@ -38,9 +38,11 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <condition_variable>
 #include <mutex>
 #include <type_traits>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include <fcntl.h>
@@ -5265,7 +5267,7 @@ int stream_driver(const char* kind, const char* tacs_path, int64_t n_voxels, int
         if (he == hipSuccess) he = hipEventRecord(B.ev_in[b], B.copy);
         return he == hipSuccess ? VPET_OK : hip_fail(he, "chunk copy in");
     };
-    // wait for chunk c's outputs and write them at their offsets
+    // wait for chunk c's outputs and write them at their offsets (writer thread)
     auto store = [&](int64_t c, int b) -> int {
         hipError_t he = hipEventSynchronize(B.ev_done[b]);
         if (he != hipSuccess) return hip_fail(he, "chunk outputs");
@@ -5277,24 +5279,91 @@ int stream_driver(const char* kind, const char* tacs_path, int64_t n_voxels, int
         return write_progress(prog_path, progress_line(kind, n_voxels, F, M, chunk, c + 1));
     };
 
-    if ((rc = load(done, 0)) != VPET_OK) return rc;
+    // A writer thread writes, syncs and records the chunks' outputs in chunk
+    // order, so that the file writes overlap both the GPU's work and the main
+    // thread's reads.  Chunks [done, queued) are handed over, [done, written)
+    // are on disk; its error (code and message) is passed back.
+    struct Writer {
+        std::mutex mu;
+        std::condition_variable cv;
+        int64_t queued = 0, written = 0;
+        int rc = VPET_OK;
+        std::string err;
+        bool quit = false;
+        std::thread th;
+        ~Writer() {
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                quit = true;
+            }
+            cv.notify_all();
+            if (th.joinable()) th.join();
+        }
+    } W;
+    W.queued = W.written = done;
+    try {
+        W.th = std::thread([&] {
+            for (;;) {
+                int64_t c;
+                {
+                    std::unique_lock<std::mutex> lk(W.mu);
+                    W.cv.wait(lk, [&] { return W.quit || W.written < W.queued; });
+                    if (W.quit) return;
+                    c = W.written;
+                }
+                const int r = store(c, (int)((c - done) & 1));
+                {
+                    std::lock_guard<std::mutex> lk(W.mu);
+                    if (r != VPET_OK) {
+                        W.rc = r;
+                        W.err = g_err;
+                        W.quit = true;
+                    } else {
+                        W.written = c + 1;
+                    }
+                }
+                W.cv.notify_all();
+                if (r != VPET_OK) return;
+            }
+        });
+    } catch (...) {
+        return fail(VPET_E_NOMEM, "cannot start the stream's writer thread");
+    }
+    // wait until the chunks below `upto` are on disk
+    auto wait_written = [&](int64_t upto) -> int {
+        std::unique_lock<std::mutex> lk(W.mu);
+        W.cv.wait(lk, [&] { return W.written >= upto || W.rc != VPET_OK; });
+        return W.rc == VPET_OK ? VPET_OK : fail(W.rc, "%s", W.err.c_str());
+    };
+    auto finish = [&](int r) {
+        if (out_done) {
+            std::lock_guard<std::mutex> lk(W.mu);
+            *out_done = W.written;
+        }
+        return r;
+    };
+
+    if ((rc = load(done, 0)) != VPET_OK) return finish(rc);
     for (int64_t c = done; c < last; ++c) {
         const int b = (int)((c - done) & 1);
         e = hipStreamWaitEvent(st, B.ev_in[b], 0);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-        if ((rc = run(B.d_in[b], rows(c), B.d_mom[b], B.d_prob[b], c)) != VPET_OK) return rc;
+        if (e != hipSuccess) return finish(hip_fail(e, "hipStreamWaitEvent"));
+        if ((rc = run(B.d_in[b], rows(c), B.d_mom[b], B.d_prob[b], c)) != VPET_OK) return finish(rc);
+        // h_mom[b], h_prob[b] and ev_done[b] are chunk c - 2's until it is written
+        if (c - 2 >= done && (rc = wait_written(c - 1)) != VPET_OK) return finish(rc);
         e = hipMemcpyAsync(B.h_mom[b], B.d_mom[b], mom_row * (size_t)rows(c), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(B.h_prob[b], B.d_prob[b], prob_row * (size_t)rows(c), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipEventRecord(B.ev_done[b], st);
-        if (e != hipSuccess) return hip_fail(e, "chunk copy out");
-        if (c + 1 < last && (rc = load(c + 1, b ^ 1)) != VPET_OK) return rc;   // overlaps chunk c
-        if (c > done && (rc = store(c - 1, b ^ 1)) != VPET_OK) return rc;      // overlaps chunk c
-        if (out_done) *out_done = c;
+        if (e != hipSuccess) return finish(hip_fail(e, "chunk copy out"));
+        {
+            std::lock_guard<std::mutex> lk(W.mu);
+            W.queued = c + 1;
+        }
+        W.cv.notify_all();
+        if (c + 1 < last && (rc = load(c + 1, b ^ 1)) != VPET_OK) return finish(rc);  // overlaps chunk c
     }
-    if ((rc = store(last - 1, (int)((last - 1 - done) & 1))) != VPET_OK) return rc;
-    if (out_done) *out_done = last;
-    return VPET_OK;
+    return finish(wait_written(last));
 }
 
 }  // namespace
