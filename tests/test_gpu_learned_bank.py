@@ -151,6 +151,20 @@ def test_learned_bank_parity(dims, bins, models):
     assert g["group"][5] == g["group"][6] == 2  # invalid voxels sort last
 
 
+@pytest.mark.parametrize("sched", [W.SCHED_22x60, W.SCHED_40x90])
+def test_learned_bank_parity_other_frame_counts(sched):
+    """22 and 40 frames (bank rows padded to 24 and 40 values, so that a
+    row's values and operands do not fill whole 64-lane store runs) and a
+    ragged last wavefront of bank rows (700 per model)."""
+    ft, cp, dt, th, y, rng = _volume(300, 61 + len(sched), (IRR, REV), sched=sched)
+    o = _outputs(th, rng, 5)
+    g, ref, rows = _run(y, ft, cp, dt, (IRR, REV), o, 700, 0.02, 31, dims=5, bins=1, group_voxels=256,
+                        prior_share=0.2, sd_scale=1.3)
+    swaps, nd = _check(g, ref, rows, (IRR, REV), 700)
+    print(f"[learned bank] {len(sched)} frames: threshold swaps {swaps}, bank rows off by one ulp {nd}, "
+          f"fallback voxels {g['fallback_voxels']}")
+
+
 def test_learned_bank_scans_agree_and_l1_weights_threshold():
     """The FP64 scan and the BF16 contraction scan give the same outputs bit
     for bit; the L1 distance with caller weights and ABC at given thresholds
