@@ -461,7 +461,8 @@ int vpet_abc_bank_screen(const float* tacs, int64_t n_voxels, const float* frame
  * scale; the whole-volume study of Sec. III-B2).  The observed TACs are read
  * chunk by chunk from tacs_path (raw little-endian fp32, [n_voxels][F]
  * row-major, F = grid.n_frames); while chunk c is screened on the GPU, chunk
- * c+1 is read and copied in and the outputs of chunk c-1 are written to
+ * c+1 is read and copied in and the outputs of chunk c-1 are written (by a
+ * host thread that the call starts and joins before it returns) to
  *   <out_prefix>.moments   [n_voxels][M][VPET_PSTRIDE][2] fp32
  *   <out_prefix>.prob      [n_voxels][M] fp32
  * at their voxel offsets.  After the outputs of a chunk are on disk,
