@@ -2309,6 +2309,10 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
             if (t + 2 < ntiles) fetch(t + 2);
         }
         f32x16_t acc0 = {}, acc1 = {};
+        // while a wavefront issues its products it goes before the others'
+        // screens and tile copies (measured: 2-3 % off the K <= 64 scans, but
+        // 22 % slower for the K = 80 one, which keeps the default order)
+        if constexpr (K <= 64) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int off = (lane & 31) * RS + (ks * 16 + half * 8) * 2;
@@ -2325,6 +2329,7 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh0, al[ks], acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh1, al[ks], acc1, 0, 0, 0);
         }
+        if constexpr (K <= 64) __builtin_amdgcn_s_setprio(0);
         screen(acc0, tile_row0(t), t * TR);
         screen(acc1, tile_row0(t) + kMfmaRows, t * TR + kMfmaRows);
         __syncthreads();
