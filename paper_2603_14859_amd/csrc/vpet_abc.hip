@@ -2302,6 +2302,10 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
     __syncthreads();
     for (unsigned t = 0; t < ntiles; ++t) {
         const int buf = t & 1;
+        // while a wavefront copies a tile and issues its products it goes
+        // before the others' screens (measured: 3-4 % off the K <= 64 scans,
+        // but 22 % slower for the K = 80 one, which keeps the default order)
+        if constexpr (K <= 64) __builtin_amdgcn_s_setprio(1);
         if (t + 1 < ntiles) {
             // tile t+1 (fetched one iteration ago) into the other buffer, which
             // every wave finished reading before the last barrier
@@ -2309,10 +2313,6 @@ __device__ __forceinline__ void bank_mfma_body(const BankArgs& P) {
             if (t + 2 < ntiles) fetch(t + 2);
         }
         f32x16_t acc0 = {}, acc1 = {};
-        // while a wavefront issues its products it goes before the others'
-        // screens and tile copies (measured: 2-3 % off the K <= 64 scans, but
-        // 22 % slower for the K = 80 one, which keeps the default order)
-        if constexpr (K <= 64) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int off = (lane & 31) * RS + (ks * 16 + half * 8) * 2;
