@@ -1753,7 +1753,7 @@ __device__ __forceinline__ uint64_t wave_sort_lanes(uint64_t x) {
 // spaced keys, at about 1.25 n of them below it, is checked by counting and
 // raised until at least n keys lie at or below it (else every key stays).
 // The n smallest keys are then among the first m, in fewer to sort.
-__device__ __forceinline__ int keep_smallest(uint64_t* keys, int below, int n) {
+__device__ __forceinline__ int keep_smallest(uint64_t* keys, int below, int n, uint64_t* cut = nullptr) {
     const int lane = lane_id();
     wave_lds_sync();
     const uint64_t smp = wave_sort_lanes(keys[(int)(((long long)lane * below) / kWave)]);
@@ -1778,6 +1778,7 @@ __device__ __forceinline__ int keep_smallest(uint64_t* keys, int below, int n) {
                 m += __popcll(b);
                 wave_lds_sync();
             }
+            if (cut) *cut = piv;
             return m;
         }
         if (q == kWave - 1) break;
@@ -1841,8 +1842,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vp
         }
         int below1 = 0, queued = 0;
         bool overflow = false;  // more keys at or below tau than the LDS holds: exact fallback
+        // Keys above `cut` cannot be among the n smallest: when a round could
+        // overflow the buffer it first keeps only the keys at or below a pivot
+        // with at least n of them at or below it (keep_smallest), and later
+        // keys above that pivot are dropped; it overflows only if that fails.
+        uint64_t cut = kNoKey;
         auto rank = [&](int nb) {  // queue[0, nb), nb <= 64: 32 rows per round, their loads issued together
             for (int i0 = 0; i0 < nb; i0 += 32) {
+                // a round adds at most 32 keys
+                if (!overflow && below > P.scap - 32) below = keep_smallest(keys, below, (int)P.n_acc, &cut);
                 uint32_t g[2];
                 double xv[2][Q];
 #pragma unroll
@@ -1864,10 +1872,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vp
                     pt += dpp_f64<0x4E>(pt);  // (p0 + p1) + (p2 + p3) (quad_perm [2,3,0,1])
                     const float fd = key_dist(pt);
                     const bool mine = live && part == 0;
-                    const bool keep = mine && fd <= tau;
+                    const uint64_t key = ((uint64_t)__float_as_uint(fd) << 32) | g[h];
+                    const bool keep = mine && fd <= tau && key <= cut;
                     const uint64_t b = __ballot(keep);
                     overflow = overflow || below + __popcll(b) > P.scap;
-                    if (keep && !overflow) keys[below + (int)mbcnt(b)] = ((uint64_t)__float_as_uint(fd) << 32) | g[h];
+                    if (keep && !overflow) keys[below + (int)mbcnt(b)] = key;
                     below += __popcll(b);
                     below1 += __popcll(__ballot(mine && fd <= tau1));
                 }
@@ -1942,7 +1951,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void vp
     wave_lds_sync();
     wave_bitonic_sort(keys, len);
     // the accepted keys' values (and weights) are staged in the LDS past the n
-    // accepted keys (n <= 512 makes scap >= 8 n)
+    // accepted keys (scap >= 6 n with weights, >= 5 n + 1 without)
     bank_outputs_m<WEIGHTED ? 1 : 0>(P, row, keys, red, keys + P.n_acc);
 }
 
@@ -4093,6 +4102,18 @@ int pow2_at_least(int x) {
     return p;
 }
 
+// Keys the re-ranking select holds in LDS (a power of two, at most the list
+// capacity).  About 4 n keys at or below tau are expected; a fuller buffer is
+// first pruned to the smallest keys (about 1.25 n) and overflows into the
+// exact fallback only if that fails.  8 n while that is at most 1024 keys
+// (LDS then does not limit the kernel's occupancy); beyond, the least that
+// still holds the outputs' staging past the n accepted keys (6 n keys in all
+// with importance weights, 5 n + 1 without).
+int select_key_buffer(int cap, int n, bool weighted) {
+    const int want = pow2_at_least(8 * n) <= 1024 ? 8 * n : (weighted ? 6 * n : 5 * n + 1);
+    return std::min(cap, std::max(512, pow2_at_least(want)));
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -4587,9 +4608,7 @@ int vpet_abc_infer_bank(const float* tacs, int64_t n_voxels, const float* frame_
         q += sz_c;
         A.aval = reinterpret_cast<double*>(q);
     }
-    // the re-ranking select keeps at most 8 n keys at or below tau in LDS
-    // (about 4 n are expected; more go to the exact fallback)
-    A.scap = std::min(cap, std::max(512, pow2_at_least(8 * (int)n_acc)));
+    A.scap = select_key_buffer(cap, (int)n_acc, false);
     const size_t lds = sizeof(uint64_t) * (use_mfma ? A.scap : cap) + sizeof(double) * kRedStride * kMaxWpv +
                        (use_mfma ? 2 * sizeof(double) * (size_t)ld + sizeof(uint32_t) * 2 * kWave : 0);
     // fallback blocks: up to 8 wavefronts, each with its own pow2(n + 128)-key
@@ -4906,7 +4925,7 @@ int vpet_abc_infer_bank_learned(const float* tacs, int64_t n_voxels, const float
 
     // the re-ranking select keeps at most 8 n keys at or below tau in LDS
     // (about 4 n are expected; more go to the exact fallback)
-    B.scap = std::min(cap, std::max(512, pow2_at_least(8 * (int)n_acc)));
+    B.scap = select_key_buffer(cap, (int)n_acc, true);
     // (n <= VPET_BANK_MAX_ACCEPT = 512 makes this pow2(8 n) >= 8 n: the
     // weighted select stages 5 n values past the n accepted keys)
     const size_t lds = sizeof(uint64_t) * (mfma ? B.scap : cap) + sizeof(double) * kRedStride * kMaxWpv +

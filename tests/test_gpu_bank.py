@@ -157,6 +157,43 @@ def test_infer_bank_forced_fallback_and_edges():
         _check(y[:8], ft, cp, [W.M_2TCM_IRR], 7, 0.2, 5, scan=scan)                   # tiny bank, n = 1
 
 
+def test_select_prunes_a_full_key_buffer():
+    """About 580 near-copies of bank row 100 (its curve scaled by 1 + 1e-6 j)
+    in the bank tiles that a 1024-row pilot does not sample, and a voxel equal
+    to row 100: every near-copy lies below the voxel's pilot threshold, more
+    than the re-ranking select's LDS key buffer holds (512 keys at n = 40), so
+    the select prunes the buffer to its smallest keys mid-way instead of
+    handing the voxel to the exact fallback.  The accepted set is row 100 and
+    the 39 least-scaled copies."""
+    ft, cp, y = _inputs(W.SCHED_30x50, 64, seed=21)
+    models = [W.M_2TCM_IRR]
+    th_g, x_g = V.bank_build(models, W.box_array(models), 8000, 5, cp, ft, H)
+    # pilot tiles of 64 rows: floor(t 125 / 16) for t < 16 = 0, 7, 15, ...;
+    # rows 64-447 and 512-703 lie in tiles 1-6 and 8-10
+    rows = [r for r in list(range(64, 448)) + list(range(512, 704)) if r != 100]
+    idx = torch.tensor(rows, device=DEV)
+    scale = 1.0 + 1e-6 * torch.arange(1, len(rows) + 1, device=DEV, dtype=torch.float64)
+    x_g[idx] = x_g[100].clone().unsqueeze(0) * scale.unsqueeze(1)
+    th_g[idx] = th_g[100].clone()
+    F = ft.size - 1
+    y = y.copy()
+    y[3] = x_g[100, :F].cpu().numpy().astype(np.float32)
+    kw = dict(debug=True, bank_scan="bf16", bank_pilot=1024)
+    res = V.infer_bank(torch.from_numpy(y).to(DEV), ft, H, cp.size, models, 8000, 0.005, th_g, x_g, **kw)
+    one = V.infer_bank(torch.from_numpy(y[3:4]).to(DEV), ft, H, cp.size, models, 8000, 0.005, th_g, x_g, **kw)
+    torch.cuda.synchronize()
+    n = res["n"]
+    assert n == 40
+    want = {100} | set(rows[:n - 1])
+    assert set(res["accept_idx"][3].cpu().numpy().tolist()) == want
+    assert set(one["accept_idx"][0].cpu().numpy().tolist()) == want
+    assert one["fallback_voxels"] == 0  # the select answered the voxel itself
+    t0 = th_g[100].cpu().numpy().astype(np.float64)
+    mom = one["moments"][0, 0].cpu().numpy().astype(np.float64)
+    assert np.allclose(mom[:3, 0], t0[:3], rtol=1e-6) and np.allclose(mom[:3, 1], 0.0, atol=1e-12)
+    print(f"[bank prune] exact fallbacks over the 64 voxels: {res['fallback_voxels']}, for the voxel alone: 0")
+
+
 def test_infer_bank_limits():
     ft, cp, y = _inputs(W.SCHED_22x60, 2)
     th, x = V.bank_build([W.M_2TCM_IRR], W.box_array([W.M_2TCM_IRR]), 1000, 1, cp, ft, H)
